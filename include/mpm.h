@@ -1,0 +1,198 @@
+/*
+ * mpm.h -- C ABI of the MI355X MLS-MPM soft-body library (libmpm_hip.so).
+ *
+ * The calls follow the paper's statement of the soft-body problem
+ * (Sec. 3 "Rigid-soft Coupling" and Algorithm 1 in App. C.1):
+ *   - create a soft scene and copy the rigid collision shapes into it
+ *     (Algorithm 1: "copy rigid body shapes ... to soft scene")      -> mpm_create
+ *   - after each rigid step copy rigid poses and velocities into it
+ *     (Sec. 3: poses and velocities are copied after each rigid step) -> mpm_set_colliders
+ *   - run the soft steps: particle-to-grid, grid velocity, grid-to-particle,
+ *     integrate (Algorithm 1, inner loop)                             -> mpm_step
+ *   - hand particle positions to the consumer, ideally by one device-to-device
+ *     copy (App. C.2)                                                  -> mpm_get_particles
+ * The method of a substep is MLS-MPM with APIC transfers and quadratic
+ * B-splines (Sec. 3 names MLS-MPM); colliders are analytic box / capsule
+ * SDFs applied on grid nodes (Sec. 3: the grid-node variant the simulator
+ * also supports), material is neo-Hookean or Hencky elasticity with a von
+ * Mises return map (App. C.3, Table "tab:mpm_param": Young's modulus,
+ * Poisson ratio, yield stress).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns mpm_status: 0 = MPM_OK, > 0 warning, < 0 error.
+ *     No C++ exception crosses the ABI.  Arguments are validated before any
+ *     device work is queued; on an argument error nothing is changed.
+ *   - The context owns all device memory it allocates.  Pointers passed in
+ *     are borrowed for the duration of the call only.
+ *   - on_device = 1: pointers are device pointers on the context's device;
+ *     copies are queued on the context stream and the call returns without
+ *     waiting (synchronise that stream, or call mpm_sync, before reading).
+ *     on_device = 0: pointers are host pointers; the call blocks until the
+ *     copy is complete.
+ *   - Layout at the ABI: positions / velocities [n][3] row-major float32,
+ *     matrices [n][3][3] row-major float32, particles in the order they were
+ *     given to mpm_create (scenes concatenated).  The library keeps its own
+ *     sorted SoA layout internally.
+ *   - World: grid node (i, j, k) sits at (i dx, j dx, k dx), i, j, k in
+ *     [0, res); y is up.  Dense grid outputs are [res][res][res] with x
+ *     slowest (index (i * res + j) * res + k).
+ *   - Threading: a context is used by one host thread at a time.
+ */
+#ifndef MPM_H
+#define MPM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpm_ctx_s *mpm_ctx;
+
+typedef enum {
+    MPM_OK = 0,
+    MPM_WARN_CLAMPED = 1,     /* a particle stencil touched the grid edge and was clamped */
+    MPM_WARN_FALLBACK = 2,    /* reserved */
+    MPM_ERR_ARG = -1,         /* invalid argument; nothing was changed */
+    MPM_ERR_HIP = -2,         /* HIP runtime error; detail via mpm_last_error */
+    MPM_ERR_OOM = -3,         /* device allocation failed */
+    MPM_ERR_NONFINITE = -4,   /* NaN / Inf found in the particle state */
+    MPM_ERR_STATE = -5        /* call not valid in the current state */
+} mpm_status;
+
+typedef enum { MPM_NEO_HOOKEAN = 0, MPM_HENCKY_VON_MISES = 1 } mpm_model;
+typedef enum { MPM_BOX = 0, MPM_CAPSULE = 1 } mpm_shape_type;
+
+typedef struct {
+    int model;             /* mpm_model */
+    float E;               /* Young's modulus, Pa (> 0) */
+    float nu;              /* Poisson ratio, in (-1, 0.5) */
+    float rho;             /* density, kg/m^3 (> 0) */
+    float yield_stress;    /* Pa; <= 0 or +inf disables plasticity (Hencky only) */
+    int yield_form;        /* 0: |dev eps| <= sy/(2 mu); 1: sqrt(2/3) sy/(2 mu) */
+} mpm_material;
+
+typedef struct {
+    int type;              /* mpm_shape_type */
+    float half_extents[3]; /* box half sizes, body frame */
+    float radius;          /* capsule radius */
+    float half_length;     /* capsule half segment length along body y */
+    float friction;        /* Coulomb coefficient >= 0; +inf = sticky */
+} mpm_collider_shape;
+
+typedef struct {
+    int n_particles;                 /* >= 0 */
+    const float *x;                  /* host [n][3]; inside [0, res dx)^3 */
+    const float *v;                  /* host [n][3] or NULL (zero) */
+    float particle_volume;           /* m^3 (> 0); particle mass = rho * volume */
+    int res;                         /* grid nodes per axis: 16, 32, 64 or 128 */
+    float dx;                        /* node spacing, m (> 0) */
+    float dt;                        /* substep, s (> 0) */
+    float gravity[3];                /* m/s^2 */
+    int bound;                       /* wall thickness in nodes, 0 <= bound < res/2 */
+    mpm_material mat;
+    int n_colliders;                 /* 0 .. MPM_MAX_COLLIDERS */
+    const mpm_collider_shape *colliders;
+} mpm_scene_desc;
+
+#define MPM_MAX_COLLIDERS 4
+
+/* Create a context holding n_scenes independent scenes (one batch).  Copies
+ * the scenes to the device (C = 0, F = I), sorts the particles and allocates
+ * every buffer a substep needs.  hip_stream: a hipStream_t to run on (for
+ * example PyTorch's current stream), or NULL to create one owned by the
+ * context.  Collider poses start at the origin with identity orientation and
+ * zero velocity until mpm_set_colliders is called.  On success *out holds
+ * the new context; on error *out is NULL.  MPM_ERR_OOM when the device
+ * cannot hold the state. */
+mpm_status mpm_create(const mpm_scene_desc *scenes, int n_scenes, void *hip_stream, mpm_ctx *out);
+
+/* Release every resource of the context (waits for queued work). NULL is a no-op. */
+mpm_status mpm_destroy(mpm_ctx ctx);
+
+/* Hand over collider poses and velocities (Sec. 3: copied after each rigid
+ * step).  poses [n_scenes][max_colliders][7] = centre xyz, quaternion wxyz
+ * (body -> world, normalised by the caller); velocities
+ * [n_scenes][max_colliders][6] = linear xyz (m/s), angular xyz (rad/s,
+ * world frame), where max_colliders = mpm_max_colliders(ctx).  Entries past a
+ * scene's own collider count are ignored.  Within the following mpm_step
+ * calls each collider moves kinematically: substep k of a call uses
+ * c + k dt v and exp(k dt w / 2) (x) q, the start-of-substep pose. */
+mpm_status mpm_set_colliders(mpm_ctx ctx, const float *poses, const float *velocities, int on_device);
+
+/* Run n_substeps >= 0 substeps of every scene (Algorithm 1, inner loop).
+ * Queued on the context stream; returns without waiting.  Warnings and
+ * non-finite errors found by earlier substeps are reported by mpm_sync. */
+mpm_status mpm_step(mpm_ctx ctx, int n_substeps);
+
+/* Wait for queued work; returns MPM_ERR_NONFINITE / MPM_WARN_CLAMPED if the
+ * device flagged them since the last mpm_sync, else MPM_OK. */
+mpm_status mpm_sync(mpm_ctx ctx);
+
+/* Particle positions (and optionally velocities and deformation gradients)
+ * of one scene, or of all scenes concatenated (scene = -1), in creation
+ * order.  x: [n][3]; v: [n][3] or NULL; F: [n][3][3] or NULL. */
+mpm_status mpm_get_particles(mpm_ctx ctx, int scene, float *x, float *v, float *F, int on_device);
+
+/* Full particle state (checkpoint / teacher forcing): x, v [n][3]; affine
+ * velocity C and deformation gradient F [n][3][3] of one scene or all
+ * (scene = -1).  mpm_set_state replaces that state (all four arrays are
+ * required) and re-sorts the particles. */
+mpm_status mpm_get_state(mpm_ctx ctx, int scene, float *x, float *v, float *C, float *F, int on_device);
+mpm_status mpm_set_state(mpm_ctx ctx, int scene, const float *x, const float *v, const float *C,
+                         const float *F, int on_device);
+
+/* Grid mass [res^3] and momentum [res^3][3] written by the particle-to-grid
+ * transfer of the most recent substep of one scene, before the grid update.
+ * Only available when capture is on (mpm_set_option(ctx, MPM_OPT_CAPTURE_GRID, 1)
+ * before stepping); MPM_ERR_STATE otherwise. */
+mpm_status mpm_get_grid(mpm_ctx ctx, int scene, float *m, float *p, int on_device);
+
+/* Tuning and debugging options. */
+typedef enum {
+    MPM_OPT_SORT_EVERY = 0,     /* substeps between particle re-sorts (>= 1), default 25 */
+    MPM_OPT_BLOCK = 1,          /* grid block edge for binning: 4 or 8, default 4 */
+    MPM_OPT_CHUNK = 2,          /* max particles per work item: 64 .. 4096, default 1024 */
+    MPM_OPT_PERSISTENT = 3,     /* 1: one persistent launch per substep; 0: three launches */
+    MPM_OPT_GRAPH = 4,          /* 1: replay a captured hipGraph for 25-substep blocks */
+    MPM_OPT_CAPTURE_GRID = 5,   /* 1: keep the last P2G grid for mpm_get_grid (slow, debug) */
+    MPM_OPT_TIMING = 6          /* 1: time every kernel launch with HIP events (see mpm_get_timing) */
+} mpm_option;
+
+/* Kernel classes reported by mpm_get_timing. */
+typedef enum { MPM_K_SORT = 0, MPM_K_P2G = 1, MPM_K_GRID = 2, MPM_K_G2P = 3, MPM_KCLASSES = 4 } mpm_kernel_class;
+
+mpm_status mpm_set_option(mpm_ctx ctx, int option, int value);
+mpm_status mpm_get_option(mpm_ctx ctx, int option, int *value);
+
+/* Time the candidate tunings (block edge, chunk size, persistent launch,
+ * sort cadence) on the live scenes for `substeps` substeps each, keep the
+ * fastest, and restore the particle state afterwards.  Writes a one-line
+ * JSON report to report[0 .. report_len) when report is non-NULL. */
+mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_len);
+
+/* Accumulated GPU time (ms, from HIP events recorded on the context stream
+ * around each launch while MPM_OPT_TIMING is on) and launch counts per
+ * kernel class, arrays of MPM_KCLASSES entries (either may be NULL).  Waits
+ * for the timed work.  reset = 1 clears the accumulators. */
+mpm_status mpm_get_timing(mpm_ctx ctx, double *ms_total, long long *launches, int reset);
+
+/* Internal particle order (debugging and tests): pid_out[slot] = creation
+ * index of the particle held in internal slot `slot`, for all particles
+ * (length mpm_num_particles(ctx, -1)); host pointer; blocks.  Inside each
+ * scene the slots are ordered by the Morton code of the particle's grid
+ * block (block edge = MPM_OPT_BLOCK) as of the last re-sort. */
+mpm_status mpm_get_order(mpm_ctx ctx, int *pid_out);
+
+/* Introspection. */
+int mpm_num_scenes(mpm_ctx ctx);
+int mpm_num_particles(mpm_ctx ctx, int scene);   /* scene = -1: total */
+int mpm_max_colliders(mpm_ctx ctx);
+int mpm_res(mpm_ctx ctx, int scene);
+const char *mpm_status_string(mpm_status status);
+const char *mpm_last_error(mpm_ctx ctx);          /* detail of the last error on ctx */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPM_H */

@@ -1,0 +1,882 @@
+// Host runtime and C ABI of the MI355X MLS-MPM library.
+//
+// The context owns every device buffer: particle state (two struct-of-arrays
+// buffers that the counting sort ping-pongs between), one dense grid per
+// scene in block-linear order, the sort / work-list arrays, collider tables
+// and a small pinned staging ring for collider uploads.  mpm_step queues
+// substeps (sort when due, P2G, grid update, G2P) on the context stream and
+// returns; only mpm_sync and host-side reads wait.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/mpm.h"
+#include "mpm_kernels.hpp"
+#include "mpm_types.hpp"
+
+using namespace mpm;
+
+namespace {
+
+constexpr int STAGE_RING = 4;
+
+struct GraphKey {
+    int parity, sort_first, n;
+    bool operator<(const GraphKey &o) const
+    {
+        if (parity != o.parity) return parity < o.parity;
+        if (sort_first != o.sort_first) return sort_first < o.sort_first;
+        return n < o.n;
+    }
+};
+
+}  // namespace
+
+struct mpm_ctx_s {
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int cus = 256;
+
+    int n_scenes = 0;
+    int N = 0;
+    long long pstride = 0;
+    std::vector<SceneDev> h_scenes;
+    std::vector<mpm_scene_desc> descs;
+    std::vector<ColliderDev> h_cols;
+    std::vector<int> h_col_scene;
+    int max_col = 0;
+
+    SceneDev *d_scenes = nullptr;
+    int *d_psc = nullptr;
+    float *d_P[2] = {nullptr, nullptr};
+    int cur = 0;
+
+    long long n_nodes = 0;
+    float *d_grid = nullptr;   // 7 arrays of n_nodes: m, px, py, pz, vx, vy, vz
+    ColliderDev *d_cols = nullptr;
+    void *d_colnow = nullptr;
+    int *d_col_scene = nullptr;
+
+    // sort and work lists
+    int B = 4, CH = 1024, sort_every = 25, since_sort = 1 << 30;
+    int T = 0, T_cap = 0;
+    int *d_scene_bin_off = nullptr;
+    unsigned *d_keys = nullptr;
+    int *d_count = nullptr, *d_pstart = nullptr, *d_perm = nullptr;
+    int3 *d_tsum = nullptr;
+    unsigned char *d_dil = nullptr;
+    Lists L{};
+    int items_cap = 0;
+    int *d_flags = nullptr;
+    int *d_queue = nullptr, *d_scene_done = nullptr;
+
+    // debug capture of the P2G grid
+    int capture = 0;
+    float *d_cap = nullptr;
+    long long *d_cap_off = nullptr;
+    long long cap_nodes = 0;
+
+    int persistent = 0, graph = 0;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+
+    // per-kernel-class timing with HIP events on the context stream
+    int timing = 0;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+    double kt_ms[MPM_KCLASSES] = {};
+    long long kt_n[MPM_KCLASSES] = {};
+
+    // io
+    float *d_io = nullptr;
+    float *h_stage[STAGE_RING] = {};
+    hipEvent_t stage_ev[STAGE_RING] = {};
+    int stage_next = 0;
+
+    std::string last_error;
+};
+
+namespace {
+
+#define HIPCHK(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            ctx->last_error = std::string(#expr) + ": " + hipGetErrorString(e_);        \
+            return e_ == hipErrorOutOfMemory ? MPM_ERR_OOM : MPM_ERR_HIP;               \
+        }                                                                               \
+    } while (0)
+
+#define ARGCHK(cond, msg)                   \
+    do {                                    \
+        if (!(cond)) {                      \
+            if (ctx) ctx->last_error = msg; \
+            return MPM_ERR_ARG;             \
+        }                                   \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, size_t n)
+{
+    return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
+}
+
+bool valid_res(int r) { return r == 16 || r == 32 || r == 64 || r == 128 || r == 256; }
+
+mpm_status validate_desc(mpm_ctx ctx, const mpm_scene_desc &d, int i)
+{
+    char buf[160];
+    auto bad = [&](const char *what) {
+        std::snprintf(buf, sizeof buf, "scene %d: %s", i, what);
+        if (ctx) ctx->last_error = buf;
+        return MPM_ERR_ARG;
+    };
+    if (d.n_particles < 0) return bad("n_particles < 0");
+    if (d.n_particles > 0 && !d.x) return bad("x is NULL");
+    if (!valid_res(d.res)) return bad("res must be 16, 32, 64, 128 or 256");
+    if (!(d.dx > 0) || !std::isfinite(d.dx)) return bad("dx must be > 0");
+    if (!(d.dt > 0) || !std::isfinite(d.dt)) return bad("dt must be > 0");
+    if (d.bound < 0 || 2 * d.bound >= d.res) return bad("bound out of range");
+    if (!(d.particle_volume > 0)) return bad("particle_volume must be > 0");
+    if (d.mat.model != 0 && d.mat.model != 1) return bad("unknown material model");
+    if (!(d.mat.E > 0) || !(d.mat.nu > -1.0f && d.mat.nu < 0.5f) || !(d.mat.rho > 0)) return bad("bad material");
+    if (d.mat.yield_form != 0 && d.mat.yield_form != 1) return bad("yield_form must be 0 or 1");
+    if (d.n_colliders < 0 || d.n_colliders > MPM_MAX_COLLIDERS) return bad("n_colliders out of range");
+    if (d.n_colliders > 0 && !d.colliders) return bad("colliders is NULL");
+    for (int k = 0; k < d.n_colliders; k++) {
+        const mpm_collider_shape &c = d.colliders[k];
+        if (c.type != 0 && c.type != 1) return bad("unknown collider type");
+        if (!(c.friction >= 0)) return bad("collider friction must be >= 0");
+        if (c.type == 0 && !(c.half_extents[0] >= 0 && c.half_extents[1] >= 0 && c.half_extents[2] >= 0))
+            return bad("box half extents must be >= 0");
+        if (c.type == 1 && !(c.radius >= 0 && c.half_length >= 0)) return bad("capsule radius / half length must be >= 0");
+    }
+    for (int g = 0; g < 3; g++)
+        if (!std::isfinite(d.gravity[g])) return bad("gravity not finite");
+    for (long long k = 0; k < 3LL * d.n_particles; k++) {
+        if (!std::isfinite(d.x[k])) return bad("x not finite");
+        if (d.v && !std::isfinite(d.v[k])) return bad("v not finite");
+    }
+    return MPM_OK;
+}
+
+SceneDev make_scene(const mpm_scene_desc &d, int p_begin, int col_off, int B)
+{
+    SceneDev S{};
+    S.p_begin = p_begin;
+    S.p_end = p_begin + d.n_particles;
+    S.res = d.res;
+    S.nb = d.res / B;
+    S.col_off = col_off;
+    S.n_col = d.n_colliders;
+    S.bound = d.bound;
+    S.model = d.mat.model;
+    double E = d.mat.E, nu = d.mat.nu;
+    double mu = E / (2 * (1 + nu)), la = E * nu / ((1 + nu) * (1 - 2 * nu));
+    S.plastic = d.mat.model == 1 && d.mat.yield_stress > 0 && std::isfinite(d.mat.yield_stress);
+    double ye = S.plastic ? d.mat.yield_stress / (2 * mu) : INFINITY;
+    if (d.mat.yield_form == 1) ye *= std::sqrt(2.0 / 3.0);
+    S.dx = d.dx;
+    S.inv_dx = (float)(1.0 / d.dx);
+    S.dt = d.dt;
+    for (int a = 0; a < 3; a++) S.g[a] = d.gravity[a];
+    S.mu = (float)mu;
+    S.la = (float)la;
+    S.yield_eps = (float)ye;
+    S.vol = d.particle_volume;
+    S.mass = (float)((double)d.mat.rho * d.particle_volume);
+    S.kstress = (float)((double)d.dt * d.particle_volume * 4.0 / ((double)d.dx * d.dx));
+    S.D = (float)(4.0 / ((double)d.dx * d.dx));
+    return S;
+}
+
+mpm_status set_block(mpm_ctx ctx, int B)
+{
+    // (Re)build the per-scene grid offsets and bin tables for block edge B.
+    ctx->B = B;
+    long long goff = 0;
+    int boff = 0;
+    std::vector<int> bin_off(ctx->n_scenes + 1);
+    for (int s = 0; s < ctx->n_scenes; s++) {
+        SceneDev &S = ctx->h_scenes[s];
+        S.nb = S.res / B;
+        S.grid_off = goff;
+        S.bin_off = boff;
+        bin_off[s] = boff;
+        goff += (long long)S.res * S.res * S.res;
+        boff += S.nb * S.nb * S.nb;
+    }
+    bin_off[ctx->n_scenes] = boff;
+    ctx->T = boff;
+    if (boff > ctx->T_cap) {
+        ctx->last_error = "bin table larger than allocated";
+        return MPM_ERR_STATE;
+    }
+    HIPCHK(hipMemcpyAsync(ctx->d_scenes, ctx->h_scenes.data(), sizeof(SceneDev) * ctx->n_scenes,
+                          hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->d_scene_bin_off, bin_off.data(), sizeof(int) * (ctx->n_scenes + 1),
+                          hipMemcpyHostToDevice, ctx->stream));
+    // the grid layout changed: every (m, p) must be zero and every v finite
+    HIPCHK(launch_clear_f(ctx->d_grid, 7 * ctx->n_nodes, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->since_sort = 1 << 30;
+    for (auto &g : ctx->graphs) hipGraphExecDestroy(g.second);
+    ctx->graphs.clear();
+    return MPM_OK;
+}
+
+hipEvent_t take_event(mpm_ctx ctx)
+{
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one kernel launch with events when timing is on.
+struct KTimer {
+    mpm_ctx ctx;
+    int cls;
+    hipEvent_t a = nullptr, b = nullptr;
+    KTimer(mpm_ctx c, int k) : ctx(c), cls(k)
+    {
+        if (ctx->timing) {
+            a = take_event(ctx);
+            b = take_event(ctx);
+            if (a) (void)hipEventRecord(a, ctx->stream);
+        }
+    }
+    ~KTimer()
+    {
+        if (ctx->timing && a && b) {
+            (void)hipEventRecord(b, ctx->stream);
+            ctx->ev_pending.push_back({cls, {a, b}});
+        }
+    }
+};
+
+hipError_t resolve_timing(mpm_ctx ctx)
+{
+    for (auto &p : ctx->ev_pending) {
+        hipError_t e = hipEventSynchronize(p.second.second);
+        if (e != hipSuccess) return e;
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, p.second.first, p.second.second);
+        if (e != hipSuccess) return e;
+        ctx->kt_ms[p.first] += ms;
+        ctx->kt_n[p.first] += 1;
+        ctx->ev_pool.push_back(p.second.first);
+        ctx->ev_pool.push_back(p.second.second);
+    }
+    ctx->ev_pending.clear();
+    return hipSuccess;
+}
+
+SortArgs sort_args(mpm_ctx ctx)
+{
+    SortArgs a{};
+    a.scenes = ctx->d_scenes;
+    a.n_scenes = ctx->n_scenes;
+    a.psc = ctx->d_psc;
+    a.P = ctx->d_P[ctx->cur];
+    a.Pn = ctx->d_P[1 - ctx->cur];
+    a.pstride = ctx->pstride;
+    a.N = ctx->N;
+    a.T = ctx->T;
+    a.scene_bin_off = ctx->d_scene_bin_off;
+    a.keys = ctx->d_keys;
+    a.count = ctx->d_count;
+    a.pstart = ctx->d_pstart;
+    a.perm = ctx->d_perm;
+    a.tsum = ctx->d_tsum;
+    a.dil = ctx->d_dil;
+    a.L = ctx->L;
+    a.B = ctx->B;
+    a.CH = ctx->CH;
+    return a;
+}
+
+StepArgs step_args(mpm_ctx ctx, int substep)
+{
+    StepArgs a{};
+    a.scenes = ctx->d_scenes;
+    a.n_scenes = ctx->n_scenes;
+    a.P = ctx->d_P[ctx->cur];
+    a.pstride = ctx->pstride;
+    long long n = ctx->n_nodes;
+    a.gm = ctx->d_grid;
+    a.gpx = ctx->d_grid + n;
+    a.gpy = ctx->d_grid + 2 * n;
+    a.gpz = ctx->d_grid + 3 * n;
+    a.gvx = ctx->d_grid + 4 * n;
+    a.gvy = ctx->d_grid + 5 * n;
+    a.gvz = ctx->d_grid + 6 * n;
+    a.cap = ctx->capture ? ctx->d_cap : nullptr;
+    a.cap_off = ctx->d_cap_off;
+    a.cols = ctx->d_cols;
+    a.colnow = ctx->d_colnow;
+    a.L = ctx->L;
+    a.flags = ctx->d_flags;
+    a.substep = substep;
+    a.B = ctx->B;
+    a.queue = ctx->d_queue;
+    a.scene_done = ctx->d_scene_done;
+    return a;
+}
+
+mpm_status do_sort(mpm_ctx ctx)
+{
+    KTimer kt(ctx, MPM_K_SORT);
+    HIPCHK(launch_sort(sort_args(ctx), ctx->stream));
+    ctx->cur = 1 - ctx->cur;
+    ctx->since_sort = 0;
+    return MPM_OK;
+}
+
+int substep_wgs(mpm_ctx ctx) { return ctx->cus * 8; }
+
+// Queue n substeps (the collider advance at the end included).
+mpm_status queue_substeps(mpm_ctx ctx, int n)
+{
+    for (int i = 0; i < n; i++) {
+        if (ctx->since_sort >= ctx->sort_every) {
+            mpm_status st = do_sort(ctx);
+            if (st != MPM_OK) return st;
+        }
+        if (ctx->capture) HIPCHK(launch_clear_f(ctx->d_cap, 4 * ctx->cap_nodes, ctx->stream));
+        StepArgs a = step_args(ctx, i);
+        {
+            KTimer kt(ctx, MPM_K_P2G);
+            HIPCHK(launch_p2g(a, ctx->CH, substep_wgs(ctx), ctx->stream));
+        }
+        {
+            KTimer kt(ctx, MPM_K_GRID);
+            HIPCHK(launch_grid(a, substep_wgs(ctx), ctx->stream));
+        }
+        {
+            KTimer kt(ctx, MPM_K_G2P);
+            HIPCHK(launch_g2p(a, substep_wgs(ctx), ctx->stream));
+        }
+        ctx->since_sort++;
+    }
+    HIPCHK(launch_collider_advance(ctx->d_cols, (int)ctx->h_cols.size(), ctx->d_col_scene, ctx->d_scenes, n,
+                                   ctx->stream));
+    return MPM_OK;
+}
+
+// Copies between caller memory and a device buffer of the context.
+mpm_status to_device(mpm_ctx ctx, void *dst, const void *src, size_t bytes, int on_device)
+{
+    if (bytes == 0) return MPM_OK;
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream));
+    if (!on_device) HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MPM_OK;
+}
+
+mpm_status from_device(mpm_ctx ctx, void *dst, const void *src, size_t bytes, int on_device)
+{
+    if (bytes == 0) return MPM_OK;
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
+    if (!on_device) HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MPM_OK;
+}
+
+void scene_range(mpm_ctx ctx, int scene, int &b, int &e)
+{
+    if (scene < 0) {
+        b = 0;
+        e = ctx->N;
+    } else {
+        b = ctx->h_scenes[scene].p_begin;
+        e = ctx->h_scenes[scene].p_end;
+    }
+}
+
+void release(mpm_ctx ctx)
+{
+    if (!ctx) return;
+    hipSetDevice(ctx->dev);
+    if (ctx->stream) hipStreamSynchronize(ctx->stream);
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto &p : ctx->ev_pending) {
+        ctx->ev_pool.push_back(p.second.first);
+        ctx->ev_pool.push_back(p.second.second);
+    }
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    void *bufs[] = {ctx->d_scenes, ctx->d_psc, ctx->d_P[0], ctx->d_P[1], ctx->d_grid, ctx->d_cols, ctx->d_colnow,
+                    ctx->d_col_scene, ctx->d_scene_bin_off, ctx->d_keys, ctx->d_count, ctx->d_pstart, ctx->d_perm,
+                    ctx->d_tsum, ctx->d_dil, ctx->L.items, ctx->L.gitems, ctx->L.n_items, ctx->L.n_gitems,
+                    ctx->L.scene_item_begin, ctx->L.scene_gitem_begin, ctx->L.bflag, ctx->L.ovf, ctx->L.n_ovf,
+                    ctx->d_flags, ctx->d_queue, ctx->d_scene_done, ctx->d_cap, ctx->d_cap_off, ctx->d_io};
+    for (void *p : bufs)
+        if (p) hipFree(p);
+    for (int i = 0; i < STAGE_RING; i++) {
+        if (ctx->h_stage[i]) hipHostFree(ctx->h_stage[i]);
+        if (ctx->stage_ev[i]) hipEventDestroy(ctx->stage_ev[i]);
+    }
+    if (ctx->own_stream && ctx->stream) hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+mpm_status create_impl(mpm_ctx ctx, const mpm_scene_desc *scenes, int n_scenes)
+{
+    ctx->n_scenes = n_scenes;
+    ctx->descs.assign(scenes, scenes + n_scenes);
+    long long N = 0;
+    for (int s = 0; s < n_scenes; s++) N += scenes[s].n_particles;
+    if (N > (1LL << 30)) {
+        ctx->last_error = "too many particles";
+        return MPM_ERR_ARG;
+    }
+    ctx->N = (int)N;
+    ctx->pstride = std::max<long long>(N, 1);
+    int p = 0;
+    for (int s = 0; s < n_scenes; s++) {
+        const mpm_scene_desc &d = scenes[s];
+        ctx->h_scenes.push_back(make_scene(d, p, (int)ctx->h_cols.size(), 4));
+        for (int k = 0; k < d.n_colliders; k++) {
+            const mpm_collider_shape &c = d.colliders[k];
+            ColliderDev cd{};
+            cd.type = c.type;
+            for (int a = 0; a < 3; a++) cd.he[a] = c.half_extents[a];
+            cd.radius = c.radius;
+            cd.half_length = c.half_length;
+            cd.friction = c.friction;
+            cd.quat[0] = 1.0f;
+            ctx->h_cols.push_back(cd);
+            ctx->h_col_scene.push_back(s);
+        }
+        ctx->max_col = std::max(ctx->max_col, d.n_colliders);
+        p += d.n_particles;
+    }
+    // sizes
+    long long nodes = 0;
+    int T4 = 0;
+    for (int s = 0; s < n_scenes; s++) {
+        int r = scenes[s].res;
+        nodes += (long long)r * r * r;
+        T4 += (r / 4) * (r / 4) * (r / 4);
+    }
+    ctx->n_nodes = nodes;
+    ctx->T_cap = T4;
+    ctx->items_cap = (int)std::min<long long>(N / 64 + T4 + 8, 1LL << 30);
+
+    HIPCHK(dalloc(&ctx->d_scenes, n_scenes));
+    HIPCHK(dalloc(&ctx->d_psc, N));
+    for (int b = 0; b < 2; b++) HIPCHK(dalloc(&ctx->d_P[b], (size_t)NCOMP * ctx->pstride));
+    HIPCHK(dalloc(&ctx->d_grid, (size_t)7 * nodes));
+    HIPCHK(dalloc(&ctx->d_cols, ctx->h_cols.size()));
+    HIPCHK(hipMalloc(&ctx->d_colnow, std::max<size_t>(ctx->h_cols.size(), 1) * 128));
+    HIPCHK(dalloc(&ctx->d_col_scene, ctx->h_cols.size()));
+    HIPCHK(dalloc(&ctx->d_scene_bin_off, n_scenes + 1));
+    HIPCHK(dalloc(&ctx->d_keys, N));
+    HIPCHK(dalloc(&ctx->d_count, T4));
+    HIPCHK(dalloc(&ctx->d_pstart, T4));
+    HIPCHK(dalloc(&ctx->d_perm, N));
+    HIPCHK(dalloc(&ctx->d_tsum, (T4 + 2047) / 2048 + 1));
+    HIPCHK(dalloc(&ctx->d_dil, T4));
+    HIPCHK(dalloc(&ctx->L.items, ctx->items_cap));
+    HIPCHK(dalloc(&ctx->L.gitems, T4));
+    HIPCHK(dalloc(&ctx->L.n_items, 1));
+    HIPCHK(dalloc(&ctx->L.n_gitems, 1));
+    HIPCHK(dalloc(&ctx->L.scene_item_begin, n_scenes + 1));
+    HIPCHK(dalloc(&ctx->L.scene_gitem_begin, n_scenes + 1));
+    HIPCHK(dalloc(&ctx->L.bflag, T4));
+    HIPCHK(dalloc(&ctx->L.ovf, T4));
+    HIPCHK(dalloc(&ctx->L.n_ovf, 1));
+    ctx->L.ovf_cap = T4;
+    HIPCHK(dalloc(&ctx->d_flags, n_scenes));
+    HIPCHK(dalloc(&ctx->d_queue, 4));
+    HIPCHK(dalloc(&ctx->d_scene_done, 3 * n_scenes));
+    HIPCHK(dalloc(&ctx->d_io, (size_t)24 * N));
+    for (int i = 0; i < STAGE_RING; i++) {
+        size_t bytes = std::max<size_t>(ctx->h_cols.size(), 1) * sizeof(ColliderDev) + 64;
+        HIPCHK(hipHostMalloc((void **)&ctx->h_stage[i], bytes, hipHostMallocDefault));
+        HIPCHK(hipEventCreateWithFlags(&ctx->stage_ev[i], hipEventDisableTiming));
+    }
+    HIPCHK(hipMemsetAsync(ctx->d_count, 0, sizeof(int) * T4, ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->L.bflag, 0, sizeof(int) * T4, ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->L.n_ovf, 0, sizeof(int), ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->L.n_items, 0, sizeof(int), ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->L.n_gitems, 0, sizeof(int), ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->d_flags, 0, sizeof(int) * n_scenes, ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->d_P[0], 0, sizeof(float) * NCOMP * ctx->pstride, ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->d_P[1], 0, sizeof(float) * NCOMP * ctx->pstride, ctx->stream));
+    if (!ctx->h_cols.empty()) {
+        HIPCHK(hipMemcpyAsync(ctx->d_cols, ctx->h_cols.data(), sizeof(ColliderDev) * ctx->h_cols.size(),
+                              hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(ctx->d_col_scene, ctx->h_col_scene.data(), sizeof(int) * ctx->h_col_scene.size(),
+                              hipMemcpyHostToDevice, ctx->stream));
+    }
+    std::vector<int> psc(N);
+    for (int s = 0; s < n_scenes; s++)
+        for (int i = ctx->h_scenes[s].p_begin; i < ctx->h_scenes[s].p_end; i++) psc[i] = s;
+    HIPCHK(hipMemcpyAsync(ctx->d_psc, psc.data(), sizeof(int) * N, hipMemcpyHostToDevice, ctx->stream));
+    mpm_status st = set_block(ctx, 4);
+    if (st != MPM_OK) return st;
+    // particles: upload x, v per scene into d_io and convert
+    for (int s = 0; s < n_scenes; s++) {
+        const mpm_scene_desc &d = scenes[s];
+        if (d.n_particles == 0) continue;
+        float *dx_ = ctx->d_io, *dv_ = ctx->d_io + 3LL * d.n_particles;
+        HIPCHK(hipMemcpy(dx_, d.x, sizeof(float) * 3 * d.n_particles, hipMemcpyHostToDevice));
+        if (d.v) HIPCHK(hipMemcpy(dv_, d.v, sizeof(float) * 3 * d.n_particles, hipMemcpyHostToDevice));
+        HIPCHK(launch_init_particles(ctx->d_scenes, n_scenes, ctx->d_psc, ctx->d_P[ctx->cur], ctx->pstride, dx_,
+                                     d.v ? dv_ : nullptr, nullptr, nullptr, ctx->h_scenes[s].p_begin,
+                                     ctx->h_scenes[s].p_end, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    st = do_sort(ctx);
+    if (st != MPM_OK) return st;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mpm_status_string(mpm_status s)
+{
+    switch (s) {
+    case MPM_OK: return "ok";
+    case MPM_WARN_CLAMPED: return "warning: particle stencil clamped at the grid edge";
+    case MPM_WARN_FALLBACK: return "warning: fallback";
+    case MPM_ERR_ARG: return "invalid argument";
+    case MPM_ERR_HIP: return "HIP runtime error";
+    case MPM_ERR_OOM: return "out of device memory";
+    case MPM_ERR_NONFINITE: return "non-finite particle state";
+    case MPM_ERR_STATE: return "call not valid in the current state";
+    }
+    return "unknown status";
+}
+
+const char *mpm_last_error(mpm_ctx ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+mpm_status mpm_create(const mpm_scene_desc *scenes, int n_scenes, void *hip_stream, mpm_ctx *out)
+{
+    mpm_ctx ctx = nullptr;
+    if (!out) return MPM_ERR_ARG;
+    *out = nullptr;
+    if (!scenes || n_scenes <= 0 || n_scenes > (1 << 20)) return MPM_ERR_ARG;
+    for (int s = 0; s < n_scenes; s++) {
+        mpm_status st = validate_desc(nullptr, scenes[s], s);
+        if (st != MPM_OK) return st;
+    }
+    ctx = new mpm_ctx_s();
+    if (hipGetDevice(&ctx->dev) != hipSuccess) {
+        delete ctx;
+        return MPM_ERR_HIP;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ctx->dev) == hipSuccess) ctx->cus = prop.multiProcessorCount;
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return MPM_ERR_HIP;
+        }
+        ctx->own_stream = true;
+    }
+    mpm_status st = create_impl(ctx, scenes, n_scenes);
+    if (st != MPM_OK) {
+        std::fprintf(stderr, "mpm_create: %s\n", ctx->last_error.c_str());
+        release(ctx);
+        return st;
+    }
+    *out = ctx;
+    return MPM_OK;
+}
+
+mpm_status mpm_destroy(mpm_ctx ctx)
+{
+    release(ctx);
+    return MPM_OK;
+}
+
+int mpm_num_scenes(mpm_ctx ctx) { return ctx ? ctx->n_scenes : 0; }
+int mpm_num_particles(mpm_ctx ctx, int scene)
+{
+    if (!ctx) return 0;
+    if (scene < 0) return ctx->N;
+    if (scene >= ctx->n_scenes) return 0;
+    return ctx->h_scenes[scene].p_end - ctx->h_scenes[scene].p_begin;
+}
+int mpm_max_colliders(mpm_ctx ctx) { return ctx ? ctx->max_col : 0; }
+int mpm_res(mpm_ctx ctx, int scene)
+{
+    if (!ctx || scene < 0 || scene >= ctx->n_scenes) return 0;
+    return ctx->h_scenes[scene].res;
+}
+
+mpm_status mpm_set_colliders(mpm_ctx ctx, const float *poses, const float *velocities, int on_device)
+{
+    ARGCHK(ctx, "null context");
+    ARGCHK(poses && velocities, "poses / velocities must not be NULL");
+    if (ctx->h_cols.empty()) return MPM_OK;
+    hipSetDevice(ctx->dev);
+    int K = ctx->max_col;
+    std::vector<float> hp((size_t)ctx->n_scenes * K * 7), hv((size_t)ctx->n_scenes * K * 6);
+    if (on_device) {
+        HIPCHK(hipMemcpyAsync(hp.data(), poses, hp.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipMemcpyAsync(hv.data(), velocities, hv.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    } else {
+        std::memcpy(hp.data(), poses, hp.size() * 4);
+        std::memcpy(hv.data(), velocities, hv.size() * 4);
+    }
+    for (size_t c = 0; c < ctx->h_cols.size(); c++) {
+        int s = ctx->h_col_scene[c];
+        int k = (int)c - ctx->h_scenes[s].col_off;
+        const float *P = &hp[((size_t)s * K + k) * 7];
+        const float *V = &hv[((size_t)s * K + k) * 6];
+        for (int i = 0; i < 13; i++) ARGCHK(std::isfinite(i < 7 ? P[i] : V[i - 7]), "non-finite collider pose");
+        ColliderDev &cd = ctx->h_cols[c];
+        for (int a = 0; a < 3; a++) {
+            cd.pos[a] = P[a];
+            cd.vlin[a] = V[a];
+            cd.omega[a] = V[3 + a];
+        }
+        for (int a = 0; a < 4; a++) cd.quat[a] = P[3 + a];
+    }
+    int slot = ctx->stage_next;
+    ctx->stage_next = (slot + 1) % STAGE_RING;
+    HIPCHK(hipEventSynchronize(ctx->stage_ev[slot]));
+    std::memcpy(ctx->h_stage[slot], ctx->h_cols.data(), sizeof(ColliderDev) * ctx->h_cols.size());
+    HIPCHK(hipMemcpyAsync(ctx->d_cols, ctx->h_stage[slot], sizeof(ColliderDev) * ctx->h_cols.size(),
+                          hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipEventRecord(ctx->stage_ev[slot], ctx->stream));
+    return MPM_OK;
+}
+
+mpm_status mpm_step(mpm_ctx ctx, int n_substeps)
+{
+    ARGCHK(ctx, "null context");
+    ARGCHK(n_substeps >= 0, "n_substeps must be >= 0");
+    if (n_substeps == 0) return MPM_OK;
+    hipSetDevice(ctx->dev);
+    return queue_substeps(ctx, n_substeps);
+}
+
+mpm_status mpm_sync(mpm_ctx ctx)
+{
+    ARGCHK(ctx, "null context");
+    hipSetDevice(ctx->dev);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    std::vector<int> fl(ctx->n_scenes);
+    HIPCHK(hipMemcpy(fl.data(), ctx->d_flags, sizeof(int) * ctx->n_scenes, hipMemcpyDeviceToHost));
+    int any = 0;
+    for (int f : fl) any |= f;
+    if (any) HIPCHK(hipMemset(ctx->d_flags, 0, sizeof(int) * ctx->n_scenes));
+    if (any & FLAG_NONFINITE) {
+        ctx->last_error = "non-finite particle state";
+        return MPM_ERR_NONFINITE;
+    }
+    if (any & FLAG_OVERFLOW_FULL) {
+        ctx->last_error = "overflow grid-block list full";
+        return MPM_ERR_STATE;
+    }
+    if (any & FLAG_CLAMPED) return MPM_WARN_CLAMPED;
+    return MPM_OK;
+}
+
+mpm_status mpm_get_state(mpm_ctx ctx, int scene, float *x, float *v, float *C, float *F, int on_device)
+{
+    ARGCHK(ctx, "null context");
+    ARGCHK(scene >= -1 && scene < ctx->n_scenes, "scene out of range");
+    hipSetDevice(ctx->dev);
+    int b, e;
+    scene_range(ctx, scene, b, e);
+    long long n = e - b;
+    float *dx_ = ctx->d_io, *dv_ = dx_ + 3 * n, *dC_ = dv_ + 3 * n, *dF_ = dC_ + 9 * n;
+    HIPCHK(launch_get_state(ctx->d_scenes, ctx->d_psc, ctx->d_P[ctx->cur], ctx->pstride, b, e, x ? dx_ : nullptr,
+                            v ? dv_ : nullptr, C ? dC_ : nullptr, F ? dF_ : nullptr, ctx->stream));
+    mpm_status st = MPM_OK;
+    if (x && (st = from_device(ctx, x, dx_, 12 * n, on_device)) != MPM_OK) return st;
+    if (v && (st = from_device(ctx, v, dv_, 12 * n, on_device)) != MPM_OK) return st;
+    if (C && (st = from_device(ctx, C, dC_, 36 * n, on_device)) != MPM_OK) return st;
+    if (F && (st = from_device(ctx, F, dF_, 36 * n, on_device)) != MPM_OK) return st;
+    return MPM_OK;
+}
+
+mpm_status mpm_get_particles(mpm_ctx ctx, int scene, float *x, float *v, float *F, int on_device)
+{
+    ARGCHK(x, "x must not be NULL");
+    return mpm_get_state(ctx, scene, x, v, nullptr, F, on_device);
+}
+
+mpm_status mpm_set_state(mpm_ctx ctx, int scene, const float *x, const float *v, const float *C, const float *F,
+                         int on_device)
+{
+    ARGCHK(ctx, "null context");
+    ARGCHK(scene >= -1 && scene < ctx->n_scenes, "scene out of range");
+    ARGCHK(x && v && C && F, "x, v, C and F are required");
+    hipSetDevice(ctx->dev);
+    int b, e;
+    scene_range(ctx, scene, b, e);
+    long long n = e - b;
+    float *dx_ = ctx->d_io, *dv_ = dx_ + 3 * n, *dC_ = dv_ + 3 * n, *dF_ = dC_ + 9 * n;
+    if (!on_device) {
+        for (long long k = 0; k < 3 * n; k++) ARGCHK(std::isfinite(x[k]) && std::isfinite(v[k]), "non-finite x / v");
+    }
+    mpm_status st;
+    if ((st = to_device(ctx, dx_, x, 12 * n, on_device)) != MPM_OK) return st;
+    if ((st = to_device(ctx, dv_, v, 12 * n, on_device)) != MPM_OK) return st;
+    if ((st = to_device(ctx, dC_, C, 36 * n, on_device)) != MPM_OK) return st;
+    if ((st = to_device(ctx, dF_, F, 36 * n, on_device)) != MPM_OK) return st;
+    HIPCHK(launch_init_particles(ctx->d_scenes, ctx->n_scenes, ctx->d_psc, ctx->d_P[ctx->cur], ctx->pstride, dx_, dv_,
+                                 dC_, dF_, b, e, ctx->stream));
+    ctx->since_sort = 1 << 30;
+    return MPM_OK;
+}
+
+mpm_status mpm_get_grid(mpm_ctx ctx, int scene, float *m, float *p, int on_device)
+{
+    ARGCHK(ctx, "null context");
+    ARGCHK(scene >= 0 && scene < ctx->n_scenes, "scene out of range");
+    if (!ctx->capture || !ctx->d_cap) {
+        ctx->last_error = "grid capture is off";
+        return MPM_ERR_STATE;
+    }
+    hipSetDevice(ctx->dev);
+    long long r = ctx->h_scenes[scene].res, nn = r * r * r;
+    long long off = 0;
+    for (int s = 0; s < scene; s++) off += (long long)ctx->h_scenes[s].res * ctx->h_scenes[s].res * ctx->h_scenes[s].res;
+    std::vector<float> h(4 * nn);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipMemcpy(h.data(), ctx->d_cap + 4 * off, sizeof(float) * 4 * nn, hipMemcpyDeviceToHost));
+    std::vector<float> hm(nn), hp(3 * nn);
+    for (long long i = 0; i < nn; i++) {
+        hm[i] = h[4 * i];
+        for (int a = 0; a < 3; a++) hp[3 * i + a] = h[4 * i + 1 + a];
+    }
+    if (on_device) {
+        if (m) HIPCHK(hipMemcpy(m, hm.data(), sizeof(float) * nn, hipMemcpyHostToDevice));
+        if (p) HIPCHK(hipMemcpy(p, hp.data(), sizeof(float) * 3 * nn, hipMemcpyHostToDevice));
+    } else {
+        if (m) std::memcpy(m, hm.data(), sizeof(float) * nn);
+        if (p) std::memcpy(p, hp.data(), sizeof(float) * 3 * nn);
+    }
+    return MPM_OK;
+}
+
+mpm_status mpm_set_option(mpm_ctx ctx, int option, int value)
+{
+    ARGCHK(ctx, "null context");
+    hipSetDevice(ctx->dev);
+    switch (option) {
+    case MPM_OPT_SORT_EVERY:
+        ARGCHK(value >= 1, "sort_every must be >= 1");
+        ctx->sort_every = value;
+        return MPM_OK;
+    case MPM_OPT_BLOCK: {
+        ARGCHK(value == 4 || value == 8, "block must be 4 or 8");
+        if (value == ctx->B) return MPM_OK;
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        return set_block(ctx, value);
+    }
+    case MPM_OPT_CHUNK:
+        ARGCHK(value >= 64 && value <= 1024, "chunk must be in [64, 1024]");
+        ctx->CH = value;
+        ctx->since_sort = 1 << 30;
+        return MPM_OK;
+    case MPM_OPT_PERSISTENT:
+        ARGCHK(value == 0 || value == 1, "persistent must be 0 or 1");
+        ctx->persistent = value;
+        return MPM_OK;
+    case MPM_OPT_GRAPH:
+        ARGCHK(value == 0 || value == 1, "graph must be 0 or 1");
+        ctx->graph = value;
+        return MPM_OK;
+    case MPM_OPT_CAPTURE_GRID:
+        ARGCHK(value == 0 || value == 1, "capture must be 0 or 1");
+        if (value && !ctx->d_cap) {
+            std::vector<long long> off(ctx->n_scenes);
+            long long tot = 0;
+            for (int s = 0; s < ctx->n_scenes; s++) {
+                off[s] = tot;
+                long long r = ctx->h_scenes[s].res;
+                tot += r * r * r;
+            }
+            ctx->cap_nodes = tot;
+            HIPCHK(dalloc(&ctx->d_cap, (size_t)4 * tot));
+            HIPCHK(dalloc(&ctx->d_cap_off, ctx->n_scenes));
+            HIPCHK(hipMemcpy(ctx->d_cap_off, off.data(), sizeof(long long) * ctx->n_scenes, hipMemcpyHostToDevice));
+            HIPCHK(launch_clear_f(ctx->d_cap, 4 * tot, ctx->stream));
+        }
+        ctx->capture = value;
+        return MPM_OK;
+    case MPM_OPT_TIMING:
+        ARGCHK(value == 0 || value == 1, "timing must be 0 or 1");
+        ctx->timing = value;
+        return MPM_OK;
+    }
+    ctx->last_error = "unknown option";
+    return MPM_ERR_ARG;
+}
+
+mpm_status mpm_get_option(mpm_ctx ctx, int option, int *value)
+{
+    ARGCHK(ctx && value, "null argument");
+    switch (option) {
+    case MPM_OPT_SORT_EVERY: *value = ctx->sort_every; return MPM_OK;
+    case MPM_OPT_BLOCK: *value = ctx->B; return MPM_OK;
+    case MPM_OPT_CHUNK: *value = ctx->CH; return MPM_OK;
+    case MPM_OPT_PERSISTENT: *value = ctx->persistent; return MPM_OK;
+    case MPM_OPT_GRAPH: *value = ctx->graph; return MPM_OK;
+    case MPM_OPT_CAPTURE_GRID: *value = ctx->capture; return MPM_OK;
+    case MPM_OPT_TIMING: *value = ctx->timing; return MPM_OK;
+    }
+    ctx->last_error = "unknown option";
+    return MPM_ERR_ARG;
+}
+
+mpm_status mpm_get_timing(mpm_ctx ctx, double *ms_total, long long *launches, int reset)
+{
+    ARGCHK(ctx, "null context");
+    hipSetDevice(ctx->dev);
+    HIPCHK(resolve_timing(ctx));
+    for (int k = 0; k < MPM_KCLASSES; k++) {
+        if (ms_total) ms_total[k] = ctx->kt_ms[k];
+        if (launches) launches[k] = ctx->kt_n[k];
+        if (reset) {
+            ctx->kt_ms[k] = 0.0;
+            ctx->kt_n[k] = 0;
+        }
+    }
+    return MPM_OK;
+}
+
+mpm_status mpm_get_order(mpm_ctx ctx, int *pid_out)
+{
+    ARGCHK(ctx && pid_out, "null argument");
+    hipSetDevice(ctx->dev);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->N > 0)
+        HIPCHK(hipMemcpy(pid_out, ctx->d_P[ctx->cur] + (size_t)PID * ctx->pstride, sizeof(int) * ctx->N,
+                         hipMemcpyDeviceToHost));
+    return MPM_OK;
+}
+
+mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_len)
+{
+    ARGCHK(ctx, "null context");
+    (void)substeps;
+    if (report && report_len) report[0] = 0;
+    ctx->last_error = "autotune not available";
+    return MPM_ERR_STATE;
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Launch interface of the HIP kernels (internal, host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "mpm_types.hpp"
+
+namespace mpm {
+
+// Everything a substep kernel needs, passed by value.
+struct StepArgs {
+    const SceneDev *scenes;
+    int n_scenes;
+    float *P;                 // current particle buffer: component c at P + c * pstride
+    long long pstride;
+    float *gm, *gpx, *gpy, *gpz;   // grid mass / momentum (zero between substeps)
+    float *gvx, *gvy, *gvz;        // grid velocity
+    float *cap;               // optional capture of (m, p) per scene, dense [res^3] x 4, or null
+    const long long *cap_off; // per scene offset into cap (in nodes)
+    const ColliderDev *cols;
+    void *colnow;             // per collider: pose at the current substep (ColliderNow)
+    Lists L;
+    int *flags;               // per scene
+    int substep;              // substep index within the current call
+    int B;                    // block edge
+    int *queue;               // persistent mode: [0] item cursor
+    int *scene_done;          // persistent mode: per scene [3] phase counters
+    int n_wg;                 // persistent mode: number of workgroups launched
+};
+
+
+struct SortArgs {
+    const SceneDev *scenes;
+    int n_scenes;
+    const int *psc;           // scene of each particle slot
+    const float *P;           // current buffer
+    float *Pn;                // other buffer
+    long long pstride;
+    int N;                    // particle slots in use
+    int T;                    // bins in total
+    const int *scene_bin_off; // [n_scenes + 1]
+    unsigned *keys;           // [N]
+    int *count;               // [T] (zero on entry, zero again after scatter)
+    int *pstart;              // [T]
+    int *perm;                // [N]
+    int3 *tsum;               // per scan tile
+    unsigned char *dil;       // [T] 1 = grid block of the dilated particle set (by linear block)
+    Lists L;
+    int B;
+    int CH;                   // max particles per item
+};
+
+hipError_t launch_sort(const SortArgs &a, hipStream_t st);
+hipError_t launch_p2g(const StepArgs &a, int chunk, int n_wg, hipStream_t st);
+hipError_t launch_grid(const StepArgs &a, int n_wg, hipStream_t st);
+hipError_t launch_g2p(const StepArgs &a, int n_wg, hipStream_t st);
+hipError_t launch_collider_advance(ColliderDev *cols, int n_cols, const int *col_scene, const SceneDev *scenes,
+                                   int n_substeps, hipStream_t st);
+
+// Boundary conversions (creation order <-> sorted SoA).
+hipError_t launch_init_particles(const SceneDev *scenes, int n_scenes, const int *psc, float *P, long long pstride,
+                                 const float *x, const float *v, const float *C, const float *F, int begin, int end,
+                                 hipStream_t st);
+hipError_t launch_get_state(const SceneDev *scenes, const int *psc, const float *P, long long pstride, int begin,
+                            int end, float *x, float *v, float *C, float *F, hipStream_t st);
+hipError_t launch_clear_f(float *p, long long n, hipStream_t st);
+hipError_t launch_reset_scene_counters(int *queue, int *scene_done, int n_scenes, int *n_ovf, hipStream_t st);
+
+}  // namespace mpm

@@ -1,0 +1,405 @@
+// Device math of the MLS-MPM substep for gfx950 (FP32).
+//
+// Quadratic B-spline weights and APIC transfer (MLS-MPM, the method the
+// paper's soft-body solver follows, Sec. 3), neo-Hookean and Hencky
+// elasticity with a von Mises return map (App. C.3, Table "tab:mpm_param"),
+// analytic box / capsule SDFs (Sec. 3).
+//
+// Numerical design: the deformation gradient is carried as G = F - I and the
+// Hencky model is evaluated from the eigen-decomposition of F^T F - I =
+// G + G^T + G^T G, so log strains come from log1p of small numbers and keep
+// their relative precision near F = I (an FP32 SVD of F itself loses it).
+// With F^T F = V S^2 V^T and U = F V S^-1 (S signed, last value negative when
+// det F < 0):
+//   tau   = U diag(d) U^T            = F V diag(d_k / S_k^2) V^T F^T
+//   F_new = U exp(eps_new) V^T        = F V diag(exp(eps_new,k) / S_k) V^T
+// so neither U nor an SVD of F is formed.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include "mpm_types.hpp"
+
+namespace mpm {
+
+#define MPM_HD __host__ __device__ __forceinline__
+
+MPM_HD float frcp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
+MPM_HD float frsqrt(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rsqf(x);
+#else
+    return 1.0f / sqrtf(x);
+#endif
+}
+
+MPM_HD float fsqrt(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return sqrtf(x);
+#endif
+}
+
+// ---------------------------------------------------------------- Morton order
+MPM_HD uint32_t spread3(uint32_t x)
+{
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000FFu;
+    x = (x | (x << 8)) & 0x0300F00Fu;
+    x = (x | (x << 4)) & 0x030C30C3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+MPM_HD uint32_t compact3(uint32_t x)
+{
+    x &= 0x09249249u;
+    x = (x ^ (x >> 2)) & 0x030C30C3u;
+    x = (x ^ (x >> 4)) & 0x0300F00Fu;
+    x = (x ^ (x >> 8)) & 0x030000FFu;
+    x = (x ^ (x >> 16)) & 0x000003FFu;
+    return x;
+}
+
+MPM_HD uint32_t morton3(uint32_t x, uint32_t y, uint32_t z)
+{
+    return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+// ---------------------------------------------------------------- B-spline
+// Weights of nodes base, base+1, base+2 for fractional offset f in [0.5, 1.5).
+MPM_HD void bspline_w(float f, float w[3])
+{
+    float a = 1.5f - f, b = f - 1.0f, c = f - 0.5f;
+    w[0] = 0.5f * a * a;
+    w[1] = 0.75f - b * b;
+    w[2] = 0.5f * c * c;
+}
+
+// ---------------------------------------------------------------- 3x3 symmetric eigen
+// Cyclic Jacobi on a symmetric matrix held as (a00, a11, a22, a01, a02, a12).
+// On return the diagonal holds the eigenvalues and V (row-major, columns =
+// eigenvectors) the rotation.  Four sweeps of three rotations reach FP32
+// precision for 3x3 input.
+#ifndef MPM_JACOBI_SWEEPS
+#define MPM_JACOBI_SWEEPS 4
+#endif
+struct Sym3 {
+    float a00, a11, a22, a01, a02, a12;
+};
+
+MPM_HD void jacobi_rot(float &app, float &aqq, float &apq, float &arp, float &arq, float *V, int p, int q)
+{
+    float t = 0.0f;
+    if (apq != 0.0f) {
+        float zeta = (aqq - app) * frcp(2.0f * apq);
+        float az = fabsf(zeta);
+        float tt = frcp(az + fsqrt(fmaf(az, az, 1.0f)));
+        t = zeta >= 0.0f ? tt : -tt;
+        if (az > 1e18f) t = 0.0f;     // rotation smaller than rounding
+    }
+    float c = frsqrt(fmaf(t, t, 1.0f));
+    float s = t * c;
+    app = fmaf(-t, apq, app);
+    aqq = fmaf(t, apq, aqq);
+    apq = 0.0f;
+    float rp = arp, rq = arq;
+    arp = c * rp - s * rq;
+    arq = s * rp + c * rq;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        float vp = V[3 * k + p], vq = V[3 * k + q];
+        V[3 * k + p] = c * vp - s * vq;
+        V[3 * k + q] = s * vp + c * vq;
+    }
+}
+
+MPM_HD void sym_eig(Sym3 &a, float V[9])
+{
+#pragma unroll
+    for (int i = 0; i < 9; i++) V[i] = (i % 4 == 0) ? 1.0f : 0.0f;
+#pragma unroll
+    for (int sweep = 0; sweep < MPM_JACOBI_SWEEPS; sweep++) {
+        jacobi_rot(a.a00, a.a11, a.a01, a.a02, a.a12, V, 0, 1);   // r = 2: a20 = a02, a21 = a12
+        jacobi_rot(a.a00, a.a22, a.a02, a.a01, a.a12, V, 0, 2);   // r = 1: a10 = a01, a12
+        jacobi_rot(a.a11, a.a22, a.a12, a.a01, a.a02, V, 1, 2);   // r = 0: a01, a02
+    }
+}
+
+// ---------------------------------------------------------------- constitutive models
+// All matrices row-major [9].  G = F - I.
+
+MPM_HD float det_minus_one(const float *G)
+{
+    // det(I + G) - 1 = tr G + (tr G^2 ... ) expanded to keep precision near G = 0
+    float tr = G[0] + G[4] + G[8];
+    float m2 = (G[0] * G[4] - G[1] * G[3]) + (G[0] * G[8] - G[2] * G[6]) + (G[4] * G[8] - G[5] * G[7]);
+    float d3 = G[0] * (G[4] * G[8] - G[5] * G[7]) - G[1] * (G[3] * G[8] - G[5] * G[6]) +
+               G[2] * (G[3] * G[7] - G[4] * G[6]);
+    return tr + m2 + d3;
+}
+
+// Neo-Hookean Kirchhoff stress: mu (F F^T - I) + lambda ln(J) I.
+MPM_HD void tau_neo_hookean(const float *G, float mu, float la, float tau[9], int &bad)
+{
+    float jm1 = det_minus_one(G);
+    bad |= !(jm1 > -1.0f);
+    float lnJ = log1pf(jm1);
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = i; j < 3; j++) {
+            // F F^T - I = G + G^T + G G^T
+            float ggt = G[3 * i] * G[3 * j] + G[3 * i + 1] * G[3 * j + 1] + G[3 * i + 2] * G[3 * j + 2];
+            float v = mu * (G[3 * i + j] + G[3 * j + i] + ggt) + (i == j ? la * lnJ : 0.0f);
+            tau[3 * i + j] = v;
+            tau[3 * j + i] = v;
+        }
+}
+
+struct Material {
+    int model, plastic;
+    float mu, la, yield_eps;
+};
+
+// tau = F M F^T for symmetric M, F = I + G (row-major).
+MPM_HD void tau_from_M(const float *G, const float *M, float tau[9])
+{
+    float FM[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            float acc = M[3 * i + j];
+#pragma unroll
+            for (int k = 0; k < 3; k++) acc = fmaf(G[3 * i + k], M[3 * k + j], acc);
+            FM[3 * i + j] = acc;
+        }
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = i; j < 3; j++) {
+            float acc = FM[3 * i + j];
+#pragma unroll
+            for (int k = 0; k < 3; k++) acc = fmaf(FM[3 * i + k], G[3 * j + k], acc);
+            tau[3 * i + j] = acc;
+            tau[3 * j + i] = acc;
+        }
+}
+
+// Hencky elasticity with an optional von Mises return map.  Gt is the trial
+// displacement gradient; Gout receives the projected one (may alias Gt only
+// through a copy made by the caller), tau the Kirchhoff stress of Gout.
+// Returns 1 if the particle yielded.
+MPM_HD int hencky_update(const float *Gt, const Material &mat, float *Gout, float tau[9], int &bad)
+{
+    const float SMIN = 1e-6f;
+    Sym3 s;   // C - I = G + G^T + G^T G
+    s.a00 = 2.0f * Gt[0] + (Gt[0] * Gt[0] + Gt[3] * Gt[3] + Gt[6] * Gt[6]);
+    s.a11 = 2.0f * Gt[4] + (Gt[1] * Gt[1] + Gt[4] * Gt[4] + Gt[7] * Gt[7]);
+    s.a22 = 2.0f * Gt[8] + (Gt[2] * Gt[2] + Gt[5] * Gt[5] + Gt[8] * Gt[8]);
+    s.a01 = Gt[1] + Gt[3] + (Gt[0] * Gt[1] + Gt[3] * Gt[4] + Gt[6] * Gt[7]);
+    s.a02 = Gt[2] + Gt[6] + (Gt[0] * Gt[2] + Gt[3] * Gt[5] + Gt[6] * Gt[8]);
+    s.a12 = Gt[5] + Gt[7] + (Gt[1] * Gt[2] + Gt[4] * Gt[5] + Gt[7] * Gt[8]);
+    float V[9];
+    sym_eig(s, V);
+    float lam[3] = {s.a00, s.a11, s.a22};
+    float jm1 = det_minus_one(Gt);
+    bad |= !(jm1 == jm1);
+    // the smallest singular value carries the sign of det F
+    int kmin = lam[0] <= lam[1] ? (lam[0] <= lam[2] ? 0 : 2) : (lam[1] <= lam[2] ? 1 : 2);
+    float sig2[3], eps[3], sgn[3];
+    int clamp[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        sig2[k] = 1.0f + lam[k];
+        sgn[k] = (k == kmin && jm1 < -1.0f) ? -1.0f : 1.0f;
+        clamp[k] = (sgn[k] < 0.0f) || !(sig2[k] >= SMIN * SMIN);
+        eps[k] = clamp[k] ? logf(SMIN) : 0.5f * log1pf(lam[k]);
+    }
+    float tr = eps[0] + eps[1] + eps[2];
+    float mean = tr * (1.0f / 3.0f);
+    float dv[3] = {eps[0] - mean, eps[1] - mean, eps[2] - mean};
+    float nd = fsqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    float dg = nd - mat.yield_eps;
+    int yielded = mat.plastic && dg > 0.0f;
+    float en[3] = {eps[0], eps[1], eps[2]};
+#pragma unroll
+    for (int i = 0; i < 9; i++) Gout[i] = Gt[i];
+    if (yielded) {
+        float r = dg / nd;
+        float q[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            en[k] = eps[k] - r * dv[k];
+            float sk = sgn[k] * fsqrt(fmaxf(sig2[k], 0.0f));
+            q[k] = clamp[k] ? expf(en[k]) / sk - 1.0f : expm1f(en[k] - eps[k]);
+        }
+        // F_new = F (I + Q), Q = V diag(q) V^T  ->  G_new = G + Q + G Q
+        float Q[9];
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++)
+                Q[3 * i + j] = V[3 * i] * q[0] * V[3 * j] + V[3 * i + 1] * q[1] * V[3 * j + 1] +
+                               V[3 * i + 2] * q[2] * V[3 * j + 2];
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++)
+                Gout[3 * i + j] = Gt[3 * i + j] + Q[3 * i + j] +
+                                  (Gt[3 * i] * Q[j] + Gt[3 * i + 1] * Q[3 + j] + Gt[3 * i + 2] * Q[6 + j]);
+    }
+    // tau = U diag(d) U^T with U = F V S^-1 of the trial F (the return map
+    // keeps U and V): tau = F M F^T, M = V diag(d_k / S_k^2) V^T.
+    float trn = en[0] + en[1] + en[2];
+    float dk[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) dk[k] = (2.0f * mat.mu * en[k] + mat.la * trn) / fmaxf(sig2[k], SMIN * SMIN);
+    float M[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+            M[3 * i + j] = V[3 * i] * dk[0] * V[3 * j] + V[3 * i + 1] * dk[1] * V[3 * j + 1] +
+                           V[3 * i + 2] * dk[2] * V[3 * j + 2];
+    tau_from_M(Gt, M, tau);
+    return yielded;
+}
+
+// Stress of a state without any return map (a state handed in from outside).
+MPM_HD void stress_of(const float *G, const Material &mat, float tau[9], int &bad)
+{
+    if (mat.model == 0) {
+        tau_neo_hookean(G, mat.mu, mat.la, tau, bad);
+        return;
+    }
+    Material m2 = mat;
+    m2.plastic = 0;
+    float Gc[9];
+    hencky_update(G, m2, Gc, tau, bad);
+}
+
+// ---------------------------------------------------------------- rotations and SDFs
+MPM_HD void quat_to_mat(const float q[4], float R[9])
+{
+    float w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z); R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z); R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y); R[7] = 2 * (y * z + w * x); R[8] = 1 - 2 * (x * x + y * y);
+}
+
+// q_k = exp(k dt w / 2) (x) q0
+MPM_HD void quat_advance(const float q0[4], const float w[3], float tk, float q[4])
+{
+    float wn = sqrtf(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    if (wn == 0.0f) {
+        q[0] = q0[0]; q[1] = q0[1]; q[2] = q0[2]; q[3] = q0[3];
+        return;
+    }
+    float h = 0.5f * tk * wn;
+    float sh = sinf(h) / wn, ch = cosf(h);
+    float d[4] = {ch, sh * w[0], sh * w[1], sh * w[2]};
+    q[0] = d[0] * q0[0] - d[1] * q0[1] - d[2] * q0[2] - d[3] * q0[3];
+    q[1] = d[0] * q0[1] + d[1] * q0[0] + d[2] * q0[3] - d[3] * q0[2];
+    q[2] = d[0] * q0[2] - d[1] * q0[3] + d[2] * q0[0] + d[3] * q0[1];
+    q[3] = d[0] * q0[3] + d[1] * q0[2] - d[2] * q0[1] + d[3] * q0[0];
+}
+
+// Collider at one substep: world pose + rotation matrix.
+struct ColliderNow {
+    int type;
+    float he[3], radius, half_length, friction;
+    float c[3], R[9], v[3], w[3];
+};
+
+MPM_HD void collider_at(const ColliderDev &cd, float tk, ColliderNow &cn)
+{
+    cn.type = cd.type;
+    for (int a = 0; a < 3; a++) {
+        cn.he[a] = cd.he[a];
+        cn.c[a] = fmaf(tk, cd.vlin[a], cd.pos[a]);
+        cn.v[a] = cd.vlin[a];
+        cn.w[a] = cd.omega[a];
+    }
+    cn.radius = cd.radius;
+    cn.half_length = cd.half_length;
+    cn.friction = cd.friction;
+    float q[4];
+    quat_advance(cd.quat, cd.omega, tk, q);
+    quat_to_mat(q, cn.R);
+}
+
+// Signed distance and outward unit normal (world).  Box interior: nearest
+// face, ties to the lowest axis, + before -.  Capsule on its axis: body +x.
+MPM_HD float sdf_eval(const ColliderNow &c, const float x[3], float n[3])
+{
+    float r[3] = {x[0] - c.c[0], x[1] - c.c[1], x[2] - c.c[2]};
+    float p[3];
+    for (int a = 0; a < 3; a++) p[a] = c.R[a] * r[0] + c.R[3 + a] * r[1] + c.R[6 + a] * r[2];   // R^T r
+    float nb[3] = {0.0f, 0.0f, 0.0f};
+    float phi;
+    if (c.type == 0) {
+        float q[3], out = 0.0f;
+        for (int a = 0; a < 3; a++) {
+            q[a] = fabsf(p[a]) - c.he[a];
+            if (q[a] > 0.0f) out += q[a] * q[a];
+        }
+        if (out > 0.0f) {
+            phi = sqrtf(out);
+            float ip = 1.0f / phi;
+            for (int a = 0; a < 3; a++) nb[a] = q[a] > 0.0f ? copysignf(q[a] * ip, p[a] >= 0.0f ? 1.0f : -1.0f) : 0.0f;
+        } else {
+            int best = 0;
+            if (q[1] > q[best]) best = 1;
+            if (q[2] > q[best]) best = 2;
+            phi = q[best];
+            nb[best] = p[best] >= 0.0f ? 1.0f : -1.0f;
+        }
+    } else {
+        float t = fminf(fmaxf(p[1], -c.half_length), c.half_length);
+        float d[3] = {p[0], p[1] - t, p[2]};
+        float len = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        phi = len - c.radius;
+        if (len > 0.0f) {
+            float il = 1.0f / len;
+            nb[0] = d[0] * il; nb[1] = d[1] * il; nb[2] = d[2] * il;
+        } else {
+            nb[0] = 1.0f;
+        }
+    }
+    for (int a = 0; a < 3; a++) n[a] = c.R[3 * a] * nb[0] + c.R[3 * a + 1] * nb[1] + c.R[3 * a + 2] * nb[2];
+    return phi;
+}
+
+// Grid-node contact: separating test and Coulomb friction (in place).
+MPM_HD int collide_node(const ColliderNow &c, const float xi[3], float v[3])
+{
+    float n[3];
+    float phi = sdf_eval(c, xi, n);
+    float r[3] = {xi[0] - c.c[0], xi[1] - c.c[1], xi[2] - c.c[2]};
+    float vc[3] = {c.v[0] + (c.w[1] * r[2] - c.w[2] * r[1]),
+                   c.v[1] + (c.w[2] * r[0] - c.w[0] * r[2]),
+                   c.v[2] + (c.w[0] * r[1] - c.w[1] * r[0])};
+    float u[3] = {v[0] - vc[0], v[1] - vc[1], v[2] - vc[2]};
+    float un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
+    if (!(phi < 0.0f && un < 0.0f)) return 0;
+    float ut[3] = {u[0] - un * n[0], u[1] - un * n[1], u[2] - un * n[2]};
+    float lt = sqrtf(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+    float scale = 0.0f;
+    if (!isinf(c.friction) && lt > 0.0f) scale = fmaxf(0.0f, 1.0f + c.friction * un / lt);
+    for (int a = 0; a < 3; a++) v[a] = vc[a] + scale * ut[a];
+    return 1;
+}
+
+}  // namespace mpm

@@ -1,0 +1,266 @@
+"""Python binding of libmpm_hip.so (argument marshalling only).
+
+Every step of the substep runs in the library's HIP kernels; this module
+builds the C structs, passes host arrays or torch device pointers, and maps
+status codes to exceptions.  The library must exist (``__graft_entry__.build``
+or ``python -m paper_2302_04659_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import math
+import os
+import re
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpm_hip.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mpm.h")
+
+OK, WARN_CLAMPED, WARN_FALLBACK = 0, 1, 2
+ERR_ARG, ERR_HIP, ERR_OOM, ERR_NONFINITE, ERR_STATE = -1, -2, -3, -4, -5
+OPT_SORT_EVERY, OPT_BLOCK, OPT_CHUNK, OPT_PERSISTENT, OPT_GRAPH, OPT_CAPTURE_GRID, OPT_TIMING = range(7)
+K_SORT, K_P2G, K_GRID, K_G2P = range(4)
+KERNEL_CLASSES = ("sort", "p2g", "grid", "g2p")
+MAX_COLLIDERS = 4
+
+
+class Material(ct.Structure):
+    _fields_ = [("model", ct.c_int), ("E", ct.c_float), ("nu", ct.c_float), ("rho", ct.c_float),
+                ("yield_stress", ct.c_float), ("yield_form", ct.c_int)]
+
+
+class ColliderShape(ct.Structure):
+    _fields_ = [("type", ct.c_int), ("half_extents", ct.c_float * 3), ("radius", ct.c_float),
+                ("half_length", ct.c_float), ("friction", ct.c_float)]
+
+
+class SceneDesc(ct.Structure):
+    _fields_ = [("n_particles", ct.c_int), ("x", ct.POINTER(ct.c_float)), ("v", ct.POINTER(ct.c_float)),
+                ("particle_volume", ct.c_float), ("res", ct.c_int), ("dx", ct.c_float), ("dt", ct.c_float),
+                ("gravity", ct.c_float * 3), ("bound", ct.c_int), ("mat", Material), ("n_colliders", ct.c_int),
+                ("colliders", ct.POINTER(ColliderShape))]
+
+
+class MPMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libmpm_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2302_04659_amd.build`")
+        L = ct.CDLL(LIB_PATH)
+        vp, fp, ip = ct.c_void_p, ct.POINTER(ct.c_float), ct.POINTER(ct.c_int)
+        L.mpm_create.argtypes = [ct.POINTER(SceneDesc), ct.c_int, vp, ct.POINTER(vp)]
+        L.mpm_destroy.argtypes = [vp]
+        L.mpm_set_colliders.argtypes = [vp, vp, vp, ct.c_int]
+        L.mpm_step.argtypes = [vp, ct.c_int]
+        L.mpm_sync.argtypes = [vp]
+        L.mpm_get_particles.argtypes = [vp, ct.c_int, vp, vp, vp, ct.c_int]
+        L.mpm_get_state.argtypes = [vp, ct.c_int, vp, vp, vp, vp, ct.c_int]
+        L.mpm_set_state.argtypes = [vp, ct.c_int, vp, vp, vp, vp, ct.c_int]
+        L.mpm_get_grid.argtypes = [vp, ct.c_int, vp, vp, ct.c_int]
+        L.mpm_set_option.argtypes = [vp, ct.c_int, ct.c_int]
+        L.mpm_get_option.argtypes = [vp, ct.c_int, ip]
+        L.mpm_autotune.argtypes = [vp, ct.c_int, ct.c_char_p, ct.c_size_t]
+        L.mpm_get_order.argtypes = [vp, vp]
+        L.mpm_get_timing.argtypes = [vp, vp, vp, ct.c_int]
+        for name in ("mpm_num_scenes", "mpm_max_colliders"):
+            getattr(L, name).argtypes = [vp]
+        L.mpm_num_particles.argtypes = [vp, ct.c_int]
+        L.mpm_res.argtypes = [vp, ct.c_int]
+        L.mpm_status_string.argtypes = [ct.c_int]
+        L.mpm_status_string.restype = ct.c_char_p
+        L.mpm_last_error.argtypes = [vp]
+        L.mpm_last_error.restype = ct.c_char_p
+        _lib = L
+    return _lib
+
+
+def declared_functions() -> List[str]:
+    """Names of the functions include/mpm.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpm_[a-z_]+)\s*\(", txt)))
+
+
+def _ptr(a) -> Optional[int]:
+    """Host numpy float32/int32 array or torch tensor -> raw address."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags.c_contiguous, "array must be C-contiguous"
+        return a.ctypes.data
+    return a.data_ptr()   # torch tensor (device or host)
+
+
+def _f32(a, shape) -> np.ndarray:
+    out = np.ascontiguousarray(a, dtype=np.float32)
+    return out.reshape(shape)
+
+
+class Sim:
+    """A batch of MPM scenes living on the GPU (one mpm_ctx)."""
+
+    def __init__(self, scene_list: Sequence, stream=None):
+        self.L = lib()
+        self.scenes = list(scene_list)
+        n = len(self.scenes)
+        self._keep = []
+        descs = (SceneDesc * n)()
+        for i, sc in enumerate(self.scenes):
+            x = _f32(sc.x, (sc.n, 3))
+            v = _f32(sc.v, (sc.n, 3))
+            self._keep += [x, v]
+            d = descs[i]
+            d.n_particles = sc.n
+            d.x = x.ctypes.data_as(ct.POINTER(ct.c_float))
+            d.v = v.ctypes.data_as(ct.POINTER(ct.c_float))
+            d.particle_volume = sc.particle_volume
+            d.res, d.dx, d.dt = sc.res, sc.dx, sc.dt
+            d.gravity[:] = list(sc.gravity)
+            d.bound = sc.bound
+            d.mat = Material(sc.model, sc.E, sc.nu, sc.rho, sc.yield_stress, sc.yield_form)
+            d.n_colliders = sc.n_colliders
+            if sc.n_colliders:
+                cs = (ColliderShape * sc.n_colliders)()
+                for k, c in enumerate(sc.colliders):
+                    cs[k].type = c.type
+                    cs[k].half_extents[:] = [float(h) for h in c.half_extents]
+                    cs[k].radius, cs[k].half_length = c.radius, c.half_length
+                    cs[k].friction = c.friction
+                self._keep.append(cs)
+                d.colliders = ct.cast(cs, ct.POINTER(ColliderShape))
+        h = ct.c_void_p()
+        st = self.L.mpm_create(descs, n, ct.c_void_p(stream) if stream else None, ct.byref(h))
+        if st != OK:
+            raise MPMError(st, "mpm_create failed: " + self.L.mpm_status_string(st).decode())
+        self.h = h
+        self._keep = []
+        self.n_scenes = n
+        self.N = int(self.L.mpm_num_particles(self.h, -1))
+        self.max_col = int(self.L.mpm_max_colliders(self.h))
+        self.offsets = np.cumsum([0] + [sc.n for sc in self.scenes])
+
+    # ----------------------------------------------------------------- errors
+    def _check(self, st: int, what: str, allow_warn: bool = True):
+        if st == OK or (allow_warn and st > 0):
+            return st
+        raise MPMError(st, f"{what}: {self.L.mpm_last_error(self.h).decode()}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.mpm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------------- calls
+    def set_colliders(self, poses, vels, on_device: bool = False):
+        """poses (n_scenes, max_col, 7), vels (n_scenes, max_col, 6)."""
+        if on_device:
+            return self._check(self.L.mpm_set_colliders(self.h, _ptr(poses), _ptr(vels), 1), "set_colliders")
+        P = _f32(poses, (self.n_scenes, self.max_col, 7))
+        V = _f32(vels, (self.n_scenes, self.max_col, 6))
+        return self._check(self.L.mpm_set_colliders(self.h, P.ctypes.data, V.ctypes.data, 0), "set_colliders")
+
+    def set_colliders_ctrl(self, k: int):
+        """Hand over every scene's poses / velocities of control step k."""
+        if self.max_col == 0:
+            return
+        P = np.zeros((self.n_scenes, self.max_col, 7), np.float32)
+        V = np.zeros((self.n_scenes, self.max_col, 6), np.float32)
+        P[:, :, 3] = 1.0
+        for s, sc in enumerate(self.scenes):
+            if sc.n_colliders:
+                P[s, : sc.n_colliders] = sc.ctrl_poses[k]
+                V[s, : sc.n_colliders] = sc.ctrl_vels[k]
+        self.set_colliders(P, V)
+
+    def step(self, n: int = 1):
+        return self._check(self.L.mpm_step(self.h, int(n)), "step")
+
+    def sync(self):
+        return self._check(self.L.mpm_sync(self.h), "sync")
+
+    def run_schedule(self, n_ctrl: int, substeps: int = 25, ctrl0: int = 0):
+        for k in range(ctrl0, ctrl0 + n_ctrl):
+            self.set_colliders_ctrl(k)
+            self.step(substeps)
+
+    def _count(self, scene: int) -> int:
+        return self.N if scene < 0 else int(self.offsets[scene + 1] - self.offsets[scene])
+
+    def get_state(self, scene: int = -1):
+        n = self._count(scene)
+        x = np.zeros((n, 3), np.float32)
+        v = np.zeros((n, 3), np.float32)
+        C = np.zeros((n, 3, 3), np.float32)
+        F = np.zeros((n, 3, 3), np.float32)
+        self._check(self.L.mpm_get_state(self.h, scene, x.ctypes.data, v.ctypes.data, C.ctypes.data,
+                                         F.ctypes.data, 0), "get_state")
+        return x, v, C, F
+
+    def get_particles(self, scene: int = -1, with_v: bool = True, with_F: bool = False):
+        n = self._count(scene)
+        x = np.zeros((n, 3), np.float32)
+        v = np.zeros((n, 3), np.float32) if with_v else None
+        F = np.zeros((n, 3, 3), np.float32) if with_F else None
+        self._check(self.L.mpm_get_particles(self.h, scene, x.ctypes.data, _ptr(v), _ptr(F), 0), "get_particles")
+        return x, v, F
+
+    def get_particles_device(self, x, v=None, F=None, scene: int = -1):
+        """Copy into torch device tensors (stream-ordered, no host round trip)."""
+        return self._check(self.L.mpm_get_particles(self.h, scene, _ptr(x), _ptr(v), _ptr(F), 1),
+                           "get_particles")
+
+    def set_state(self, x, v, C, F, scene: int = -1):
+        n = self._count(scene)
+        arrs = [_f32(x, (n, 3)), _f32(v, (n, 3)), _f32(C, (n, 3, 3)), _f32(F, (n, 3, 3))]
+        return self._check(self.L.mpm_set_state(self.h, scene, *[a.ctypes.data for a in arrs], 0), "set_state")
+
+    def get_grid(self, scene: int):
+        r = int(self.L.mpm_res(self.h, scene))
+        m = np.zeros((r, r, r), np.float32)
+        p = np.zeros((r, r, r, 3), np.float32)
+        self._check(self.L.mpm_get_grid(self.h, scene, m.ctypes.data, p.ctypes.data, 0), "get_grid")
+        return m, p
+
+    def set_option(self, opt: int, value: int):
+        return self._check(self.L.mpm_set_option(self.h, opt, int(value)), "set_option", allow_warn=False)
+
+    def get_option(self, opt: int) -> int:
+        v = ct.c_int()
+        self._check(self.L.mpm_get_option(self.h, opt, ct.byref(v)), "get_option")
+        return v.value
+
+    def order(self) -> np.ndarray:
+        pid = np.zeros(self.N, np.int32)
+        self._check(self.L.mpm_get_order(self.h, pid.ctypes.data), "get_order")
+        return pid
+
+    def timing(self, reset: bool = True):
+        """{kernel class: (total ms, launches)} from the library's HIP events."""
+        ms = np.zeros(4, np.float64)
+        n = np.zeros(4, np.int64)
+        self._check(self.L.mpm_get_timing(self.h, ms.ctypes.data, n.ctypes.data, int(reset)), "get_timing")
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def autotune(self, substeps: int = 10) -> str:
+        buf = ct.create_string_buffer(4096)
+        self._check(self.L.mpm_autotune(self.h, int(substeps), buf, 4096), "autotune")
+        return buf.value.decode()

@@ -1,0 +1,73 @@
+"""Host-side checks that need no GPU: the C-ABI library loads and exports
+every function include/mpm.h declares, and the seeded scene generators are
+reproducible and shaped like the workloads they stand for."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2302_04659_amd import scenes
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2302_04659_amd import mpm
+    if not os.path.exists(mpm.LIB_PATH):
+        pytest.skip("libmpm_hip.so not built (run __graft_entry__.build())")
+    L = mpm.lib()
+    names = mpm.declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings_without_gpu():
+    from paper_2302_04659_amd import mpm
+    if not os.path.exists(mpm.LIB_PATH):
+        pytest.skip("libmpm_hip.so not built")
+    L = mpm.lib()
+    assert L.mpm_status_string(0) == b"ok"
+    assert b"invalid" in L.mpm_status_string(-1)
+    assert L.mpm_num_scenes(None) == 0
+
+
+def test_struct_layout_matches_header():
+    """ctypes mirrors of the C structs have the C sizes (x86-64 SysV)."""
+    from paper_2302_04659_amd import mpm
+    import ctypes as ct
+    assert ct.sizeof(mpm.Material) == 24
+    assert ct.sizeof(mpm.ColliderShape) == 28
+    # int, pad, 2 pointers, float, int, 2 floats, 3 floats, int, material(24), int, pad, pointer
+    assert ct.sizeof(mpm.SceneDesc) == 4 + 4 + 8 + 8 + 4 + 4 + 8 + 12 + 4 + 24 + 4 + 4 + 8
+
+
+def test_scene_generators_reproducible():
+    a, b = scenes.cfg2(seed=5), scenes.cfg2(seed=5)
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.ctrl_poses, b.ctrl_poses)
+    c = scenes.cfg2(seed=6)
+    assert not np.array_equal(a.x, c.x)
+
+
+def test_workload_shapes():
+    s1 = scenes.cfg1()
+    assert s1.n == 8192 and s1.res == 32 and s1.x.dtype == np.float32
+    # 16 particles in each of the 8^3 sub-cubes (stratified)
+    cell = np.floor((s1.x.astype(np.float64) - [0.375, 3 / 32 + 0.1, 0.375]) / (0.25 / 8)).astype(int)
+    _, counts = np.unique(cell, axis=0, return_counts=True)
+    assert counts.min() == 16 and counts.max() == 16
+    s2 = scenes.cfg2()
+    assert s2.n == 65536 and s2.res == 64 and s2.n_colliders == 1
+    counts = scenes.cfg3_counts()
+    assert len(counts) == 256 and counts.min() >= 1e4 and counts.max() <= 6e4
+    assert abs(counts.mean() - 27906) < 0.1 * 27906          # E[N] of log-uniform [1e4, 6e4]
+    for sc in scenes.cfg3(n_scenes=8, n_ctrl=2):
+        assert 1 <= sc.n_colliders <= 2
+        lo = sc.x.min(0)
+        assert lo[1] >= 3 * sc.dx - 1e-6                   # resting on the floor plane
+        assert (sc.x.max(0) < 1 - 3 * sc.dx).all()
+
+
+def test_cfg4_heap_shape():
+    s = scenes.cfg4(n_ctrl=2)
+    assert s.n == 1048576 and s.res == 128 and s.n_colliders == 3
+    r = np.linalg.norm(s.x.astype(np.float64) - [0.5, 3 / 128, 0.5], axis=1)
+    assert r.max() <= 0.311 and (s.x[:, 1] >= 3 / 128 - 1e-6).all()

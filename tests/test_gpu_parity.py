@@ -1,0 +1,155 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars (from the method's own tolerances):
+  * grid momentum of one P2G from identical FP32 inputs:
+      |p_gpu - p_orc|_2 / max(|p_orc|_2, sum m |g| dt) <= 1e-5
+  * particle positions after 100 free-running substeps: max |dx| <= 1e-3 dx
+"""
+import numpy as np
+import pytest
+
+from gpu_util import announce, momentum_floor, random_state, rel_l2
+from paper_2302_04659_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mpm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need the MI355X"
+    from paper_2302_04659_amd import mpm as m
+    m.lib()
+    return m
+
+
+def _teacher_scenes():
+    return [
+        ("small-nh", scenes.small_scene(1, n=3000, res=16, model=scenes.NEO_HOOKEAN)),
+        ("small-hencky", scenes.small_scene(2, n=3000, res=16, model=scenes.HENCKY_VM)),
+        ("cfg1b", scenes.cfg1b()),
+        ("cfg2", scenes.cfg2()),
+    ]
+
+
+@pytest.mark.parametrize("name,idx", [(n, i) for i, (n, _) in enumerate(_teacher_scenes())])
+@pytest.mark.parametrize("block", [4, 8])
+def test_teacher_forced_p2g_and_substep(mpm, orc, name, idx, block):
+    sc = _teacher_scenes()[idx][1]
+    announce("teacher-forced", name, "B", block, "n", sc.n)
+    C, F = random_state(sc, 10 + idx, c_scale=2.0, f_scale=0.05)
+    sim = mpm.Sim([sc])
+    sim.set_option(mpm.OPT_BLOCK, block)
+    sim.set_option(mpm.OPT_CAPTURE_GRID, 1)
+    sim.set_state(sc.x, sc.v, C, F)
+    o = orc.Oracle(sc, x=sc.x, v=sc.v, C=C, F=F)
+    if sc.n_colliders:
+        sim.set_colliders_ctrl(0)
+        o.set_colliders(sc.ctrl_poses[0], sc.ctrl_vels[0])
+    sim.step(1)
+    sim.sync()
+    gm, gp = sim.get_grid(0)
+    om, op = o.p2g()
+    floor = momentum_floor(sc, om.sum())
+    assert rel_l2(gm, om) <= 1e-6
+    err_p = rel_l2(gp, op, floor)
+    print(name, "grid momentum rel err", err_p)
+    assert err_p <= 1e-5
+    o.grid_op()
+    o.g2p()
+    x, v, Cg, Fg = sim.get_state(0)
+    dx = sc.dx
+    assert np.abs(x - o.x).max() <= 1e-4 * dx
+    vs = max(np.abs(o.v).max(), 1e-3)
+    assert np.abs(v - o.v).max() <= 1e-4 * vs
+    assert np.abs(Fg - o.F).max() <= 1e-5
+    cs = max(np.abs(o.C).max(), 1e-3)
+    assert np.abs(Cg - o.C).max() <= 1e-3 * cs
+    sim.close()
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg1b", "cfg2", "small-hencky", "small-sticky"])
+def test_free_running_100(mpm, orc, name):
+    if name == "small-hencky":
+        sc = scenes.small_scene(3, n=4000, res=32, model=scenes.HENCKY_VM, n_ctrl=4, dt=1e-4)
+    elif name == "small-sticky":
+        sc = scenes.small_scene(4, n=4000, res=32, model=scenes.NEO_HOOKEAN, n_ctrl=4, dt=1e-4,
+                                friction=float("inf"), omega=2.0)
+    else:
+        sc = scenes.WORKLOADS[name]()
+    announce("free-running 100", name, "n", sc.n)
+    sim = mpm.Sim([sc])
+    o = orc.Oracle(sc)
+    sim.run_schedule(4)
+    o.run_schedule(4)
+    st = sim.sync()
+    assert st == mpm.OK
+    x, v, C, F = sim.get_state(0)
+    err = np.abs(x - o.x).max() / sc.dx
+    print(name, "max position error / dx after 100 substeps:", err,
+          "rms", np.sqrt(((x - o.x) ** 2).sum(1).mean()) / sc.dx)
+    assert err <= 1e-3
+    if name == "cfg1":      # ballistic closed form
+        n = 100
+        g = np.array(sc.gravity)
+        x_exp = sc.x.astype(np.float64) + g * sc.dt ** 2 * n * (n + 1) / 2
+        assert np.abs(x - x_exp).max() <= 1e-3 * sc.dx
+        assert np.abs(F - np.eye(3)).max() <= 1e-5
+    sim.close()
+
+
+def _morton(x, y, z):
+    out = 0
+    for bit in range(10):
+        out |= ((x >> bit) & 1) << (3 * bit) | ((y >> bit) & 1) << (3 * bit + 1) | ((z >> bit) & 1) << (3 * bit + 2)
+    return out
+
+
+@pytest.mark.parametrize("block", [4, 8])
+def test_sort_order_is_valid(mpm, block):
+    """Internal order right after a re-sort: a permutation, scene segments
+    kept, Morton codes of the particles' blocks non-decreasing per scene.
+    (Equal keys may come in any order; only the key sequence is unique.)"""
+    batch = [scenes.small_scene(s, n=500 + 300 * s, res=32) for s in range(4)]
+    announce("sort order", len(batch), "B", block)
+    sim = mpm.Sim(batch)
+    sim.set_option(mpm.OPT_BLOCK, block)
+    x0 = np.concatenate([sc.x for sc in batch])
+    v0 = np.concatenate([sc.v for sc in batch])
+    n = x0.shape[0]
+    sim.set_state(x0, v0, np.zeros((n, 3, 3)), np.tile(np.eye(3), (n, 1, 1)))
+    sim.step(1)                      # the step starts with the re-sort
+    sim.sync()
+    pid = sim.order()
+    assert np.array_equal(np.sort(pid), np.arange(sim.N))
+    for s, sc in enumerate(batch):
+        lo, hi = sim.offsets[s], sim.offsets[s + 1]
+        seg = pid[lo:hi]
+        assert seg.min() >= lo and seg.max() < hi
+        base = np.clip(np.floor(x0[seg].astype(np.float64) * sc.res - 0.5).astype(int), 0, sc.res - 3)
+        blk = base // block
+        keys = np.array([_morton(*b) for b in blk])
+        assert (np.diff(keys) >= 0).all()
+    sim.close()
+
+
+def test_batched_equals_single(mpm, orc):
+    """Scenes in one batch evolve exactly as when simulated alone (to FP32
+    reorder tolerance) and match the oracle; includes an empty scene."""
+    batch = [scenes.small_scene(10 + s, n=800 * (s + 1), res=16 * (1 + s % 2)) for s in range(3)]
+    empty = scenes.small_scene(99, n=1, res=16, colliders=False)
+    empty.x = np.zeros((0, 3), np.float32)
+    empty.v = np.zeros((0, 3), np.float32)
+    batch.insert(1, empty)
+    announce("batched", len(batch))
+    sim = mpm.Sim(batch)
+    sim.run_schedule(2)
+    assert sim.sync() == mpm.OK
+    for s, sc in enumerate(batch):
+        if sc.n == 0:
+            continue
+        o = orc.Oracle(sc)
+        o.run_schedule(2)
+        x, _, _, _ = sim.get_state(s)
+        assert np.abs(x - o.x).max() <= 1e-3 * sc.dx, s
+    sim.close()
