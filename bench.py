@@ -1,0 +1,208 @@
+"""Throughput of the MLS-MPM substep on one MI355X.
+
+A step is one full substep (re-sort when due, P2G, grid update, G2P with
+the return map) of every scene of the workload; collider poses and
+velocities are handed over every 25 substeps (one control step), as the
+workload prescribes.  Inputs are seeded synthetic scenes already resident in
+HBM when the timed region starts.
+
+Prints ONE JSON line: particle-substeps/s, the HBM roofline fraction of the
+dominant kernel (its average duration measured with HIP events on the
+library's stream over the timed region), and the FP64 CPU oracle timed on a
+bounded sample of the same workload on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic particle bytes per particle-substep touched by each kernel
+# (FP32): P2G reads x, v, A (15 floats); G2P reads x, G (12 floats) and
+# writes x, v, A, G (24 floats).  Grid bytes (16 B per active node and
+# pass) are left out, so `achieved` is a lower bound.
+ALG_BYTES = {"p2g": 60.0, "g2p": 144.0, "grid": 0.0, "sort": 0.0}
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2302_04659_amd", "csrc", "mpm_kernels.hip")
+
+
+def workload(name):
+    from paper_2302_04659_amd import scenes
+    if name == "cfg3":
+        return scenes.cfg3(n_ctrl=64), ("cfg3: 256 independent slabs, 10k-60k particles each (log-uniform, seed 0), "
+                                       "64^3 grid per scene, 1-2 box/capsule pushers on piecewise-linear trajectories, "
+                                       "Hencky + von Mises (E 5e3, nu 0.3, yield 1e3), dt 5e-5")
+    if name == "cfg4":
+        return [scenes.cfg4(n_ctrl=64)], ("cfg4: 1,048,576-particle plasticine heap, 128^3 grid, 3 moving SDF colliders, "
+                                          "dt 2.5e-5, re-sort every 10 substeps")
+    if name == "cfg2":
+        return [scenes.cfg2(n_ctrl=64)], "cfg2: 65,536-particle slab pushed by a box, 64^3 grid, dt 5e-5"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def kernel_traffic(kernel, wl):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{wl}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    src_hash = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != src_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(scene_list, n_scenes, substeps):
+    import oracle
+    oracle.build(force=False)
+    sample = scene_list[:n_scenes]
+    orcs = [oracle.Oracle(sc) for sc in sample]
+    for o, sc in zip(orcs, sample):
+        if sc.n_colliders:
+            o.set_colliders(sc.ctrl_poses[0], sc.ctrl_vels[0])
+    t0 = time.perf_counter()
+    for o in orcs:
+        o.step(substeps)
+    dt = time.perf_counter() - t0
+    n = sum(sc.n for sc in sample)
+    return {"value": n * substeps / dt, "unit": "particle-substeps/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{n_scenes} scenes of the workload ({n} particles) x {substeps} substeps, FP64, "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=25)
+    ap.add_argument("--workload", default="cfg3")
+    ap.add_argument("--block", type=int, default=0, help="grid block edge (0 = library default / autotuned)")
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--sort-every", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--graph", type=int, default=-1)
+    ap.add_argument("--persistent", type=int, default=-1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-scenes", type=int, default=32)
+    ap.add_argument("--cpu-substeps", type=int, default=25)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(scenes would shard across GPUs with no per-substep exchange).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2302_04659_amd import mpm
+    assert torch.cuda.is_available(), "needs the MI355X"
+    torch.cuda.set_device(0)
+
+    scene_list, desc = workload(args.workload)
+    sim = mpm.Sim(scene_list)
+    N = sim.N
+    if args.workload == "cfg4":
+        sim.set_option(mpm.OPT_SORT_EVERY, 10)
+    if args.block:
+        sim.set_option(mpm.OPT_BLOCK, args.block)
+    if args.chunk:
+        sim.set_option(mpm.OPT_CHUNK, args.chunk)
+    if args.sort_every:
+        sim.set_option(mpm.OPT_SORT_EVERY, args.sort_every)
+    if args.graph >= 0:
+        sim.set_option(mpm.OPT_GRAPH, args.graph)
+    if args.persistent >= 0:
+        sim.set_option(mpm.OPT_PERSISTENT, args.persistent)
+    tune = None
+    if args.autotune:
+        tune = sim.autotune(10)
+
+    ctrl = [0]
+
+    def run(n):
+        # hand over poses / velocities at every control-step boundary
+        done = 0
+        while done < n:
+            k = min(25 - run.phase, n - done)
+            if run.phase == 0:
+                sim.set_colliders_ctrl(ctrl[0] % scene_list[0].n_ctrl if scene_list[0].n_ctrl else 0)
+                ctrl[0] += 1
+            sim.step(k)
+            done += k
+            run.phase = (run.phase + k) % 25
+    run.phase = 0
+
+    run(args.warmup)
+    st = sim.sync()
+    use_graph = sim.get_option(mpm.OPT_GRAPH) == 1
+    # Timed region.  Per-kernel HIP events (library stream) bracket every
+    # launch of the region; with graph replay they cannot, so the kernels are
+    # then timed over a second region of the same length right after it.
+    sim.set_option(mpm.OPT_TIMING, 0 if use_graph else 1)
+    sim.timing(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = sim.sync()
+    if use_graph:
+        sim.set_option(mpm.OPT_TIMING, 1)
+        sim.timing(reset=True)
+        run(args.steps)
+        sim.sync()
+    kt = sim.timing(reset=True)
+    sim.set_option(mpm.OPT_TIMING, 0)
+    if st < 0:
+        raise SystemExit(f"simulation reported status {st}")
+
+    value = N * args.steps / elapsed
+    dom = max(("p2g", "g2p", "grid", "sort"), key=lambda k: kt[k][0])
+    dom_ms = kt[dom][0] / max(kt[dom][1], 1)
+    bytes_launch = ALG_BYTES[dom] * N
+    achieved = bytes_launch / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
+    out = {
+        "metric": "MPM particle-substeps/s at 1 GPU",
+        "value": value,
+        "unit": "particle-substeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "scenes": len(scene_list), "particles": N,
+                   "block": sim.get_option(mpm.OPT_BLOCK), "chunk": sim.get_option(mpm.OPT_CHUNK),
+                   "sort_every": sim.get_option(mpm.OPT_SORT_EVERY),
+                   "graph": sim.get_option(mpm.OPT_GRAPH), "persistent": sim.get_option(mpm.OPT_PERSISTENT)},
+        "kernels_ms_per_launch": {k: round(v[0] / max(v[1], 1), 5) for k, v in kt.items()},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": kernel_traffic(dom, args.workload)},
+        "path_roofline": {"alg_bytes_per_particle_substep": 200.0, "peak_particle_substeps_per_s": 4.0e10,
+                          "frac": value / 4.0e10},
+    }
+    if tune:
+        out["autotune"] = tune
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(scene_list, min(args.cpu_scenes, len(scene_list)), args.cpu_substeps)
+    print(json.dumps(out), flush=True)
+    sim.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -152,7 +152,7 @@ mpm_status mpm_get_grid(mpm_ctx ctx, int scene, float *m, float *p, int on_devic
 typedef enum {
     MPM_OPT_SORT_EVERY = 0,     /* substeps between particle re-sorts (>= 1), default 25 */
     MPM_OPT_BLOCK = 1,          /* grid block edge for binning: 4 or 8, default 4 */
-    MPM_OPT_CHUNK = 2,          /* max particles per work item: 64 .. 4096, default 1024 */
+    MPM_OPT_CHUNK = 2,          /* max particles per work item: 64 .. 8192, default 2048 */
     MPM_OPT_PERSISTENT = 3,     /* 1: one persistent launch per substep; 0: three launches */
     MPM_OPT_GRAPH = 4,          /* 1: replay a captured hipGraph for 25-substep blocks */
     MPM_OPT_CAPTURE_GRID = 5,   /* 1: keep the last P2G grid for mpm_get_grid (slow, debug) */
@@ -160,7 +160,9 @@ typedef enum {
 } mpm_option;
 
 /* Kernel classes reported by mpm_get_timing. */
-typedef enum { MPM_K_SORT = 0, MPM_K_P2G = 1, MPM_K_GRID = 2, MPM_K_G2P = 3, MPM_KCLASSES = 4 } mpm_kernel_class;
+typedef enum {
+    MPM_K_SORT = 0, MPM_K_P2G = 1, MPM_K_GRID = 2, MPM_K_G2P = 3, MPM_K_PERSISTENT = 4, MPM_KCLASSES = 5
+} mpm_kernel_class;
 
 mpm_status mpm_set_option(mpm_ctx ctx, int option, int value);
 mpm_status mpm_get_option(mpm_ctx ctx, int option, int *value);

@@ -28,14 +28,22 @@ namespace {
 constexpr int STAGE_RING = 4;
 
 struct GraphKey {
-    int parity, sort_first, n;
+    int parity, since_sort, sort_every;
     bool operator<(const GraphKey &o) const
     {
         if (parity != o.parity) return parity < o.parity;
-        if (sort_first != o.sort_first) return sort_first < o.sort_first;
-        return n < o.n;
+        if (since_sort != o.since_sort) return since_sort < o.since_sort;
+        return sort_every < o.sort_every;
     }
 };
+
+// A captured 25-substep control step and the context state it leaves.
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    int end_parity = 0, end_since_sort = 0;
+};
+
+constexpr int GRAPH_BLOCK = 25;
 
 }  // namespace
 
@@ -66,7 +74,7 @@ struct mpm_ctx_s {
     int *d_col_scene = nullptr;
 
     // sort and work lists
-    int B = 4, CH = 1024, sort_every = 25, since_sort = 1 << 30;
+    int B = 4, CH = 2048, sort_every = 25, since_sort = 1 << 30;
     int T = 0, T_cap = 0;
     int *d_scene_bin_off = nullptr;
     unsigned *d_keys = nullptr;
@@ -85,7 +93,7 @@ struct mpm_ctx_s {
     long long cap_nodes = 0;
 
     int persistent = 0, graph = 0;
-    std::map<GraphKey, hipGraphExec_t> graphs;
+    std::map<GraphKey, GraphEntry> graphs;
 
     // per-kernel-class timing with HIP events on the context stream
     int timing = 0;
@@ -197,6 +205,12 @@ SceneDev make_scene(const mpm_scene_desc &d, int p_begin, int col_off, int B)
     return S;
 }
 
+void clear_graphs(mpm_ctx ctx)
+{
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second.exec);
+    ctx->graphs.clear();
+}
+
 mpm_status set_block(mpm_ctx ctx, int B)
 {
     // (Re)build the per-scene grid offsets and bin tables for block edge B.
@@ -227,8 +241,7 @@ mpm_status set_block(mpm_ctx ctx, int B)
     HIPCHK(launch_clear_f(ctx->d_grid, 7 * ctx->n_nodes, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->since_sort = 1 << 30;
-    for (auto &g : ctx->graphs) hipGraphExecDestroy(g.second);
-    ctx->graphs.clear();
+    clear_graphs(ctx);
     return MPM_OK;
 }
 
@@ -346,8 +359,8 @@ mpm_status do_sort(mpm_ctx ctx)
 
 int substep_wgs(mpm_ctx ctx) { return ctx->cus * 8; }
 
-// Queue n substeps (the collider advance at the end included).
-mpm_status queue_substeps(mpm_ctx ctx, int n)
+// Queue n substeps (sort when due, P2G, grid, G2P) and the collider advance.
+mpm_status queue_plain(mpm_ctx ctx, int n)
 {
     for (int i = 0; i < n; i++) {
         if (ctx->since_sort >= ctx->sort_every) {
@@ -356,6 +369,12 @@ mpm_status queue_substeps(mpm_ctx ctx, int n)
         }
         if (ctx->capture) HIPCHK(launch_clear_f(ctx->d_cap, 4 * ctx->cap_nodes, ctx->stream));
         StepArgs a = step_args(ctx, i);
+        if (ctx->persistent) {
+            KTimer kt(ctx, MPM_K_PERSISTENT);
+            HIPCHK(launch_persistent(a, ctx->CH, ctx->cus * 4, ctx->stream));
+            ctx->since_sort++;
+            continue;
+        }
         {
             KTimer kt(ctx, MPM_K_P2G);
             HIPCHK(launch_p2g(a, ctx->CH, substep_wgs(ctx), ctx->stream));
@@ -373,6 +392,57 @@ mpm_status queue_substeps(mpm_ctx ctx, int n)
     HIPCHK(launch_collider_advance(ctx->d_cols, (int)ctx->h_cols.size(), ctx->d_col_scene, ctx->d_scenes, n,
                                    ctx->stream));
     return MPM_OK;
+}
+
+// One control step of GRAPH_BLOCK substeps replayed from a captured hipGraph
+// (captured on first use for the current buffer parity and sort phase).
+mpm_status queue_graph_block(mpm_ctx ctx)
+{
+    GraphKey key{ctx->cur, std::min(ctx->since_sort, ctx->sort_every), ctx->sort_every};
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        const int cur0 = ctx->cur, ss0 = ctx->since_sort;
+        ctx->since_sort = key.since_sort;
+        HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        mpm_status st = queue_plain(ctx, GRAPH_BLOCK);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+        if (st != MPM_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            ctx->cur = cur0;
+            ctx->since_sort = ss0;
+            if (st == MPM_OK) HIPCHK(e);
+            return st;
+        }
+        GraphEntry ent;
+        e = hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            ctx->cur = cur0;
+            ctx->since_sort = ss0;
+            HIPCHK(e);
+        }
+        ent.end_parity = ctx->cur;
+        ent.end_since_sort = ctx->since_sort;
+        ctx->cur = cur0;
+        it = ctx->graphs.emplace(key, ent).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second.exec, ctx->stream));
+    ctx->cur = it->second.end_parity;
+    ctx->since_sort = it->second.end_since_sort;
+    return MPM_OK;
+}
+
+mpm_status queue_substeps(mpm_ctx ctx, int n)
+{
+    if (ctx->graph && !ctx->timing && !ctx->capture) {
+        while (n >= GRAPH_BLOCK) {
+            mpm_status st = queue_graph_block(ctx);
+            if (st != MPM_OK) return st;
+            n -= GRAPH_BLOCK;
+        }
+    }
+    return n > 0 ? queue_plain(ctx, n) : MPM_OK;
 }
 
 // Copies between caller memory and a device buffer of the context.
@@ -408,7 +478,7 @@ void release(mpm_ctx ctx)
     if (!ctx) return;
     hipSetDevice(ctx->dev);
     if (ctx->stream) hipStreamSynchronize(ctx->stream);
-    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+    clear_graphs(ctx);
     for (auto &p : ctx->ev_pending) {
         ctx->ev_pool.push_back(p.second.first);
         ctx->ev_pool.push_back(p.second.second);
@@ -417,7 +487,7 @@ void release(mpm_ctx ctx)
     void *bufs[] = {ctx->d_scenes, ctx->d_psc, ctx->d_P[0], ctx->d_P[1], ctx->d_grid, ctx->d_cols, ctx->d_colnow,
                     ctx->d_col_scene, ctx->d_scene_bin_off, ctx->d_keys, ctx->d_count, ctx->d_pstart, ctx->d_perm,
                     ctx->d_tsum, ctx->d_dil, ctx->L.items, ctx->L.gitems, ctx->L.n_items, ctx->L.n_gitems,
-                    ctx->L.scene_item_begin, ctx->L.scene_gitem_begin, ctx->L.bflag, ctx->L.ovf, ctx->L.n_ovf,
+                    ctx->L.scene_item_begin, ctx->L.scene_gitem_begin, ctx->L.bflag, ctx->L.ovf, ctx->L.n_ovf, ctx->L.ibound,
                     ctx->d_flags, ctx->d_queue, ctx->d_scene_done, ctx->d_cap, ctx->d_cap_off, ctx->d_io};
     for (void *p : bufs)
         if (p) hipFree(p);
@@ -487,6 +557,7 @@ mpm_status create_impl(mpm_ctx ctx, const mpm_scene_desc *scenes, int n_scenes)
     HIPCHK(dalloc(&ctx->d_tsum, (T4 + 2047) / 2048 + 1));
     HIPCHK(dalloc(&ctx->d_dil, T4));
     HIPCHK(dalloc(&ctx->L.items, ctx->items_cap));
+    HIPCHK(dalloc(&ctx->L.ibound, ctx->items_cap));
     HIPCHK(dalloc(&ctx->L.gitems, T4));
     HIPCHK(dalloc(&ctx->L.n_items, 1));
     HIPCHK(dalloc(&ctx->L.n_gitems, 1));
@@ -511,6 +582,8 @@ mpm_status create_impl(mpm_ctx ctx, const mpm_scene_desc *scenes, int n_scenes)
     HIPCHK(hipMemsetAsync(ctx->L.n_items, 0, sizeof(int), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->L.n_gitems, 0, sizeof(int), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->d_flags, 0, sizeof(int) * n_scenes, ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->d_queue, 0, sizeof(int) * 4, ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->d_scene_done, 0, sizeof(int) * 3 * n_scenes, ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->d_P[0], 0, sizeof(float) * NCOMP * ctx->pstride, ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->d_P[1], 0, sizeof(float) * NCOMP * ctx->pstride, ctx->stream));
     if (!ctx->h_cols.empty()) {
@@ -684,6 +757,10 @@ mpm_status mpm_sync(mpm_ctx ctx)
         ctx->last_error = "non-finite particle state";
         return MPM_ERR_NONFINITE;
     }
+    if (any & FLAG_SPIN) {
+        ctx->last_error = "persistent substep: a dependency wait timed out";
+        return MPM_ERR_STATE;
+    }
     if (any & FLAG_OVERFLOW_FULL) {
         ctx->last_error = "overflow grid-block list full";
         return MPM_ERR_STATE;
@@ -780,6 +857,7 @@ mpm_status mpm_set_option(mpm_ctx ctx, int option, int value)
     case MPM_OPT_SORT_EVERY:
         ARGCHK(value >= 1, "sort_every must be >= 1");
         ctx->sort_every = value;
+        clear_graphs(ctx);
         return MPM_OK;
     case MPM_OPT_BLOCK: {
         ARGCHK(value == 4 || value == 8, "block must be 4 or 8");
@@ -788,12 +866,21 @@ mpm_status mpm_set_option(mpm_ctx ctx, int option, int value)
         return set_block(ctx, value);
     }
     case MPM_OPT_CHUNK:
-        ARGCHK(value >= 64 && value <= 1024, "chunk must be in [64, 1024]");
+        ARGCHK(value >= 64 && value <= 8192, "chunk must be in [64, 8192]");
         ctx->CH = value;
         ctx->since_sort = 1 << 30;
+        clear_graphs(ctx);
         return MPM_OK;
     case MPM_OPT_PERSISTENT:
         ARGCHK(value == 0 || value == 1, "persistent must be 0 or 1");
+        if (value == 1) {
+            // The one-launch-per-substep kernel (k_substep_persistent) stopped
+            // making progress in one tested configuration (block 8, chunk 512,
+            // re-sort every substep) and the cause is not established; it stays
+            // switched off until it is.
+            ctx->last_error = "persistent substep is disabled";
+            return MPM_ERR_STATE;
+        }
         ctx->persistent = value;
         return MPM_OK;
     case MPM_OPT_GRAPH:
@@ -870,13 +957,125 @@ mpm_status mpm_get_order(mpm_ctx ctx, int *pid_out)
     return MPM_OK;
 }
 
+// Tuning results kept for the life of the process, keyed by device, grid
+// resolutions and particle-count bucket.
+static std::map<std::string, std::vector<int>> g_tune_cache;
+
+static std::string tune_key(mpm_ctx ctx)
+{
+    hipDeviceProp_t prop;
+    std::string k = "dev";
+    if (hipGetDeviceProperties(&prop, ctx->dev) == hipSuccess) k = prop.gcnArchName;
+    int resmask = 0;
+    for (auto &S : ctx->h_scenes) resmask |= S.res;
+    int bucket = 0;
+    while ((1LL << bucket) < (long long)ctx->N) bucket++;
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "|res%d|n2^%d|s%d", resmask, bucket, ctx->n_scenes > 1 ? 1 : 0);
+    return k + buf;
+}
+
 mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_len)
 {
     ARGCHK(ctx, "null context");
-    (void)substeps;
+    ARGCHK(substeps >= 1 && substeps <= 1000, "substeps must be in [1, 1000]");
+    hipSetDevice(ctx->dev);
     if (report && report_len) report[0] = 0;
-    ctx->last_error = "autotune not available";
-    return MPM_ERR_STATE;
+    std::string key = tune_key(ctx);
+    std::string rep;
+    auto hit = g_tune_cache.find(key);
+    std::vector<int> best;
+    if (hit != g_tune_cache.end()) {
+        best = hit->second;
+        rep = "{\"cached\": true";
+    } else {
+        // snapshot the particle state and the collider table
+        const long long N = ctx->N;
+        float *snap = nullptr;
+        ColliderDev *csnap = nullptr;
+        HIPCHK(dalloc(&snap, (size_t)24 * std::max<long long>(N, 1)));
+        HIPCHK(dalloc(&csnap, ctx->h_cols.size()));
+        float *sx = snap, *sv = sx + 3 * N, *sC = sv + 3 * N, *sF = sC + 9 * N;
+        mpm_status st = mpm_get_state(ctx, -1, sx, sv, sC, sF, 1);
+        if (st != MPM_OK) return st;
+        if (!ctx->h_cols.empty())
+            HIPCHK(hipMemcpyAsync(csnap, ctx->d_cols, sizeof(ColliderDev) * ctx->h_cols.size(),
+                                  hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        const int saved[3] = {ctx->B, ctx->CH, ctx->sort_every};
+        const int saved_timing = ctx->timing, saved_graph = ctx->graph;
+        ctx->timing = 0;
+        ctx->graph = 0;
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        const int Bs[2] = {4, 8}, CHs[3] = {512, 2048, 8192}, SEs[3] = {10, 25, 50};
+        float best_ms = 1e30f;
+        rep = "{\"cached\": false, \"trials\": [";
+        bool first = true;
+        for (int B : Bs)
+            for (int CH : CHs)
+                for (int SE : SEs) {
+                    if (B != ctx->B && (st = set_block(ctx, B)) != MPM_OK) return st;
+                    ctx->CH = CH;
+                    ctx->sort_every = SE;
+                    if ((st = mpm_set_state(ctx, -1, sx, sv, sC, sF, 1)) != MPM_OK) return st;
+                    if (!ctx->h_cols.empty())
+                        HIPCHK(hipMemcpyAsync(ctx->d_cols, csnap, sizeof(ColliderDev) * ctx->h_cols.size(),
+                                              hipMemcpyDeviceToDevice, ctx->stream));
+                    // the sort right after set_state is part of every trial; time
+                    // enough substeps that later re-sorts are amortised as in use
+                    int n = std::max(substeps, SE);
+                    HIPCHK(hipEventRecord(e0, ctx->stream));
+                    if ((st = queue_plain(ctx, n)) != MPM_OK) return st;
+                    HIPCHK(hipEventRecord(e1, ctx->stream));
+                    HIPCHK(hipEventSynchronize(e1));
+                    float ms = 0.0f;
+                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                    float per = ms / n;
+                    char buf[160];
+                    std::snprintf(buf, sizeof buf, "%s{\"block\": %d, \"chunk\": %d, \"sort_every\": %d, \"ms_per_substep\": %.5f}",
+                                  first ? "" : ", ", B, CH, SE, per);
+                    rep += buf;
+                    first = false;
+                    if (per < best_ms) {
+                        best_ms = per;
+                        best = {B, CH, SE};
+                    }
+                }
+        rep += "]";
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        // restore the state the caller had
+        if (ctx->B != saved[0] && (st = set_block(ctx, saved[0])) != MPM_OK) return st;
+        ctx->CH = saved[1];
+        ctx->sort_every = saved[2];
+        if ((st = mpm_set_state(ctx, -1, sx, sv, sC, sF, 1)) != MPM_OK) return st;
+        if (!ctx->h_cols.empty())
+            HIPCHK(hipMemcpyAsync(ctx->d_cols, csnap, sizeof(ColliderDev) * ctx->h_cols.size(),
+                                  hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        (void)hipFree(snap);
+        (void)hipFree(csnap);
+        ctx->timing = saved_timing;
+        ctx->graph = saved_graph;
+        g_tune_cache[key] = best;
+    }
+    mpm_status st;
+    if (best[0] != ctx->B && (st = set_block(ctx, best[0])) != MPM_OK) return st;
+    ctx->CH = best[1];
+    ctx->sort_every = best[2];
+    ctx->since_sort = 1 << 30;
+    clear_graphs(ctx);
+    char buf[160];
+    std::snprintf(buf, sizeof buf, ", \"best\": {\"block\": %d, \"chunk\": %d, \"sort_every\": %d}}", best[0],
+                  best[1], best[2]);
+    rep += buf;
+    if (report && report_len) {
+        std::strncpy(report, rep.c_str(), report_len - 1);
+        report[report_len - 1] = 0;
+    }
+    return MPM_OK;
 }
 
 }  // extern "C"

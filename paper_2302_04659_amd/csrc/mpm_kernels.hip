@@ -37,6 +37,18 @@ __device__ __forceinline__ int cvt_rpi(float x)
     return r;
 }
 
+// Particle component c of slot j: base pointer per component (uniform) plus a
+// 32-bit byte offset, so loads and stores use scalar-base addressing.
+__device__ __forceinline__ float pload(const float *P, long long ps, int c, unsigned joff)
+{
+    return *(const float *)((const char *)(P + c * ps) + joff);
+}
+
+__device__ __forceinline__ void pstore(float *P, long long ps, int c, unsigned joff, float v)
+{
+    *(float *)((char *)(P + c * ps) + joff) = v;
+}
+
 __device__ __forceinline__ long long node_index(const SceneDev &S, int B, int i, int j, int k)
 {
     int nb = S.nb;
@@ -77,23 +89,71 @@ __device__ __forceinline__ Material material_of(const SceneDev &S)
     return m;
 }
 
-// ====================================================================== sort
-__global__ __launch_bounds__(WG) void k_keys(SortArgs a)
+// Bound on |m v_c + (A d)_c| over the 27 stencil offsets d (|d_e| <= 1.5 dx).
+__device__ __forceinline__ float scatter_bound(float mass, float dx, const float v[3], const float A[9])
 {
-    int j = blockIdx.x * WG + threadIdx.x;
-    if (j >= a.N) return;
+    float b = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        float row = fabsf(A[3 * c]) + fabsf(A[3 * c + 1]) + fabsf(A[3 * c + 2]);
+        b = fmaxf(b, fmaf(mass, fabsf(v[c]), 1.5f * dx * row));
+    }
+    return b;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// ====================================================================== sort
+// Runs of equal keys in consecutive lanes (the particles are nearly sorted
+// from the previous sort): one atomic per run instead of one per particle.
+struct KeyRun {
+    int head_lane;   // first lane of this lane's run
+    int len;         // run length (valid at the head lane)
+};
+
+__device__ __forceinline__ KeyRun key_run(unsigned key)
+{
+    const int lane = threadIdx.x & 63;
+    const unsigned prev = __shfl_up(key, 1, 64);
+    const bool head = lane == 0 || prev != key;
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    KeyRun r;
+    r.head_lane = 63 - __clzll(heads & upto);
+    const unsigned long long after = heads & ~upto;
+    const int next = after ? __ffsll((long long)after) - 1 : 64;
+    r.len = next - lane;
+    return r;
+}
+
+__device__ __forceinline__ unsigned particle_key(const SortArgs &a, int j)
+{
     int s = a.psc[j];
     const SceneDev &S = a.scenes[s];
     int b[3], cl = 0;
     float f;
     for (int d = 0; d < 3; d++) particle_base(S, a.P[(long long)(X0 + d) * a.pstride + j], b[d], f, cl);
-    unsigned key = (unsigned)a.scene_bin_off[s] + morton3(b[0] / a.B, b[1] / a.B, b[2] / a.B);
-    a.keys[j] = key;
-    atomicAdd(&a.count[key], 1);
+    return (unsigned)a.scene_bin_off[s] + morton3(b[0] / a.B, b[1] / a.B, b[2] / a.B);
 }
 
-// Grid blocks that may receive mass: the 27-neighbourhood of every block
-// holding particles (a P2G tile reaches one block beyond its own).
+__global__ __launch_bounds__(WG) void k_keys(SortArgs a)
+{
+    const int j = blockIdx.x * WG + threadIdx.x;
+    const bool valid = j < a.N;
+    const unsigned key = valid ? particle_key(a, j) : 0xFFFFFFFFu;
+    if (valid) a.keys[j] = key;
+    const KeyRun r = key_run(key);
+    if (valid && r.head_lane == (int)(threadIdx.x & 63)) atomicAdd(&a.count[key], r.len);
+}
+
+// Grid blocks that receive mass from particles at home in their bin: the
+// block itself and its upper neighbours (a stencil spans base .. base + 2).
+// Mass a drifted particle puts one block lower is queued on the overflow
+// list by P2G itself.
 __global__ __launch_bounds__(WG) void k_dilate(SortArgs a)
 {
     int b = blockIdx.x * WG + threadIdx.x;
@@ -104,9 +164,9 @@ __global__ __launch_bounds__(WG) void k_dilate(SortArgs a)
     uint32_t m = (uint32_t)(b - off);
     int bx = compact3(m), by = compact3(m >> 1), bz = compact3(m >> 2);
     int nb = S.nb, hit = 0;
-    for (int dx = -1; dx <= 1; dx++)
-        for (int dy = -1; dy <= 1; dy++)
-            for (int dz = -1; dz <= 1; dz++) {
+    for (int dx = -1; dx <= 0; dx++)
+        for (int dy = -1; dy <= 0; dy++)
+            for (int dz = -1; dz <= 0; dz++) {
                 int x = bx + dx, y = by + dy, z = bz + dz;
                 if (x < 0 || y < 0 || z < 0 || x >= nb || y >= nb || z >= nb) continue;
                 hit |= a.count[off + morton3(x, y, z)] > 0;
@@ -225,11 +285,17 @@ __global__ __launch_bounds__(WG) void k_scan_emit(SortArgs a)
 
 __global__ __launch_bounds__(WG) void k_scatter(SortArgs a)
 {
-    int j = blockIdx.x * WG + threadIdx.x;
-    if (j >= a.N) return;
-    unsigned key = a.keys[j];
-    int c = atomicSub(&a.count[key], 1);
-    a.perm[a.pstart[key] + c - 1] = j;
+    const int j = blockIdx.x * WG + threadIdx.x;
+    const bool valid = j < a.N;
+    const unsigned key = valid ? a.keys[j] : 0xFFFFFFFFu;
+    const KeyRun r = key_run(key);
+    const int lane = threadIdx.x & 63;
+    int old = 0;
+    if (valid && r.head_lane == lane) old = atomicSub(&a.count[key], r.len);
+    old = __shfl(old, r.head_lane, 64);
+    // the run takes the slots [start + old - len, start + old) in lane order
+    const int len = __shfl(r.len, r.head_lane, 64);
+    if (valid) a.perm[a.pstart[key] + old - len + (lane - r.head_lane)] = j;
 }
 
 __global__ __launch_bounds__(WG) void k_gather(SortArgs a)
@@ -239,6 +305,31 @@ __global__ __launch_bounds__(WG) void k_gather(SortArgs a)
     int j = a.perm[p];
 #pragma unroll
     for (int c = 0; c < NCOMP; c++) a.Pn[(long long)c * a.pstride + p] = a.P[(long long)c * a.pstride + j];
+}
+
+// Scale bound of every new work item (the P2G fixed-point scale), from the
+// freshly gathered particles.
+__global__ __launch_bounds__(WG) void k_item_bounds(SortArgs a)
+{
+    __shared__ float red[WG / 64];
+    const int n_items = *a.L.n_items;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const Item item = a.L.items[it];
+        const SceneDev &S = a.scenes[item.scene];
+        float b = 0.0f;
+        for (int li = threadIdx.x; li < item.count; li += WG) {
+            const long long j = item.start + li;
+            float v[3], A[9];
+            for (int d = 0; d < 3; d++) v[d] = a.Pn[(V0 + d) * a.pstride + j];
+            for (int e = 0; e < 9; e++) A[e] = a.Pn[(A00 + e) * a.pstride + j];
+            b = fmaxf(b, scatter_bound(S.mass, S.dx, v, A));
+        }
+        b = wave_max(b);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
+        __syncthreads();
+        if (threadIdx.x == 0) a.L.ibound[it] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        __syncthreads();
+    }
 }
 
 hipError_t launch_sort(const SortArgs &a, hipStream_t st)
@@ -253,22 +344,36 @@ hipError_t launch_sort(const SortArgs &a, hipStream_t st)
     if (a.N > 0) {
         k_scatter<<<gN, WG, 0, st>>>(a);
         k_gather<<<gN, WG, 0, st>>>(a);
+        k_item_bounds<<<2048, WG, 0, st>>>(a);
     }
     return hipGetLastError();
 }
 
 // ====================================================================== substep pieces
-__device__ __forceinline__ void load_particle_xvA(const StepArgs &a, int j, float x[3], float v[3], float A[9])
+__device__ __forceinline__ void load_particle_xvA(const StepArgs &a, int jj, float x[3], float v[3], float A[9])
 {
     const float *P = a.P;
-    long long ps = a.pstride;
+    const long long ps = a.pstride;
+    const unsigned jo = (unsigned)jj << 2;
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        x[d] = P[(X0 + d) * ps + j];
-        v[d] = P[(V0 + d) * ps + j];
+        x[d] = pload(P, ps, X0 + d, jo);
+        v[d] = pload(P, ps, V0 + d, jo);
     }
 #pragma unroll
-    for (int e = 0; e < 9; e++) A[e] = P[(A00 + e) * ps + j];
+    for (int e = 0; e < 9; e++) A[e] = pload(P, ps, A00 + e, jo);
+}
+
+// Put a grid block that is not on the static update list on the overflow
+// list (once per substep).
+__device__ __forceinline__ void queue_block(const StepArgs &a, int s, const SceneDev &S, int lb)
+{
+    int *fl = a.L.bflag + S.bin_off + lb;
+    if (*fl == 0 && atomicCAS(fl, 0, 1) == 0) {
+        int pos = atomicAdd(a.L.n_ovf, 1);
+        if (pos < a.L.ovf_cap) a.L.ovf[pos] = make_int2(s, lb);
+        else atomicOr(a.flags + s, (int)FLAG_OVERFLOW_FULL);
+    }
 }
 
 // Slow path of P2G: scatter one particle straight into the global grid and
@@ -295,20 +400,8 @@ __device__ void p2g_global(const StepArgs &a, int s, const SceneDev &S, const fl
             for (int cz = 0; cz < 2; cz++) {
                 int bx = (b[0] + 2 * cx) / B, by = (b[1] + 2 * cy) / B, bz = (b[2] + 2 * cz) / B;
                 if ((cx && bx == b[0] / B) || (cy && by == b[1] / B) || (cz && bz == b[2] / B)) continue;
-                int lb = (bx * S.nb + by) * S.nb + bz;
-                int *fl = a.L.bflag + S.bin_off + lb;
-                if (*fl == 0 && atomicCAS(fl, 0, 1) == 0) {
-                    int pos = atomicAdd(a.L.n_ovf, 1);
-                    if (pos < a.L.ovf_cap) a.L.ovf[pos] = make_int2(s, lb);
-                    else atomicOr(a.flags + s, (int)FLAG_OVERFLOW_FULL);
-                }
+                queue_block(a, s, S, (bx * S.nb + by) * S.nb + bz);
             }
-}
-
-__device__ __forceinline__ float wave_max(float v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
 }
 
 // Collider poses of scene s at substep k, written once per substep.
@@ -322,8 +415,8 @@ __device__ void write_colliders_now(const StepArgs &a, const SceneDev &S)
     }
 }
 
-template <int B, int PPT>
-__device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile, float *sred)
+template <int B>
+__device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
 {
     constexpr int T = B + 4, T3 = T * T * T;
     const int t = threadIdx.x;
@@ -334,43 +427,11 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile,
     const int org[3] = {bx * B - 1, by * B - 1, bz * B - 1};
 
     for (int n = t; n < 4 * T3; n += WG) tile[n] = 0;
-
-    float xs[PPT][3], vs[PPT][3], As[PPT][9];
-    int bs[PPT][3], mode[PPT];   // mode: 0 none, 1 tile, 2 global
-    float fs[PPT][3];
-    float bmax = 0.0f;
-#pragma unroll
-    for (int r = 0; r < PPT; r++) {
-        int li = r * WG + t;
-        mode[r] = 0;
-        if (li < item.count) {
-            int j = item.start + li;
-            load_particle_xvA(a, j, xs[r], vs[r], As[r]);
-            int cl = 0, in = 1;
-#pragma unroll
-            for (int d = 0; d < 3; d++) {
-                particle_base(S, xs[r][d], bs[r][d], fs[r][d], cl);
-                int tb = bs[r][d] - org[d];
-                in &= (tb >= 0) & (tb <= B + 1);
-            }
-            if (cl) atomicOr(a.flags + s, (int)FLAG_CLAMPED);
-            mode[r] = (in && !cl) ? 1 : 2;
-            if (mode[r] == 1) {
-                float bnd = 0.0f;
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    float row = fabsf(As[r][3 * c]) + fabsf(As[r][3 * c + 1]) + fabsf(As[r][3 * c + 2]);
-                    bnd = fmaxf(bnd, S.mass * fabsf(vs[r][c]) + 1.5f * S.dx * row);
-                }
-                bmax = fmaxf(bmax, bnd);
-            }
-        }
-    }
-    bmax = wave_max(bmax);
-    if ((t & 63) == 0) sred[t >> 6] = bmax;
+    // bound of this item's particles, left by the previous G2P (or the sort)
+    const float bmax = a.L.ibound[it];
     if (it == a.L.scene_item_begin[s]) write_colliders_now(a, S);
     __syncthreads();
-    bmax = fmaxf(fmaxf(sred[0], sred[1]), fmaxf(sred[2], sred[3]));
+    if (t == 0) a.L.ibound[it] = 0.0f;     // this substep's G2P accumulates the next bound
 
     // Power-of-two fixed-point scales keeping every node sum below 2^30:
     // |contribution| <= w * bound, w <= 0.421875, at most item.count particles.
@@ -381,47 +442,59 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile,
     ep = min(max(ep, -120), 120);
     const float Sm = ldexpf(1.0f, em), Sp = ldexpf(1.0f, ep);
     const float kk = Sp / (Sm * S.mass);       // momentum scale relative to the mass-scaled weight
+    const float msc = Sm * S.mass;
 
+    for (int base = 0; base < item.count; base += WG) {
+        const int li = base + t;
+        if (li >= item.count) break;
+        float x[3], v[3], A[9], f[3];
+        int bp[3];
+        load_particle_xvA(a, item.start + li, x, v, A);
+        int cl = 0, in = 1;
 #pragma unroll
-    for (int r = 0; r < PPT; r++) {
-        if (mode[r] == 1) {
-            float wx[3], wy[3], wz[3];
-            bspline_w(fs[r][0], wx);
-            bspline_w(fs[r][1], wy);
-            bspline_w(fs[r][2], wz);
-            const float msc = Sm * S.mass;
-#pragma unroll
-            for (int o = 0; o < 3; o++) wx[o] *= msc;
-            // r(o) = kk * (m v + A (o - f) dx); increments along each axis
-            float Ad[3][3], r0[3];
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-#pragma unroll
-                for (int e = 0; e < 3; e++) Ad[c][e] = kk * As[r][3 * c + e] * S.dx;
-                r0[c] = kk * S.mass * vs[r][c] - (Ad[c][0] * fs[r][0] + Ad[c][1] * fs[r][1] + Ad[c][2] * fs[r][2]);
-            }
-            int *tb = tile + ((bs[r][0] - org[0]) * T + (bs[r][1] - org[1])) * T + (bs[r][2] - org[2]);
-#pragma unroll
-            for (int ox = 0; ox < 3; ox++)
-#pragma unroll
-                for (int oy = 0; oy < 3; oy++) {
-                    float wxy = wx[ox] * wy[oy];
-                    float rxy[3];
-#pragma unroll
-                    for (int c = 0; c < 3; c++) rxy[c] = r0[c] + (float)ox * Ad[c][0] + (float)oy * Ad[c][1];
-#pragma unroll
-                    for (int oz = 0; oz < 3; oz++) {
-                        float w = wxy * wz[oz];
-                        int o = (ox * T + oy) * T + oz;
-                        atomicAdd(tb + o, cvt_rpi(w));
-#pragma unroll
-                        for (int c = 0; c < 3; c++)
-                            atomicAdd(tb + (c + 1) * T3 + o, cvt_rpi(w * (rxy[c] + (float)oz * Ad[c][2])));
-                    }
-                }
-        } else if (mode[r] == 2) {
-            p2g_global(a, s, S, xs[r], vs[r], As[r], bs[r], fs[r]);
+        for (int d = 0; d < 3; d++) {
+            particle_base(S, x[d], bp[d], f[d], cl);
+            int tb = bp[d] - org[d];
+            in &= (tb >= 0) & (tb <= B + 1);
         }
+        if (cl) atomicOr(a.flags + s, (int)FLAG_CLAMPED);
+        if (!in || cl) {
+            p2g_global(a, s, S, x, v, A, bp, f);
+            continue;
+        }
+        float wx[3], wy[3], wz[3];
+        bspline_w(f[0], wx);
+        bspline_w(f[1], wy);
+        bspline_w(f[2], wz);
+#pragma unroll
+        for (int o = 0; o < 3; o++) wx[o] *= msc;
+        // r(o) = kk * (m v + A (o - f) dx); increments along each axis
+        float Ad[3][3], r0[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+#pragma unroll
+            for (int e = 0; e < 3; e++) Ad[c][e] = kk * A[3 * c + e] * S.dx;
+            r0[c] = kk * S.mass * v[c] - (Ad[c][0] * f[0] + Ad[c][1] * f[1] + Ad[c][2] * f[2]);
+        }
+        int *tb = tile + ((bp[0] - org[0]) * T + (bp[1] - org[1])) * T + (bp[2] - org[2]);
+#pragma unroll
+        for (int ox = 0; ox < 3; ox++)
+#pragma unroll
+            for (int oy = 0; oy < 3; oy++) {
+                float wxy = wx[ox] * wy[oy];
+                float rxy[3];
+#pragma unroll
+                for (int c = 0; c < 3; c++) rxy[c] = r0[c] + (float)ox * Ad[c][0] + (float)oy * Ad[c][1];
+#pragma unroll
+                for (int oz = 0; oz < 3; oz++) {
+                    float w = wxy * wz[oz];
+                    int o = (ox * T + oy) * T + oz;
+                    atomicAdd(tb + o, cvt_rpi(w));
+#pragma unroll
+                    for (int c = 0; c < 3; c++)
+                        atomicAdd(tb + (c + 1) * T3 + o, cvt_rpi(w * (rxy[c] + (float)oz * Ad[c][2])));
+                }
+            }
     }
     __syncthreads();
     const float im = 1.0f / Sm, ip = 1.0f / Sp;
@@ -431,6 +504,8 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile,
         int tx = n / (T * T), ty = (n / T) % T, tz = n % T;
         int gi = org[0] + tx, gj = org[1] + ty, gk = org[2] + tz;
         if (gi < 0 || gj < 0 || gk < 0 || gi >= S.res || gj >= S.res || gk >= S.res) continue;
+        if (tx == 0 || ty == 0 || tz == 0)   // node of a lower neighbour block: make sure it is updated
+            queue_block(a, s, S, ((gi / B) * S.nb + (gj / B)) * S.nb + (gk / B));
         long long idx = node_index(S, B, gi, gj, gk);
         atomicAdd(a.gm + idx, (float)m0 * im);
         atomicAdd(a.gpx + idx, (float)p0 * ip);
@@ -440,16 +515,15 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile,
     __syncthreads();
 }
 
-template <int B, int PPT>
+template <int B>
 __global__ __launch_bounds__(WG) void k_p2g(StepArgs a)
 {
     constexpr int T = B + 4, T3 = T * T * T;
     __shared__ int tile[4 * T3];
-    __shared__ float sred[4];
     const int n_items = *a.L.n_items;
     for (int it = xcd_remap(blockIdx.x, gridDim.x); it < n_items; it += gridDim.x) {
         Item item = a.L.items[it];
-        p2g_item<B, PPT>(a, it, item, tile, sred);
+        p2g_item<B>(a, it, item, tile);
     }
 }
 
@@ -513,7 +587,7 @@ __global__ __launch_bounds__(WG) void k_grid(StepArgs a)
 
 // ---------------------------------------------------------------- G2P + integration
 template <int B>
-__device__ void g2p_item(const StepArgs &a, const Item &item, float *vt)
+__device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt)
 {
     constexpr int T = B + 4, T3 = T * T * T;
     const int t = threadIdx.x;
@@ -537,17 +611,16 @@ __device__ void g2p_item(const StepArgs &a, const Item &item, float *vt)
     }
     __syncthreads();
     const Material mat = material_of(S);
-    const float *P = a.P;
-    float *Pw = a.P;
     const long long ps = a.pstride;
     int bad_any = 0, cl_any = 0;
+    float bnd = 0.0f;
     for (int li = t; li < item.count; li += WG) {
-        const int j = item.start + li;
+        const unsigned jo = (unsigned)(item.start + li) << 2;
         float x[3], G[9];
 #pragma unroll
-        for (int d = 0; d < 3; d++) x[d] = P[(X0 + d) * ps + j];
+        for (int d = 0; d < 3; d++) x[d] = pload(a.P, ps, X0 + d, jo);
 #pragma unroll
-        for (int e = 0; e < 9; e++) G[e] = P[(G00 + e) * ps + j];
+        for (int e = 0; e < 9; e++) G[e] = pload(a.P, ps, G00 + e, jo);
         int b[3], cl = 0, in = 1;
         float f[3];
 #pragma unroll
@@ -564,26 +637,35 @@ __device__ void g2p_item(const StepArgs &a, const Item &item, float *vt)
         float vp[3] = {0.0f, 0.0f, 0.0f};
         float So[3][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};   // sum w v_c o_e
         if (in) {
+            // separable gather: reduce over z, then y, then x
             const float *vb = vt + ((b[0] - org[0]) * T + (b[1] - org[1])) * T + (b[2] - org[2]);
+            const float wz2 = 2.0f * wz[2], wy2 = 2.0f * wy[2], wx2 = 2.0f * wx[2];
 #pragma unroll
-            for (int ox = 0; ox < 3; ox++)
+            for (int ox = 0; ox < 3; ox++) {
+                float A[3] = {0.0f, 0.0f, 0.0f}, By[3] = {0.0f, 0.0f, 0.0f}, Bz[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int oy = 0; oy < 3; oy++) {
-                    float wxy = wx[ox] * wy[oy];
+                    const int o = (ox * T + oy) * T;
 #pragma unroll
-                    for (int oz = 0; oz < 3; oz++) {
-                        float w = wxy * wz[oz];
-                        int o = (ox * T + oy) * T + oz;
-                        float tv[3] = {w * vb[o], w * vb[T3 + o], w * vb[2 * T3 + o]};
-#pragma unroll
-                        for (int c = 0; c < 3; c++) {
-                            vp[c] += tv[c];
-                            if (ox) So[c][0] += (float)ox * tv[c];
-                            if (oy) So[c][1] += (float)oy * tv[c];
-                            if (oz) So[c][2] += (float)oz * tv[c];
-                        }
+                    for (int c = 0; c < 3; c++) {
+                        const float v0 = vb[c * T3 + o], v1 = vb[c * T3 + o + 1], v2 = vb[c * T3 + o + 2];
+                        const float az = fmaf(wz[0], v0, fmaf(wz[1], v1, wz[2] * v2));
+                        const float bzv = fmaf(wz[1], v1, wz2 * v2);
+                        A[c] = fmaf(wy[oy], az, A[c]);
+                        if (oy == 1) By[c] = fmaf(wy[1], az, By[c]);
+                        if (oy == 2) By[c] = fmaf(wy2, az, By[c]);
+                        Bz[c] = fmaf(wy[oy], bzv, Bz[c]);
                     }
                 }
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    vp[c] = fmaf(wx[ox], A[c], vp[c]);
+                    if (ox == 1) So[c][0] = fmaf(wx[1], A[c], So[c][0]);
+                    if (ox == 2) So[c][0] = fmaf(wx2, A[c], So[c][0]);
+                    So[c][1] = fmaf(wx[ox], By[c], So[c][1]);
+                    So[c][2] = fmaf(wx[ox], Bz[c], So[c][2]);
+                }
+            }
         } else {
             for (int ox = 0; ox < 3; ox++)
                 for (int oy = 0; oy < 3; oy++)
@@ -605,7 +687,7 @@ __device__ void g2p_item(const StepArgs &a, const Item &item, float *vt)
 #pragma unroll
         for (int c = 0; c < 3; c++)
 #pragma unroll
-            for (int e = 0; e < 3; e++) C[3 * c + e] = Dd * (So[c][e] - vp[c] * f[e]);
+            for (int e = 0; e < 3; e++) C[3 * c + e] = Dd * fmaf(-vp[c], f[e], So[c][e]);
 #pragma unroll
         for (int d = 0; d < 3; d++) x[d] = fmaf(S.dt, vp[d], x[d]);
         // F <- (I + dt C) F  ->  G <- G + dt C + dt C G
@@ -632,45 +714,44 @@ __device__ void g2p_item(const StepArgs &a, const Item &item, float *vt)
         bad_any |= bad;
 #pragma unroll
         for (int d = 0; d < 3; d++) {
-            Pw[(X0 + d) * ps + j] = x[d];
-            Pw[(V0 + d) * ps + j] = vp[d];
+            pstore(a.P, ps, X0 + d, jo, x[d]);
+            pstore(a.P, ps, V0 + d, jo, vp[d]);
         }
+        float An[9];
 #pragma unroll
         for (int e = 0; e < 9; e++) {
-            Pw[(A00 + e) * ps + j] = fmaf(S.mass, C[e], -S.kstress * tau[e]);
-            Pw[(G00 + e) * ps + j] = Gn[e];
+            An[e] = fmaf(S.mass, C[e], -S.kstress * tau[e]);
+            pstore(a.P, ps, A00 + e, jo, An[e]);
+            pstore(a.P, ps, G00 + e, jo, Gn[e]);
         }
+        bnd = fmaxf(bnd, scatter_bound(S.mass, S.dx, vp, An));
     }
+    bnd = wave_max(bnd);
+    if ((t & 63) == 0 && bnd > 0.0f) atomicMax((int *)(a.L.ibound + it), __float_as_int(bnd));
     if (bad_any) atomicOr(a.flags + s, (int)FLAG_NONFINITE);
     if (cl_any) atomicOr(a.flags + s, (int)FLAG_CLAMPED);
     __syncthreads();
 }
 
 template <int B>
-__global__ __launch_bounds__(WG) void k_g2p(StepArgs a)
+__global__ __launch_bounds__(WG, 4) void k_g2p(StepArgs a)
 {
     constexpr int T = B + 4, T3 = T * T * T;
     __shared__ float vt[3 * T3];
-    if (blockIdx.x == 0 && threadIdx.x == 0) *a.L.n_ovf = 0;   // grid update has consumed the list
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(a.L.n_ovf, 0);   // grid update has consumed the list
     const int n_items = *a.L.n_items;
     for (int it = xcd_remap(blockIdx.x, gridDim.x); it < n_items; it += gridDim.x) {
         Item item = a.L.items[it];
-        g2p_item<B>(a, item, vt);
+        g2p_item<B>(a, it, item, vt);
     }
 }
 
 hipError_t launch_p2g(const StepArgs &a, int chunk, int n_wg, hipStream_t st)
 {
+    (void)chunk;
     n_wg = (n_wg + 7) & ~7;
-    if (a.B == 4) {
-        if (chunk <= 256) k_p2g<4, 1><<<n_wg, WG, 0, st>>>(a);
-        else if (chunk <= 512) k_p2g<4, 2><<<n_wg, WG, 0, st>>>(a);
-        else k_p2g<4, 4><<<n_wg, WG, 0, st>>>(a);
-    } else {
-        if (chunk <= 256) k_p2g<8, 1><<<n_wg, WG, 0, st>>>(a);
-        else if (chunk <= 512) k_p2g<8, 2><<<n_wg, WG, 0, st>>>(a);
-        else k_p2g<8, 4><<<n_wg, WG, 0, st>>>(a);
-    }
+    if (a.B == 4) k_p2g<4><<<n_wg, WG, 0, st>>>(a);
+    else k_p2g<8><<<n_wg, WG, 0, st>>>(a);
     return hipGetLastError();
 }
 
@@ -687,6 +768,114 @@ hipError_t launch_g2p(const StepArgs &a, int n_wg, hipStream_t st)
     n_wg = (n_wg + 7) & ~7;
     if (a.B == 4) k_g2p<4><<<n_wg, WG, 0, st>>>(a);
     else k_g2p<8><<<n_wg, WG, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- persistent substep
+// One launch per substep over all scenes.  Workgroups pull queue entries in
+// order: all P2G items, then grid blocks (four per entry, one per wave, plus
+// one overflow sweep per scene), then all G2P items.  A grid entry of scene s
+// waits until every P2G item of s has finished, a G2P item of s until every
+// grid entry of s has; per-scene counters replace a device-wide barrier, so
+// a small scene never waits for a big one.  Entries only ever wait for
+// entries dequeued before them, which are held by running workgroups, so the
+// waits always end; a bounded spin guards against a broken invariant (it
+// raises FLAG_SPIN instead of hanging).  The last workgroup to leave resets
+// the counters for the next launch.
+__device__ __forceinline__ void wait_counter(int *ctr, int target, int *flag)
+{
+    for (int i = 0; i < (1 << 22); i++) {
+        if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) {
+            __threadfence();
+            return;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    atomicOr(flag, (int)FLAG_SPIN);
+    __threadfence();
+}
+
+template <int B>
+__global__ __launch_bounds__(WG) void k_substep_persistent(StepArgs a)
+{
+    constexpr int T = B + 4, T3 = T * T * T;
+    __shared__ int smem[4 * T3];
+    __shared__ int s_q;
+    const int n_items = *a.L.n_items;
+    const int n_g = *a.L.n_gitems;
+    const int n_grid = n_g + a.n_scenes;
+    const int n_gq = (n_grid + 3) / 4;
+    const int total = 2 * n_items + n_gq;
+    int *p2g_done = a.scene_done;
+    int *grid_done = a.scene_done + a.n_scenes;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (;;) {
+        if (threadIdx.x == 0) s_q = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int q = s_q;
+        __syncthreads();
+        if (q >= total) break;
+        if (q < n_items) {
+            Item item = a.L.items[q];
+            p2g_item<B>(a, q, item, smem);
+            if (threadIdx.x == 0) {
+                __threadfence();
+                atomicAdd(&p2g_done[item.scene], 1);
+            }
+        } else if (q < n_items + n_gq) {
+            const int g = (q - n_items) * 4 + wv;
+            if (g < n_grid) {
+                int s, lb = -1;
+                if (g < n_g) {
+                    int2 e = a.L.gitems[g];
+                    s = e.x;
+                    lb = e.y;
+                } else {
+                    s = g - n_g;
+                }
+                wait_counter(&p2g_done[s], a.L.scene_item_begin[s + 1] - a.L.scene_item_begin[s], a.flags + s);
+                if (lb >= 0) {
+                    grid_block<B>(a, s, lb, lane);
+                } else {
+                    const int no = min(*a.L.n_ovf, a.L.ovf_cap);
+                    for (int k = 0; k < no; k++) {
+                        int2 e = a.L.ovf[k];
+                        if (e.x != s) continue;
+                        grid_block<B>(a, s, e.y, lane);
+                        if (lane == 0) a.L.bflag[a.scenes[s].bin_off + e.y] = 0;
+                    }
+                }
+                __threadfence();
+                if (lane == 0) atomicAdd(&grid_done[s], 1);
+            }
+        } else {
+            const int qi = q - n_items - n_gq;
+            Item item = a.L.items[qi];
+            const int s = item.scene;
+            if (threadIdx.x == 0)
+                wait_counter(&grid_done[s], a.L.scene_gitem_begin[s + 1] - a.L.scene_gitem_begin[s] + 1, a.flags + s);
+            __syncthreads();
+            g2p_item<B>(a, qi, item, (float *)smem);
+        }
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        int done = atomicAdd(a.queue + 1, 1);
+        if (done == (int)gridDim.x - 1) {
+            a.queue[0] = 0;
+            a.queue[1] = 0;
+            *a.L.n_ovf = 0;
+            for (int s = 0; s < 2 * a.n_scenes; s++) a.scene_done[s] = 0;
+            __threadfence();
+        }
+    }
+}
+
+hipError_t launch_persistent(const StepArgs &a, int chunk, int n_wg, hipStream_t st)
+{
+    (void)chunk;
+    if (a.B == 4) k_substep_persistent<4><<<n_wg, WG, 0, st>>>(a);
+    else k_substep_persistent<8><<<n_wg, WG, 0, st>>>(a);
     return hipGetLastError();
 }
 

@@ -21,8 +21,8 @@ struct StepArgs {
     int *flags;               // per scene
     int substep;              // substep index within the current call
     int B;                    // block edge
-    int *queue;               // persistent mode: [0] item cursor
-    int *scene_done;          // persistent mode: per scene [3] phase counters
+    int *queue;               // persistent mode: [0] queue cursor, [1] workgroups finished
+    int *scene_done;          // persistent mode: [n_scenes] P2G items done, [n_scenes] grid entries done
     int n_wg;                 // persistent mode: number of workgroups launched
 };
 
@@ -52,6 +52,7 @@ hipError_t launch_sort(const SortArgs &a, hipStream_t st);
 hipError_t launch_p2g(const StepArgs &a, int chunk, int n_wg, hipStream_t st);
 hipError_t launch_grid(const StepArgs &a, int n_wg, hipStream_t st);
 hipError_t launch_g2p(const StepArgs &a, int n_wg, hipStream_t st);
+hipError_t launch_persistent(const StepArgs &a, int chunk, int n_wg, hipStream_t st);
 hipError_t launch_collider_advance(ColliderDev *cols, int n_cols, const int *col_scene, const SceneDev *scenes,
                                    int n_substeps, hipStream_t st);
 

@@ -50,6 +50,49 @@ MPM_HD float fsqrt(float x)
 #endif
 }
 
+// ln(1 + x) for x > -1.  |x| <= 1/4: 2 atanh(s), s = x / (2 + x), odd series
+// to s^9 (truncation < 3e-11); otherwise the hardware log2.  Relative error
+// stays at a few ulp near x = 0, where the log strains live.
+MPM_HD float flog1p(float x)
+{
+    if (fabsf(x) <= 0.25f) {
+        float s = x * frcp(2.0f + x);
+        s = fmaf(fmaf(-s, 2.0f + x, x), frcp(2.0f + x), s);   // one Newton correction of the quotient
+        float s2 = s * s;
+        float p = fmaf(s2, 1.0f / 9.0f, 1.0f / 7.0f);
+        p = fmaf(s2, p, 1.0f / 5.0f);
+        p = fmaf(s2, p, 1.0f / 3.0f);
+        p = fmaf(s2, p, 1.0f);
+        return 2.0f * s * p;
+    }
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_logf(1.0f + x) * 0.6931471805599453f;
+#else
+    return logf(1.0f + x);
+#endif
+}
+
+// e^x - 1.  |x| <= 1/4: Taylor series to x^8 (truncation < 1e-11); otherwise
+// the hardware exp2.
+MPM_HD float fexpm1(float x)
+{
+    if (fabsf(x) <= 0.25f) {
+        float p = fmaf(x, 1.0f / 40320.0f, 1.0f / 5040.0f);
+        p = fmaf(x, p, 1.0f / 720.0f);
+        p = fmaf(x, p, 1.0f / 120.0f);
+        p = fmaf(x, p, 1.0f / 24.0f);
+        p = fmaf(x, p, 1.0f / 6.0f);
+        p = fmaf(x, p, 0.5f);
+        p = fmaf(x, p, 1.0f);
+        return x * p;
+    }
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_exp2f(x * 1.4426950408889634f) - 1.0f;
+#else
+    return expf(x) - 1.0f;
+#endif
+}
+
 // ---------------------------------------------------------------- Morton order
 MPM_HD uint32_t spread3(uint32_t x)
 {
@@ -94,12 +137,32 @@ MPM_HD void bspline_w(float f, float w[3])
 #ifndef MPM_JACOBI_SWEEPS
 #define MPM_JACOBI_SWEEPS 4
 #endif
+#ifndef MPM_JACOBI_APPROX
+#define MPM_JACOBI_APPROX 0
+#endif
 struct Sym3 {
     float a00, a11, a22, a01, a02, a12;
 };
 
 MPM_HD void jacobi_rot(float &app, float &aqq, float &apq, float &arp, float &arq, float *V, int p, int q)
 {
+#if MPM_JACOBI_APPROX
+    // Approximate Givens rotation (quaternion half-angle form, one rsqrt):
+    // the half-angle (ch, sh) comes from the 2x2 block, clamped to pi/8 where
+    // the first-order estimate is poor; c = ch^2 - sh^2, s = 2 ch sh.
+    float ch = 2.0f * (app - aqq), sh = apq;
+    const bool use = 5.8284271f * sh * sh < ch * ch;     // tan^2(pi/8) bound, 1/0.1716
+    const float om = frsqrt(fmaf(ch, ch, sh * sh));
+    ch = use ? om * ch : 0.92387953f;
+    sh = use ? om * sh : 0.38268343f;
+    float c = fmaf(ch, ch, -sh * sh), s = 2.0f * ch * sh;
+    // rotation J with J_pp = c, J_pq = -s ... written as the same update as below
+    s = -s;
+    const float a_pp = app, a_qq = aqq, a_pq = apq;
+    app = c * c * a_pp - 2.0f * c * s * a_pq + s * s * a_qq;
+    aqq = s * s * a_pp + 2.0f * c * s * a_pq + c * c * a_qq;
+    apq = (c * c - s * s) * a_pq + c * s * (a_pp - a_qq);
+#else
     float t = 0.0f;
     if (apq != 0.0f) {
         float zeta = (aqq - app) * frcp(2.0f * apq);
@@ -113,6 +176,7 @@ MPM_HD void jacobi_rot(float &app, float &aqq, float &apq, float &arp, float &ar
     app = fmaf(-t, apq, app);
     aqq = fmaf(t, apq, aqq);
     apq = 0.0f;
+#endif
     float rp = arp, rq = arq;
     arp = c * rp - s * rq;
     arq = s * rp + c * rq;
@@ -154,7 +218,7 @@ MPM_HD void tau_neo_hookean(const float *G, float mu, float la, float tau[9], in
 {
     float jm1 = det_minus_one(G);
     bad |= !(jm1 > -1.0f);
-    float lnJ = log1pf(jm1);
+    float lnJ = flog1p(jm1);
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
@@ -225,7 +289,7 @@ MPM_HD int hencky_update(const float *Gt, const Material &mat, float *Gout, floa
         sig2[k] = 1.0f + lam[k];
         sgn[k] = (k == kmin && jm1 < -1.0f) ? -1.0f : 1.0f;
         clamp[k] = (sgn[k] < 0.0f) || !(sig2[k] >= SMIN * SMIN);
-        eps[k] = clamp[k] ? logf(SMIN) : 0.5f * log1pf(lam[k]);
+        eps[k] = clamp[k] ? -13.815510557964274f : 0.5f * flog1p(lam[k]);   // ln(1e-6)
     }
     float tr = eps[0] + eps[1] + eps[2];
     float mean = tr * (1.0f / 3.0f);
@@ -237,13 +301,13 @@ MPM_HD int hencky_update(const float *Gt, const Material &mat, float *Gout, floa
 #pragma unroll
     for (int i = 0; i < 9; i++) Gout[i] = Gt[i];
     if (yielded) {
-        float r = dg / nd;
+        float r = dg * frcp(nd);
         float q[3];
 #pragma unroll
         for (int k = 0; k < 3; k++) {
             en[k] = eps[k] - r * dv[k];
             float sk = sgn[k] * fsqrt(fmaxf(sig2[k], 0.0f));
-            q[k] = clamp[k] ? expf(en[k]) / sk - 1.0f : expm1f(en[k] - eps[k]);
+            q[k] = clamp[k] ? (fexpm1(en[k]) + 1.0f) * frcp(sk) - 1.0f : fexpm1(en[k] - eps[k]);
         }
         // F_new = F (I + Q), Q = V diag(q) V^T  ->  G_new = G + Q + G Q
         float Q[9];
@@ -265,7 +329,7 @@ MPM_HD int hencky_update(const float *Gt, const Material &mat, float *Gout, floa
     float trn = en[0] + en[1] + en[2];
     float dk[3];
 #pragma unroll
-    for (int k = 0; k < 3; k++) dk[k] = (2.0f * mat.mu * en[k] + mat.la * trn) / fmaxf(sig2[k], SMIN * SMIN);
+    for (int k = 0; k < 3; k++) dk[k] = (2.0f * mat.mu * en[k] + mat.la * trn) * frcp(fmaxf(sig2[k], SMIN * SMIN));
     float M[9];
 #pragma unroll
     for (int i = 0; i < 3; i++)

@@ -68,6 +68,7 @@ struct Lists {
     int2 *ovf;                // overflow grid blocks (scene, linear block)
     int *n_ovf;               // [1]
     int ovf_cap;
+    float *ibound;            // per item: max over its particles of m|v_c| + 1.5 dx sum_e |A_ce| (P2G scale)
 };
 
 }  // namespace mpm

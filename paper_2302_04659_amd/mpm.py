@@ -22,8 +22,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "mpm.h")
 OK, WARN_CLAMPED, WARN_FALLBACK = 0, 1, 2
 ERR_ARG, ERR_HIP, ERR_OOM, ERR_NONFINITE, ERR_STATE = -1, -2, -3, -4, -5
 OPT_SORT_EVERY, OPT_BLOCK, OPT_CHUNK, OPT_PERSISTENT, OPT_GRAPH, OPT_CAPTURE_GRID, OPT_TIMING = range(7)
-K_SORT, K_P2G, K_GRID, K_G2P = range(4)
-KERNEL_CLASSES = ("sort", "p2g", "grid", "g2p")
+K_SORT, K_P2G, K_GRID, K_G2P, K_PERSISTENT = range(5)
+KERNEL_CLASSES = ("sort", "p2g", "grid", "g2p", "persistent")
 MAX_COLLIDERS = 4
 
 
@@ -255,8 +255,8 @@ class Sim:
 
     def timing(self, reset: bool = True):
         """{kernel class: (total ms, launches)} from the library's HIP events."""
-        ms = np.zeros(4, np.float64)
-        n = np.zeros(4, np.int64)
+        ms = np.zeros(len(KERNEL_CLASSES), np.float64)
+        n = np.zeros(len(KERNEL_CLASSES), np.int64)
         self._check(self.L.mpm_get_timing(self.h, ms.ctypes.data, n.ctypes.data, int(reset)), "get_timing")
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
 
