@@ -149,17 +149,23 @@ def conv1_backward(x, w, gy):
 
 
 # ---------------------------------------------------------------- network
-def forward(params, x, cin, cout, width=1):
-    """Returns the output and a cache of every layer input / pre-activation."""
+def forward(params, x, cin, cout, width=1, q=None):
+    """Returns the output and a cache of every layer input / pre-activation.
+
+    q (optional) is a rounding function applied where a BF16 implementation
+    stores values: the network input, every weight tensor fed to a
+    convolution and every hidden activation (the head output stays exact).
+    q = None is the exact network."""
+    q_ = q if q is not None else (lambda a: a)
     cache = {}
     skips = {}
-    h = x
+    h = q_(x)
     for name, kind, ci, co, relu in layer_shapes(cin, cout, width):
         if name == "c2a":
             h = np.concatenate([h, skips["e2b"]], axis=-1)
         if name == "c1a":
             h = np.concatenate([h, skips["e1b"]], axis=-1)
-        w, b = params[name + ".w"], params[name + ".b"]
+        w, b = q_(params[name + ".w"]), params[name + ".b"]
         inp = upsample(h) if kind == "up" else h
         cache[name] = inp
         if kind in ("c3", "up"):
@@ -169,35 +175,44 @@ def forward(params, x, cin, cout, width=1):
         else:
             z = conv1(inp, w, b)
         cache[name + ".z"] = z
-        h = np.maximum(z, 0.0) if relu else z
+        h = q_(np.maximum(z, 0.0)) if relu else z
         if name in ("e1b", "e2b"):
             skips[name] = h
     return h, cache
 
 
-def backward(params, cache, gout, cin, cout, width=1):
-    """Gradients of every parameter for the output gradient `gout`."""
+def backward(params, cache, gout, cin, cout, width=1, q=None):
+    """Gradients of every parameter for the output gradient `gout`.
+
+    With q (see forward): every input gradient is rounded where a BF16
+    implementation stores it -- after each convolution adjoint (computed
+    with the rounded weights), after the upsampling adjoint, and where a
+    skip gradient is summed in; the stride-2 adjoint uses the exact weights
+    and is rounded only in that sum.  Parameter gradients stay exact."""
+    q_ = q if q is not None else (lambda a: a)
     grads = {}
     shapes = layer_shapes(cin, cout, width)
     g = gout
     gskip = {}
     for name, kind, ci, co, relu in reversed(shapes):
         if name in gskip:
-            g = g + gskip.pop(name)
+            g = q_(g + gskip.pop(name))
         z = cache[name + ".z"]
         if relu:
             g = g * (z > 0)
         w = params[name + ".w"]
         inp = cache[name]
         if kind in ("c3", "up"):
-            gin, gw, gb = conv3_backward(inp, w, g)
+            gin, gw, gb = conv3_backward(inp, q_(w), g)
+            gin = q_(gin)
         elif kind == "down":
             gin, gw, gb = down_backward(inp, w, g)
         else:
-            gin, gw, gb = conv1_backward(inp, w, g)
+            gin, gw, gb = conv1_backward(inp, q_(w), g)
+            gin = q_(gin)
         grads[name + ".w"], grads[name + ".b"] = gw, gb
         if kind == "up":
-            gin = upsample_backward(gin)
+            gin = q_(upsample_backward(gin))
         if name == "c1a":
             # split the gradient of concat([up1 output, e1b output])
             n_up = [s for s in shapes if s[0] == "u1"][0][3]
