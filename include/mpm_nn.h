@@ -1,0 +1,92 @@
+/*
+ * mpm_nn.h -- C ABI of the grid U-Net surrogate kernels (libmpm_hip.so).
+ *
+ * The paper has no learned component; these kernels serve the surrogate
+ * this library adds in front of the MLS-MPM substep (the network stands in
+ * for a 25-substep control step, App. D.3 gives 25 physics steps per control
+ * step, and the plain MPM stays its fallback).  They are the training and
+ * inference primitives the Python driver composes into the U-Net:
+ * convolution forward / adjoint (BF16 MFMA, FP32 accumulate), weight and
+ * bias gradients, ReLU and resampling backward, masked MSE, Adam.
+ *
+ * Conventions: all pointers are device pointers on the current device;
+ * work is queued on `stream` (a hipStream_t, NULL = default) and the call
+ * returns without waiting.  Activations are BF16 (uint16_t bit patterns),
+ * channels-last [n][d][h][w][c]; a call reads / writes the channel slice
+ * [off, off + count) of a tensor whose channel stride is `c...`.  Channel
+ * counts on the MFMA paths are multiples of 16 (<= 128 input channels for
+ * weight gradients).  Weights are FP32 [taps][cin][cout] (taps = 27, 8 or 1,
+ * z-major, as [kd][kh][kw]).  Every call returns 0 on success, -1 on an
+ * invalid argument (nothing queued), -2 on a HIP error.
+ *
+ * kind: 0 = 3^3 convolution, zero padding 1; 1 = 3^3 convolution of the
+ * nearest x2 upsampled input (output = 2 x input size); 2 = 2^3 stride-2
+ * convolution (output = input / 2); 3 = 1^3 convolution.
+ */
+#ifndef MPM_NN_H
+#define MPM_NN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Pack FP32 weights into the BF16 fragment order of mpm_nn_conv.
+ * transpose = 0: weights of the layer; 1: weights of its adjoint (input
+ * gradient) convolution, taps mirrored and channels swapped.  out holds
+ * taps * ceil16(cin_eff) * ceil16(cout_eff) BF16 values, where (cin_eff,
+ * cout_eff) = (cin, cout), or (cout, cin) when transposed. */
+int mpm_nn_pack(const float *w, int kind, int cin, int cout, int transpose, uint16_t *out, void *stream);
+
+/* y = act(conv(x) + bias): input [n][id][ih][iw] slice (cx, x_off, cin),
+ * output slice (cy, y_off, cout); relu = 1 applies max(0, .); y32 (nullable)
+ * additionally receives FP32 outputs [voxel][cy32]. */
+int mpm_nn_conv(int kind, const uint16_t *x, int n, int id, int ih, int iw, int cx, int x_off, int cin,
+                const uint16_t *wpack, const float *bias, int relu, uint16_t *y, int cy, int y_off, int cout,
+                float *y32, int cy32, void *stream);
+
+/* Weight gradient gw[taps][cin][cout] (+= when accumulate) of the layer that
+ * maps x to an output whose gradient is g; `partial` is scratch of
+ * ceil(voxels / chunk) * taps * cin * cout floats. */
+int mpm_nn_wgrad(int kind, const uint16_t *x, int n, int id, int ih, int iw, int cx, int x_off, int cin,
+                 const uint16_t *g, int cg, int g_off, int cout, long long chunk, float *partial, float *gw,
+                 int accumulate, void *stream);
+
+/* gb[co] (+)= sum over voxels of g[voxel][g_off + co]. */
+int mpm_nn_bias_grad(const uint16_t *g, long long voxels, int cg, int g_off, int cout, float *gb, int accumulate,
+                     void *stream);
+
+/* g *= (y > 0) on a channel slice (ReLU backward from the layer output y). */
+int mpm_nn_relu_bwd(uint16_t *g, int cg, int g_off, const uint16_t *y, int cy, int y_off, long long voxels, int c,
+                    void *stream);
+
+/* coarse[v] = sum of the 8 children of v in `fine` (upsampling backward);
+ * (n, d, h, w) are the coarse sizes. */
+int mpm_nn_up_bwd(const uint16_t *fine, int cf, int f_off, uint16_t *coarse, int cc, int c_off, int n, int d, int h,
+                  int w, int c, void *stream);
+
+/* Input gradient of the 2^3 stride-2 convolution with FP32 weights w
+ * [8][cin][cout]; (n, d, h, wd) are the fine (input) sizes; accumulate = 1
+ * adds to gx (a skip connection's gradient already there). */
+int mpm_nn_down_dgrad(const uint16_t *g, int cg, int g_off, const float *w, int cin, int cout, uint16_t *gx, int cx,
+                      int x_off, int n, int d, int h, int wd, int accumulate, void *stream);
+
+/* FP32 [voxel][cs] (first c channels) -> BF16 slice, zero-padded to c_pad channels. */
+int mpm_nn_to_bf16(const float *x, int cs, long long voxels, int c, uint16_t *y, int cy, int y_off, int c_pad,
+                   void *stream);
+
+/* Masked MSE: loss_parts[nparts] receive partial sums of mask (pred - target)^2
+ * over the first c channels; g [voxel][cg] receives 2 (pred - target) / count
+ * on masked voxels (0 elsewhere), count = sum(mask) * c given as inv_count. */
+int mpm_nn_masked_mse(const float *pred, int cp, const float *target, const float *mask, long long voxels, int c,
+                      float inv_count, uint16_t *g, int cg, float *loss_parts, int nparts, void *stream);
+
+/* One bias-corrected Adam step (t >= 1) on n FP32 parameters. */
+int mpm_nn_adam(float *p, const float *g, float *m, float *v, long long n, float lr, float beta1, float beta2,
+                float eps, int t, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPM_NN_H */

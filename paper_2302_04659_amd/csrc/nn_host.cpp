@@ -1,0 +1,123 @@
+// C ABI of the surrogate kernels (argument checks + launches).
+#include <hip/hip_runtime.h>
+
+#include "../../include/mpm_nn.h"
+#include "nn_kernels.hpp"
+
+namespace {
+
+int taps_of(int kind) { return kind == 0 || kind == 1 ? 27 : (kind == 2 ? 8 : 1); }
+int ceil16(int c) { return (c + 15) / 16 * 16; }
+int st_of(hipError_t e) { return e == hipSuccess ? 0 : -2; }
+bool kind_ok(int k) { return k >= 0 && k <= 3; }
+bool c16(int c) { return c > 0 && c % 16 == 0; }
+
+void out_size(int kind, int id, int ih, int iw, int &od, int &oh, int &ow)
+{
+    if (kind == 1) { od = 2 * id; oh = 2 * ih; ow = 2 * iw; }
+    else if (kind == 2) { od = id / 2; oh = ih / 2; ow = iw / 2; }
+    else { od = id; oh = ih; ow = iw; }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpm_nn_pack(const float *w, int kind, int cin, int cout, int transpose, uint16_t *out, void *stream)
+{
+    if (!w || !out || !kind_ok(kind) || cin <= 0 || cout <= 0) return -1;
+    const int ci_e = transpose ? cout : cin, co_e = transpose ? cin : cout;
+    return st_of(nn::pack(w, taps_of(kind), cin, cout, ceil16(ci_e), ceil16(co_e), transpose, out,
+                          (hipStream_t)stream));
+}
+
+int mpm_nn_conv(int kind, const uint16_t *x, int n, int id, int ih, int iw, int cx, int x_off, int cin,
+                const uint16_t *wpack, const float *bias, int relu, uint16_t *y, int cy, int y_off, int cout,
+                float *y32, int cy32, void *stream)
+{
+    if (!kind_ok(kind) || !x || !wpack || (!y && !y32) || n <= 0 || id <= 0 || ih <= 0 || iw <= 0) return -1;
+    if (!c16(cin) || cout <= 0 || cout > 128 || x_off < 0 || x_off + cin > cx || (x_off % 4) || (cx % 4)) return -1;
+    if (y && (y_off < 0 || y_off + cout > cy)) return -1;
+    if (y32 && cy32 < cout) return -1;
+    if (kind == 2 && (id % 2 || ih % 2 || iw % 2)) return -1;
+    nn::ConvArgs a{};
+    a.kind = kind;
+    a.x = x; a.n = n; a.id = id; a.ih = ih; a.iw = iw; a.cx = cx; a.x_off = x_off; a.cin = cin;
+    a.w = wpack; a.bias = bias; a.relu = relu;
+    a.y = y; a.cy = cy; a.y_off = y_off; a.y32 = y32; a.cy32 = cy32;
+    out_size(kind, id, ih, iw, a.od, a.oh, a.ow);
+    a.cout = cout;
+    if ((cout + 15) / 16 != 1 && (cout + 15) / 16 != 2 && (cout + 15) / 16 != 4 && (cout + 15) / 16 != 8) return -1;
+    return st_of(nn::conv(a, (hipStream_t)stream));
+}
+
+int mpm_nn_wgrad(int kind, const uint16_t *x, int n, int id, int ih, int iw, int cx, int x_off, int cin,
+                 const uint16_t *g, int cg, int g_off, int cout, long long chunk, float *partial, float *gw,
+                 int accumulate, void *stream)
+{
+    if (!kind_ok(kind) || !x || !g || !partial || !gw || n <= 0 || chunk < 16 || chunk % 16) return -1;
+    if (!c16(cin) || cin > 128 || cout <= 0 || cout > 128 || x_off + cin > cx || g_off + cout > cg) return -1;
+    const int nf = (cout + 15) / 16;
+    if (nf != 1 && nf != 2 && nf != 4 && nf != 8) return -1;
+    nn::WgradArgs a{};
+    a.kind = kind;
+    a.x = x; a.n = n; a.id = id; a.ih = ih; a.iw = iw; a.cx = cx; a.x_off = x_off; a.cin = cin;
+    a.g = g; a.cg = cg; a.g_off = g_off; a.cout = cout;
+    out_size(kind, id, ih, iw, a.od, a.oh, a.ow);
+    a.chunk = chunk; a.partial = partial; a.gw = gw; a.accumulate = accumulate;
+    return st_of(nn::wgrad(a, (hipStream_t)stream));
+}
+
+int mpm_nn_bias_grad(const uint16_t *g, long long voxels, int cg, int g_off, int cout, float *gb, int accumulate,
+                     void *stream)
+{
+    if (!g || !gb || voxels <= 0 || cout <= 0 || g_off + cout > cg) return -1;
+    return st_of(nn::bias_grad(g, voxels, cg, g_off, cout, gb, accumulate, (hipStream_t)stream));
+}
+
+int mpm_nn_relu_bwd(uint16_t *g, int cg, int g_off, const uint16_t *y, int cy, int y_off, long long voxels, int c,
+                    void *stream)
+{
+    if (!g || !y || voxels <= 0 || c <= 0 || g_off + c > cg || y_off + c > cy) return -1;
+    return st_of(nn::relu_bwd(g, cg, g_off, y, cy, y_off, voxels, c, (hipStream_t)stream));
+}
+
+int mpm_nn_up_bwd(const uint16_t *fine, int cf, int f_off, uint16_t *coarse, int cc, int c_off, int n, int d, int h,
+                  int w, int c, void *stream)
+{
+    if (!fine || !coarse || n <= 0 || d <= 0 || h <= 0 || w <= 0 || c <= 0 || f_off + c > cf || c_off + c > cc) return -1;
+    return st_of(nn::up_bwd(fine, cf, f_off, coarse, cc, c_off, n, d, h, w, c, (hipStream_t)stream));
+}
+
+int mpm_nn_down_dgrad(const uint16_t *g, int cg, int g_off, const float *w, int cin, int cout, uint16_t *gx, int cx,
+                      int x_off, int n, int d, int h, int wd, int accumulate, void *stream)
+{
+    if (!g || !w || !gx || n <= 0 || d % 2 || h % 2 || wd % 2 || cin <= 0 || cout <= 0) return -1;
+    if (g_off + cout > cg || x_off + cin > cx) return -1;
+    return st_of(nn::down_dgrad(g, cg, g_off, w, cin, cout, gx, cx, x_off, n, d, h, wd, accumulate, (hipStream_t)stream));
+}
+
+int mpm_nn_to_bf16(const float *x, int cs, long long voxels, int c, uint16_t *y, int cy, int y_off, int c_pad,
+                   void *stream)
+{
+    if (!x || !y || voxels <= 0 || c <= 0 || c_pad < c || y_off + c_pad > cy || cs < c) return -1;
+    return st_of(nn::to_bf16(x, cs, voxels, c, y, cy, y_off, c_pad, (hipStream_t)stream));
+}
+
+int mpm_nn_masked_mse(const float *pred, int cp, const float *target, const float *mask, long long voxels, int c,
+                      float inv_count, uint16_t *g, int cg, float *loss_parts, int nparts, void *stream)
+{
+    if (!pred || !target || !mask || !g || !loss_parts || voxels <= 0 || c <= 0 || cp < c || cg < c || nparts <= 0)
+        return -1;
+    return st_of(nn::masked_mse(pred, cp, target, mask, voxels, c, inv_count, g, cg, loss_parts, nparts,
+                                (hipStream_t)stream));
+}
+
+int mpm_nn_adam(float *p, const float *g, float *m, float *v, long long n, float lr, float beta1, float beta2,
+                float eps, int t, void *stream)
+{
+    if (!p || !g || !m || !v || n <= 0 || t < 1) return -1;
+    return st_of(nn::adam(p, g, m, v, n, lr, beta1, beta2, eps, t, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,494 @@
+// BF16-MFMA / FP32-accumulate kernels of the grid U-Net surrogate (gfx950).
+//
+// Activations are BF16, channels-last [N][D][H][W][C]; a kernel reads or
+// writes a channel slice [off, off + cnt) of a tensor with channel stride C,
+// so skip concatenation costs nothing.  Channel counts used by the MFMA
+// paths are multiples of 16.
+//
+// Convolution = implicit GEMM on v_mfma_f32_16x16x16bf16_1k:
+//   forward  D[voxel][co] = sum_{tap, ci} X[p(voxel, tap)][ci] W[tap][ci][co]
+//   dgrad    the same kernel on dY with flipped, transposed weights
+//   wgrad    D[ci][co] += sum_voxel X[p(voxel, tap)][ci] dY[voxel][co]
+// with tap geometries: 3^3 zero-padded ("c3"), 3^3 over a nearest x2
+// upsampled input ("up"), 2^3 stride 2 ("down") and 1^3 ("c1").
+// Operand lane layout (wave64, 16x16x16): A[i][k] sits in lane i + 16 (k/4),
+// element k % 4; B[k][j] in lane j + 16 (k/4), element k % 4; D[i][j] in lane
+// j + 16 (i/4), element i % 4.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nn_kernels.hpp"
+
+namespace nn {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));   // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);                                                                 // nearest even
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ int ksize(int kind) { return kind == KIND_C3 || kind == KIND_UP ? 3 : (kind == KIND_DOWN ? 2 : 1); }
+
+// Input voxel read by output voxel (z, y, x) through tap (a, b, c); false if
+// it lies in the zero padding.  (D, H, W) are the input's spatial sizes.
+__device__ __forceinline__ bool tap_source(int kind, int z, int y, int x, int a, int b, int c, int D, int H, int W,
+                                           int &sz, int &sy, int &sx)
+{
+    if (kind == KIND_C3) {
+        sz = z + a - 1; sy = y + b - 1; sx = x + c - 1;
+        return sz >= 0 && sy >= 0 && sx >= 0 && sz < D && sy < H && sx < W;
+    }
+    if (kind == KIND_UP) {
+        int uz = z + a - 1, uy = y + b - 1, ux = x + c - 1;
+        if (uz < 0 || uy < 0 || ux < 0 || uz >= 2 * D || uy >= 2 * H || ux >= 2 * W) return false;
+        sz = uz >> 1; sy = uy >> 1; sx = ux >> 1;
+        return true;
+    }
+    if (kind == KIND_DOWN) {
+        sz = 2 * z + a; sy = 2 * y + b; sx = 2 * x + c;
+        return true;
+    }
+    sz = z; sy = y; sx = x;
+    return true;
+}
+
+// ---------------------------------------------------------------- convolution (forward / dgrad)
+// One wave computes 64 consecutive output voxels (4 row fragments) x 16 NF
+// output channels.
+template <int NF>
+__global__ __launch_bounds__(256) void k_conv(ConvArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const long long wave = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const long long nvox = (long long)a.n * a.od * a.oh * a.ow;
+    const long long v0 = wave * 64;
+    if (v0 >= nvox) return;
+    const int ks = ksize(a.kind);
+    const int ntap = ks * ks * ks;
+    const int kc = a.cin / 16;
+    f4 acc[4][NF];
+#pragma unroll
+    for (int f = 0; f < 4; f++)
+#pragma unroll
+        for (int n = 0; n < NF; n++) acc[f][n] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    // coordinates of this lane's A rows (one voxel per fragment)
+    int vz[4], vy[4], vx[4], vn[4];
+    bool vok[4];
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+        long long v = v0 + 16 * f + (lane & 15);
+        vok[f] = v < nvox;
+        if (!vok[f]) v = 0;
+        vx[f] = (int)(v % a.ow);
+        long long r = v / a.ow;
+        vy[f] = (int)(r % a.oh);
+        r /= a.oh;
+        vz[f] = (int)(r % a.od);
+        vn[f] = (int)(r / a.od);
+    }
+    const int kq = 4 * (lane >> 4);          // this lane's first K element within a fragment
+    for (int t = 0; t < ntap; t++) {
+        const int ta = t / (ks * ks), tb = (t / ks) % ks, tc = t % ks;
+        long long src[4];
+        bool ok[4];
+#pragma unroll
+        for (int f = 0; f < 4; f++) {
+            int sz, sy, sx;
+            ok[f] = vok[f] && tap_source(a.kind, vz[f], vy[f], vx[f], ta, tb, tc, a.id, a.ih, a.iw, sz, sy, sx);
+            src[f] = ok[f] ? ((((long long)vn[f] * a.id + sz) * a.ih + sy) * a.iw + sx) * a.cx + a.x_off + kq : 0;
+        }
+        const uint16_t *wt = a.w + (size_t)t * kc * NF * 256;
+        for (int c = 0; c < kc; c++) {
+            s4 A[4];
+#pragma unroll
+            for (int f = 0; f < 4; f++) {
+                if (ok[f]) {
+                    const uint2 raw = *(const uint2 *)(a.x + src[f] + 16 * c);
+                    A[f] = s4{(short)(raw.x & 0xffff), (short)(raw.x >> 16), (short)(raw.y & 0xffff), (short)(raw.y >> 16)};
+                } else {
+                    A[f] = s4{0, 0, 0, 0};
+                }
+            }
+#pragma unroll
+            for (int n = 0; n < NF; n++) {
+                const uint2 raw = *(const uint2 *)(wt + ((size_t)c * NF + n) * 256 + 4 * lane);
+                const s4 Bv = s4{(short)(raw.x & 0xffff), (short)(raw.x >> 16), (short)(raw.y & 0xffff), (short)(raw.y >> 16)};
+#pragma unroll
+                for (int f = 0; f < 4; f++) acc[f][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[f], Bv, acc[f][n], 0, 0, 0);
+            }
+        }
+    }
+    // epilogue: D[i][j] -> voxel v0 + 16 f + 4 (lane/16) + r, channel 16 n + lane % 16
+#pragma unroll
+    for (int f = 0; f < 4; f++)
+#pragma unroll
+        for (int n = 0; n < NF; n++) {
+            const int co = 16 * n + (lane & 15);
+            if (co >= a.cout) continue;
+            const float bias = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const long long v = v0 + 16 * f + 4 * (lane >> 4) + r;
+                if (v >= nvox) continue;
+                float val = acc[f][n][r] + bias;
+                if (a.relu) val = fmaxf(val, 0.0f);
+                if (a.y) a.y[v * a.cy + a.y_off + co] = f2bf(val);
+                if (a.y32) a.y32[v * a.cy32 + co] = val;
+            }
+        }
+}
+
+// Pack FP32 master weights W[tap][ci][co] (ci < cin, co < cout) into the
+// B-fragment order the conv kernel reads, as BF16; `transpose` packs the
+// weights of the adjoint (dgrad) convolution: taps mirrored, ci <-> co.
+__global__ void k_pack(const float *w, int ntap, int cin, int cout, int cin_p, int cout_p, int transpose,
+                       uint16_t *out)
+{
+    // output element index = (((t * KC + c) * NF + n) * 64 + lane) * 4 + r
+    const int KC = cin_p / 16, NF = cout_p / 16;
+    const long long total = (long long)ntap * KC * NF * 256;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+        const int r = (int)(e & 3), lane = (int)((e >> 2) & 63);
+        long long q = e >> 8;
+        const int n = (int)(q % NF);
+        q /= NF;
+        const int c = (int)(q % KC);
+        const int t = (int)(q / KC);
+        const int k = 16 * c + 4 * (lane >> 4) + r;     // input channel of this conv
+        const int j = 16 * n + (lane & 15);              // output channel of this conv
+        float v = 0.0f;
+        if (!transpose) {
+            if (k < cin && j < cout) v = w[((long long)t * cin + k) * cout + j];
+        } else {
+            // adjoint: this conv maps cout-channel gradients to cin-channel ones
+            const int tm = ntap - 1 - t;
+            if (k < cout && j < cin) v = w[((long long)tm * cin + j) * cout + k];
+        }
+        out[e] = f2bf(v);
+    }
+}
+
+// ---------------------------------------------------------------- weight gradient
+// Partial dW for one tap and one chunk of output voxels:
+//   P[chunk][tap][ci][co] = sum_{v in chunk} X[p(v, tap)][ci] dY[v][co]
+// Wave w of the workgroup owns input-channel fragments w, w + 4, ...
+template <int NF>
+__global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ks = ksize(a.kind), ntap = ks * ks * ks;
+    const int t = blockIdx.x % ntap;
+    const int chunk = blockIdx.x / ntap;
+    const long long nvox = (long long)a.n * a.od * a.oh * a.ow;
+    const long long vb = (long long)chunk * a.chunk, ve = min(nvox, vb + a.chunk);
+    const int ta = t / (ks * ks), tb = (t / ks) % ks, tc = t % ks;
+    const int KC = a.cin / 16;
+    constexpr int MF = 2;      // input-channel fragments per wave (cin <= 128)
+    f4 acc[MF][NF];
+#pragma unroll
+    for (int m = 0; m < MF; m++)
+#pragma unroll
+        for (int n = 0; n < NF; n++) acc[m][n] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int kq = 4 * (lane >> 4);
+    for (long long v0 = vb; v0 < ve; v0 += 16) {
+        // K = 16 voxels; this lane supplies voxels v0 + kq .. + 3
+        long long src[4], dst[4];
+        bool ok[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            long long v = v0 + kq + r;
+            ok[r] = v < ve;
+            if (!ok[r]) v = vb;
+            int x = (int)(v % a.ow);
+            long long q = v / a.ow;
+            int y = (int)(q % a.oh);
+            q /= a.oh;
+            int z = (int)(q % a.od);
+            int nn = (int)(q / a.od);
+            int sz, sy, sx;
+            ok[r] = ok[r] && tap_source(a.kind, z, y, x, ta, tb, tc, a.id, a.ih, a.iw, sz, sy, sx);
+            src[r] = ((((long long)nn * a.id + sz) * a.ih + sy) * a.iw + sx) * a.cx + a.x_off;
+            dst[r] = v * a.cg + a.g_off;
+            if (!(v0 + kq + r < ve)) dst[r] = -1;
+        }
+        s4 Bv[NF];
+#pragma unroll
+        for (int n = 0; n < NF; n++) {
+            const int co = 16 * n + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                Bv[n][r] = (dst[r] >= 0 && co < a.cout) ? (short)a.g[dst[r] + co] : (short)0;
+        }
+#pragma unroll
+        for (int m = 0; m < MF; m++) {
+            const int cf = wv + 4 * m;
+            if (cf >= KC) continue;
+            const int ci = 16 * cf + (lane & 15);
+            s4 Av;
+#pragma unroll
+            for (int r = 0; r < 4; r++) Av[r] = ok[r] ? (short)a.x[src[r] + ci] : (short)0;
+#pragma unroll
+            for (int n = 0; n < NF; n++) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Av, Bv[n], acc[m][n], 0, 0, 0);
+        }
+    }
+    float *P = a.partial + (((long long)chunk * ntap + t) * a.cin) * a.cout;
+#pragma unroll
+    for (int m = 0; m < MF; m++) {
+        const int cf = wv + 4 * m;
+        if (cf >= KC) continue;
+#pragma unroll
+        for (int n = 0; n < NF; n++) {
+            const int co = 16 * n + (lane & 15);
+            if (co >= a.cout) continue;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int ci = 16 * cf + 4 * (lane >> 4) + r;
+                P[(long long)ci * a.cout + co] = acc[m][n][r];
+            }
+        }
+    }
+}
+
+__global__ void k_reduce_partials(const float *partial, int nchunk, long long per, float *out, int accumulate)
+{
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < per; e += (long long)gridDim.x * blockDim.x) {
+        float s = accumulate ? out[e] : 0.0f;
+        for (int c = 0; c < nchunk; c++) s += partial[(long long)c * per + e];
+        out[e] = s;
+    }
+}
+
+// bias gradient: gb[co] = sum over voxels of dY[v][co] (one workgroup per 256 channels-slots)
+__global__ void k_bias_grad(const uint16_t *g, long long nvox, int cg, int g_off, int cout, float *gb, int accumulate)
+{
+    __shared__ float red[256];
+    const int co = blockIdx.x;
+    float s = 0.0f;
+    for (long long v = threadIdx.x; v < nvox; v += blockDim.x) s += bf2f(g[v * cg + g_off + co]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gb[co] = (accumulate ? gb[co] : 0.0f) + red[0];
+}
+
+// ---------------------------------------------------------------- elementwise and resampling
+// g <- g * (y > 0) over a channel slice (ReLU backward; y is the layer output)
+__global__ void k_relu_bwd(uint16_t *g, int cg, int g_off, const uint16_t *y, int cy, int y_off, long long nvox, int c)
+{
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nvox * c; e += (long long)gridDim.x * blockDim.x) {
+        long long v = e / c;
+        int ch = (int)(e % c);
+        if (!(bf2f(y[v * cy + y_off + ch]) > 0.0f)) g[v * cg + g_off + ch] = 0;
+    }
+}
+
+// coarse[U] = sum of the 8 fine children (nearest-upsampling backward)
+__global__ void k_up_bwd(const uint16_t *fine, int cf, int f_off, uint16_t *coarse, int cc, int c_off, int n, int d, int h,
+                         int w, int c)
+{
+    const long long total = (long long)n * d * h * w * c;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+        int ch = (int)(e % c);
+        long long v = e / c;
+        int x = (int)(v % w);
+        long long q = v / w;
+        int y = (int)(q % h);
+        q /= h;
+        int z = (int)(q % d);
+        int nn = (int)(q / d);
+        float s = 0.0f;
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++)
+                for (int cc2 = 0; cc2 < 2; cc2++) {
+                    long long fv = (((long long)nn * 2 * d + 2 * z + a) * 2 * h + 2 * y + b) * 2 * w + 2 * x + cc2;
+                    s += bf2f(fine[fv * cf + f_off + ch]);
+                }
+        coarse[v * cc + c_off + ch] = f2bf(s);
+    }
+}
+
+// dX of the 2^3 stride-2 convolution: dX[u] = dY[u / 2] W[u % 2]^T (FP32 math)
+__global__ void k_down_dgrad(const uint16_t *g, int cg, int g_off, const float *w, int cin, int cout, uint16_t *gx,
+                             int cx, int x_off, int n, int d, int h, int wd, int accumulate)
+{
+    // (d, h, wd) are the fine sizes
+    const long long total = (long long)n * d * h * wd * cin;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+        int ci = (int)(e % cin);
+        long long v = e / cin;
+        int x = (int)(v % wd);
+        long long q = v / wd;
+        int y = (int)(q % h);
+        q /= h;
+        int z = (int)(q % d);
+        int nn = (int)(q / d);
+        int t = ((z & 1) * 2 + (y & 1)) * 2 + (x & 1);
+        long long cv = (((long long)nn * (d / 2) + z / 2) * (h / 2) + y / 2) * (wd / 2) + x / 2;
+        const float *wt = w + ((long long)t * cin + ci) * cout;
+        float s = 0.0f;
+        for (int co = 0; co < cout; co++) s += bf2f(g[cv * cg + g_off + co]) * wt[co];
+        if (accumulate) s += bf2f(gx[v * cx + x_off + ci]);
+        gx[v * cx + x_off + ci] = f2bf(s);
+    }
+}
+
+// FP32 -> BF16 channel-slice copy (network input)
+__global__ void k_to_bf16(const float *x, int cs, long long nvox, int c, uint16_t *y, int cy, int y_off, int c_pad)
+{
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nvox * c_pad; e += (long long)gridDim.x * blockDim.x) {
+        long long v = e / c_pad;
+        int ch = (int)(e % c_pad);
+        y[v * cy + y_off + ch] = ch < c ? f2bf(x[v * cs + ch]) : (uint16_t)0;
+    }
+}
+
+// Masked mean-squared error and its gradient (BF16, scaled by 1 / count):
+// loss_parts[block] = partial sums of mask (pred - target)^2
+__global__ void k_masked_mse(const float *pred, int cp, const float *target, const float *mask, long long nvox, int c,
+                             float inv_count, uint16_t *g, int cg, float *loss_parts)
+{
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nvox * cg; e += (long long)gridDim.x * blockDim.x) {
+        long long v = e / cg;
+        int ch = (int)(e % cg);
+        float gv = 0.0f;
+        if (ch < c && mask[v] != 0.0f) {
+            float d = pred[v * cp + ch] - target[v * c + ch];
+            s += d * d;
+            gv = 2.0f * d * inv_count;
+        }
+        g[e] = f2bf(gv);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss_parts[blockIdx.x] = red[0];
+}
+
+// Adam on FP32 master parameters (bias-corrected with step t)
+__global__ void k_adam(float *p, const float *g, float *m, float *v, long long n, float lr, float b1, float b2, float eps,
+                       int t)
+{
+    const float c1 = 1.0f / (1.0f - powf(b1, (float)t)), c2 = 1.0f / (1.0f - powf(b2, (float)t));
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        float gg = g[e];
+        float mm = b1 * m[e] + (1.0f - b1) * gg;
+        float vv = b2 * v[e] + (1.0f - b2) * gg * gg;
+        m[e] = mm;
+        v[e] = vv;
+        p[e] -= lr * (mm * c1) / (sqrtf(vv * c2) + eps);
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+static unsigned grid_for(long long n, int per = 256)
+{
+    long long b = (n + per - 1) / per;
+    return (unsigned)(b < 16384 ? (b < 1 ? 1 : b) : 16384);
+}
+
+hipError_t conv(const ConvArgs &a, hipStream_t st)
+{
+    const long long nvox = (long long)a.n * a.od * a.oh * a.ow;
+    const unsigned g = (unsigned)((nvox + 255) / 256);
+    switch ((a.cout + 15) / 16) {
+    case 1: k_conv<1><<<g, 256, 0, st>>>(a); break;
+    case 2: k_conv<2><<<g, 256, 0, st>>>(a); break;
+    case 4: k_conv<4><<<g, 256, 0, st>>>(a); break;
+    case 8: k_conv<8><<<g, 256, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t pack(const float *w, int ntap, int cin, int cout, int cin_p, int cout_p, int transpose, uint16_t *out,
+                hipStream_t st)
+{
+    const long long total = (long long)ntap * (cin_p / 16) * (cout_p / 16) * 256;
+    k_pack<<<grid_for(total), 256, 0, st>>>(w, ntap, cin, cout, cin_p, cout_p, transpose, out);
+    return hipGetLastError();
+}
+
+hipError_t wgrad(const WgradArgs &a, hipStream_t st)
+{
+    const int ks = a.kind == KIND_C3 || a.kind == KIND_UP ? 3 : (a.kind == KIND_DOWN ? 2 : 1);
+    const int ntap = ks * ks * ks;
+    const long long nvox = (long long)a.n * a.od * a.oh * a.ow;
+    const int nchunk = (int)((nvox + a.chunk - 1) / a.chunk);
+    const unsigned g = (unsigned)(nchunk * ntap);
+    switch ((a.cout + 15) / 16) {
+    case 1: k_wgrad<1><<<g, 256, 0, st>>>(a); break;
+    case 2: k_wgrad<2><<<g, 256, 0, st>>>(a); break;
+    case 4: k_wgrad<4><<<g, 256, 0, st>>>(a); break;
+    case 8: k_wgrad<8><<<g, 256, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    const long long per = (long long)ntap * a.cin * a.cout;
+    k_reduce_partials<<<grid_for(per), 256, 0, st>>>(a.partial, nchunk, per, a.gw, a.accumulate);
+    return hipGetLastError();
+}
+
+hipError_t bias_grad(const uint16_t *g, long long nvox, int cg, int g_off, int cout, float *gb, int accumulate,
+                     hipStream_t st)
+{
+    k_bias_grad<<<cout, 256, 0, st>>>(g, nvox, cg, g_off, cout, gb, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t relu_bwd(uint16_t *g, int cg, int g_off, const uint16_t *y, int cy, int y_off, long long nvox, int c,
+                    hipStream_t st)
+{
+    k_relu_bwd<<<grid_for(nvox * c), 256, 0, st>>>(g, cg, g_off, y, cy, y_off, nvox, c);
+    return hipGetLastError();
+}
+
+hipError_t up_bwd(const uint16_t *fine, int cf, int f_off, uint16_t *coarse, int cc, int c_off, int n, int d, int h, int w,
+                  int c, hipStream_t st)
+{
+    k_up_bwd<<<grid_for((long long)n * d * h * w * c), 256, 0, st>>>(fine, cf, f_off, coarse, cc, c_off, n, d, h, w, c);
+    return hipGetLastError();
+}
+
+hipError_t down_dgrad(const uint16_t *g, int cg, int g_off, const float *w, int cin, int cout, uint16_t *gx, int cx,
+                      int x_off, int n, int d, int h, int wd, int accumulate, hipStream_t st)
+{
+    k_down_dgrad<<<grid_for((long long)n * d * h * wd * cin), 256, 0, st>>>(g, cg, g_off, w, cin, cout, gx, cx, x_off, n,
+                                                                              d, h, wd, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t to_bf16(const float *x, int cs, long long nvox, int c, uint16_t *y, int cy, int y_off, int c_pad, hipStream_t st)
+{
+    k_to_bf16<<<grid_for(nvox * c_pad), 256, 0, st>>>(x, cs, nvox, c, y, cy, y_off, c_pad);
+    return hipGetLastError();
+}
+
+hipError_t masked_mse(const float *pred, int cp, const float *target, const float *mask, long long nvox, int c,
+                      float inv_count, uint16_t *g, int cg, float *loss_parts, int nparts, hipStream_t st)
+{
+    k_masked_mse<<<nparts, 256, 0, st>>>(pred, cp, target, mask, nvox, c, inv_count, g, cg, loss_parts);
+    return hipGetLastError();
+}
+
+hipError_t adam(float *p, const float *g, float *m, float *v, long long n, float lr, float b1, float b2, float eps, int t,
+                hipStream_t st)
+{
+    k_adam<<<grid_for(n), 256, 0, st>>>(p, g, m, v, n, lr, b1, b2, eps, t);
+    return hipGetLastError();
+}
+
+}  // namespace nn
