@@ -27,7 +27,17 @@ HBM_PEAK_GBS = 8000.0
 # writes x, v, A, G (24 floats).  Grid bytes (16 B per active node and
 # pass) are left out, so `achieved` is a lower bound.
 ALG_BYTES = {"p2g": 60.0, "g2p": 144.0, "grid": 0.0, "sort": 0.0}
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2302_04659_amd", "csrc", "mpm_kernels.hip")
+# Sources the substep kernels are compiled from: a traffic summary is valid
+# only for the exact sources it was measured on.
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2302_04659_amd", "csrc", f) for f in
+                  ("mpm_kernels.hip", "mpm_device.hpp", "mpm_math.hpp", "mpm_kernels.hpp", "mpm_types.hpp")]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def workload(name):
@@ -50,7 +60,7 @@ def kernel_traffic(kernel, wl):
     path = os.path.join(ROOT, "profiles", f"{kernel}_{wl}_traffic.txt")
     if not os.path.exists(path):
         return None
-    src_hash = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    src_hash = kernel_source_hash()
     vals = {}
     for line in open(path):
         if ":" in line:
@@ -96,8 +106,11 @@ def main():
     ap.add_argument("--graph", type=int, default=-1)
     ap.add_argument("--persistent", type=int, default=-1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-scenes", type=int, default=32)
-    ap.add_argument("--cpu-substeps", type=int, default=25)
+    ap.add_argument("--cpu-scenes", type=int, default=64)
+    ap.add_argument("--cpu-substeps", type=int, default=50)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after the timed region, run a plain device-to-device copy of this many MiB three "
+                         "times (the reference kernel for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -198,6 +211,14 @@ def main():
     }
     if tune:
         out["autotune"] = tune
+    if args.copy_probe_mb:
+        nb = args.copy_probe_mb << 20
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copy probe: 3 x {nb} bytes device-to-device", file=sys.stderr)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(scene_list, min(args.cpu_scenes, len(scene_list)), args.cpu_substeps)
     print(json.dumps(out), flush=True)

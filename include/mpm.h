@@ -186,6 +186,60 @@ mpm_status mpm_get_timing(mpm_ctx ctx, double *ms_total, long long *launches, in
  * block (block edge = MPM_OPT_BLOCK) as of the last re-sort. */
 mpm_status mpm_get_order(mpm_ctx ctx, int *pid_out);
 
+/* Per-scene stepping mask: active[s] = 0 leaves scene s untouched by the
+ * following mpm_step calls (its particles neither scatter nor move; its
+ * colliders still advance).  active = NULL (or all nonzero) steps every
+ * scene again.  Host array of mpm_num_scenes(ctx) ints; blocks.  The
+ * scenes are independent (Sec. 3 runs one soft scene per environment), so
+ * stepping a subset gives those scenes exactly what stepping all would. */
+mpm_status mpm_set_scene_mask(mpm_ctx ctx, const int *active);
+
+/* ---- Grid surrogate for one control step ------------------------------
+ * The paper has no learned component; these calls let a grid network stand
+ * in for one control step of 25 substeps (App. D.3: 25 physics steps per
+ * control step), with the plain substeps above as the per-scene fallback.
+ * All scenes must share one grid resolution R; every pointer is a device
+ * pointer on the context's device; work is queued on the context stream.
+ * Units: velocities in 0.2 m/s, masses in rho dx^3 of the scene. */
+
+/* Network input and start grid of the current state at the current
+ * collider poses: a P2G and grid update (the state is not changed).
+ * feat  [n_scenes][R][R][R][cf] (cf >= 8): 0 m, 1-3 p (P2G output), 4
+ *       distance to the nearest collider in cells clipped to [-3, 3], 5-7
+ *       that collider's velocity where it is closer than 3 cells (else 0),
+ *       8.. zero;
+ * grid0 [n_scenes][R][R][R][4]: (m, v = p / m) of that P2G, before gravity,
+ *       colliders and walls (v = 0 where m = 0).  Node (i, j, k) is at
+ *       (i dx, j dx, k dx). */
+mpm_status mpm_sur_features(mpm_ctx ctx, float *feat, int cf, float *grid0);
+
+/* One control step from a grid prediction.  pred [n_scenes][R][R][R][cp]
+ * (cp >= 4, multiple of 4): 0-2 velocity change, 3 mass change over the
+ * step, at the nodes of grid0 (from mpm_sur_features on this state).
+ * Particles advance with T = 25 dt: x += T v_mid, F <- (I + T C_mid) F
+ * then the return map, v and C from v_end = v_start + dv (v_mid the mean of
+ * start and end), and a P2G of the advanced particles (m_r, v_r = p_r / m_r)
+ * is compared with the prediction over the nodes holding material before or
+ * after:
+ *   r = max(|m_r - m_pred|_1 / sum m, |m_r v_r - m_pred v_end|_1 /
+ *           max(|m v_start|_1, sum m |g| T)),
+ * per scene.  Scenes with r > threshold (or non-finite state) are put back
+ * to their state at the start of the step and run the 25 plain substeps
+ * instead (flag MPM_SUR_NO_FALLBACK keeps every scene on the surrogate and
+ * only reports r).  residual [n_scenes] (nullable) receives r; n_fallback
+ * [1] (nullable) the number of scenes over the threshold.  MPM_SUR_SYNC
+ * waits for the decision and skips the plain substeps when no scene fell
+ * back.  Colliders advance by 25 substeps either way. */
+enum { MPM_SUR_NO_FALLBACK = 1, MPM_SUR_SYNC = 2 };
+mpm_status mpm_sur_block(mpm_ctx ctx, const float *pred, int cp, const float *grid0, float threshold, int flags,
+                         float *residual, int *n_fallback);
+
+/* Training targets between the start grids g0, g1 of two consecutive
+ * control steps (both from mpm_sur_features): target [n][R^3][ct] (ct >= 4)
+ * = ((v1 - v0) in 0.2 m/s, (m1 - m0) in rho dx^3), mask [n][R^3] = 1 where
+ * m0 > 0 or m1 > 0, else 0. */
+mpm_status mpm_sur_targets(mpm_ctx ctx, const float *g0, const float *g1, float *target, int ct, float *mask);
+
 /* Introspection. */
 int mpm_num_scenes(mpm_ctx ctx);
 int mpm_num_particles(mpm_ctx ctx, int scene);   /* scene = -1: total */

@@ -76,11 +76,13 @@ int mpm_nn_down_dgrad(const uint16_t *g, int cg, int g_off, const float *w, int 
 int mpm_nn_to_bf16(const float *x, int cs, long long voxels, int c, uint16_t *y, int cy, int y_off, int c_pad,
                    void *stream);
 
-/* Masked MSE: loss_parts[nparts] receive partial sums of mask (pred - target)^2
- * over the first c channels; g [voxel][cg] receives 2 (pred - target) / count
- * on masked voxels (0 elsewhere), count = sum(mask) * c given as inv_count. */
+/* Masked MSE over the first c channels: loss_parts holds nparts + 1 floats;
+ * loss_parts[0 .. nparts) receive partial sums of mask (pred - target)^2 and
+ * loss_parts[nparts] the number of masked voxels (mask != 0), so the loss is
+ * sum(parts) / (count c).  g [voxel][cg] receives 2 (pred - target) / (count c)
+ * on masked voxels and 0 elsewhere (all cg channels).  voxels < 2^24. */
 int mpm_nn_masked_mse(const float *pred, int cp, const float *target, const float *mask, long long voxels, int c,
-                      float inv_count, uint16_t *g, int cg, float *loss_parts, int nparts, void *stream);
+                      uint16_t *g, int cg, float *loss_parts, int nparts, void *stream);
 
 /* One bias-corrected Adam step (t >= 1) on n FP32 parameters. */
 int mpm_nn_adam(float *p, const float *g, float *m, float *v, long long n, float lr, float beta1, float beta2,

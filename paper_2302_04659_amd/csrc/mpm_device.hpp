@@ -1,0 +1,97 @@
+// Device helpers shared by the substep kernels and the surrogate kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "mpm_kernels.hpp"
+#include "mpm_math.hpp"
+
+namespace mpm {
+
+constexpr int WG = 256;
+constexpr float SUR_VEL = 0.2f;   // velocity unit of the surrogate's inputs and outputs (m/s)
+
+__device__ __forceinline__ int xcd_remap(int b, int G)
+{
+    // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous run of work items so neighbouring grid blocks share an L2.
+    return (b & 7) * (G >> 3) + (b >> 3);
+}
+
+__device__ __forceinline__ int cvt_rpi(float x)
+{
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// Particle component c of slot j: base pointer per component (uniform) plus a
+// 32-bit byte offset, so loads and stores use scalar-base addressing.
+__device__ __forceinline__ float pload(const float *P, long long ps, int c, unsigned joff)
+{
+    return *(const float *)((const char *)(P + c * ps) + joff);
+}
+
+__device__ __forceinline__ void pstore(float *P, long long ps, int c, unsigned joff, float v)
+{
+    *(float *)((char *)(P + c * ps) + joff) = v;
+}
+
+__device__ __forceinline__ long long node_index(const SceneDev &S, int B, int i, int j, int k)
+{
+    int nb = S.nb;
+    int lb = ((i / B) * nb + (j / B)) * nb + (k / B);
+    int l = ((i % B) * B + (j % B)) * B + (k % B);
+    return S.grid_off + (long long)lb * (B * B * B) + l;
+}
+
+__device__ __forceinline__ int scene_of_bin(const int *off, int n_scenes, int b)
+{
+    int lo = 0, hi = n_scenes;          // off[lo] <= b < off[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void particle_base(const SceneDev &S, float x, int &b, float &f, int &clamped)
+{
+    float xi = x * S.inv_dx;
+    float fb = floorf(xi - 0.5f);
+    int bi = (int)fb;
+    int c = bi < 0 ? 0 : (bi > S.res - 3 ? S.res - 3 : bi);
+    clamped |= (c != bi) || !(fb == fb);
+    b = c;
+    f = xi - (float)c;
+}
+
+__device__ __forceinline__ Material material_of(const SceneDev &S)
+{
+    Material m;
+    m.model = S.model;
+    m.plastic = S.plastic;
+    m.mu = S.mu;
+    m.la = S.la;
+    m.yield_eps = S.yield_eps;
+    return m;
+}
+
+// Bound on |m v_c + (A d)_c| over the 27 stencil offsets d (|d_e| <= 1.5 dx).
+__device__ __forceinline__ float scatter_bound(float mass, float dx, const float v[3], const float A[9])
+{
+    float b = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        float row = fabsf(A[3 * c]) + fabsf(A[3 * c + 1]) + fabsf(A[3 * c + 2]);
+        b = fmaxf(b, fmaf(mass, fabsf(v[c]), 1.5f * dx * row));
+    }
+    return b;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+}  // namespace mpm

@@ -86,6 +86,12 @@ struct mpm_ctx_s {
     int *d_flags = nullptr;
     int *d_queue = nullptr, *d_scene_done = nullptr;
 
+    // per-scene step mask (1 = step), dense per-scene grid offsets
+    int *d_active = nullptr;
+    // grid surrogate: re-splat grid and residual sums
+    float *d_sur_gend = nullptr, *d_sur_acc = nullptr;
+    int *d_sur_nfb = nullptr;
+
     // debug capture of the P2G grid
     int capture = 0;
     float *d_cap = nullptr;
@@ -345,6 +351,11 @@ StepArgs step_args(mpm_ctx ctx, int substep)
     a.B = ctx->B;
     a.queue = ctx->d_queue;
     a.scene_done = ctx->d_scene_done;
+    a.active = ctx->d_active;
+    a.dense = nullptr;
+    a.feat = nullptr;
+    a.cf = 0;
+    a.keep_bound = 0;
     return a;
 }
 
@@ -488,7 +499,8 @@ void release(mpm_ctx ctx)
                     ctx->d_col_scene, ctx->d_scene_bin_off, ctx->d_keys, ctx->d_count, ctx->d_pstart, ctx->d_perm,
                     ctx->d_tsum, ctx->d_dil, ctx->L.items, ctx->L.gitems, ctx->L.n_items, ctx->L.n_gitems,
                     ctx->L.scene_item_begin, ctx->L.scene_gitem_begin, ctx->L.bflag, ctx->L.ovf, ctx->L.n_ovf, ctx->L.ibound,
-                    ctx->d_flags, ctx->d_queue, ctx->d_scene_done, ctx->d_cap, ctx->d_cap_off, ctx->d_io};
+                    ctx->d_flags, ctx->d_queue, ctx->d_scene_done, ctx->d_cap, ctx->d_cap_off, ctx->d_io,
+                    ctx->d_active, ctx->d_sur_gend, ctx->d_sur_acc, ctx->d_sur_nfb};
     for (void *p : bufs)
         if (p) hipFree(p);
     for (int i = 0; i < STAGE_RING; i++) {
@@ -568,6 +580,20 @@ mpm_status create_impl(mpm_ctx ctx, const mpm_scene_desc *scenes, int n_scenes)
     HIPCHK(dalloc(&ctx->L.n_ovf, 1));
     ctx->L.ovf_cap = T4;
     HIPCHK(dalloc(&ctx->d_flags, n_scenes));
+    HIPCHK(dalloc(&ctx->d_active, n_scenes));
+    HIPCHK(launch_fill_i(ctx->d_active, n_scenes, 1, ctx->stream));
+    {
+        std::vector<long long> off(n_scenes);
+        long long tot = 0;
+        for (int s = 0; s < n_scenes; s++) {
+            off[s] = tot;
+            long long r = scenes[s].res;
+            tot += r * r * r;
+        }
+        ctx->cap_nodes = tot;
+        HIPCHK(dalloc(&ctx->d_cap_off, n_scenes));
+        HIPCHK(hipMemcpy(ctx->d_cap_off, off.data(), sizeof(long long) * n_scenes, hipMemcpyHostToDevice));
+    }
     HIPCHK(dalloc(&ctx->d_queue, 4));
     HIPCHK(dalloc(&ctx->d_scene_done, 3 * n_scenes));
     HIPCHK(dalloc(&ctx->d_io, (size_t)24 * N));
@@ -890,18 +916,8 @@ mpm_status mpm_set_option(mpm_ctx ctx, int option, int value)
     case MPM_OPT_CAPTURE_GRID:
         ARGCHK(value == 0 || value == 1, "capture must be 0 or 1");
         if (value && !ctx->d_cap) {
-            std::vector<long long> off(ctx->n_scenes);
-            long long tot = 0;
-            for (int s = 0; s < ctx->n_scenes; s++) {
-                off[s] = tot;
-                long long r = ctx->h_scenes[s].res;
-                tot += r * r * r;
-            }
-            ctx->cap_nodes = tot;
-            HIPCHK(dalloc(&ctx->d_cap, (size_t)4 * tot));
-            HIPCHK(dalloc(&ctx->d_cap_off, ctx->n_scenes));
-            HIPCHK(hipMemcpy(ctx->d_cap_off, off.data(), sizeof(long long) * ctx->n_scenes, hipMemcpyHostToDevice));
-            HIPCHK(launch_clear_f(ctx->d_cap, 4 * tot, ctx->stream));
+            HIPCHK(dalloc(&ctx->d_cap, (size_t)4 * ctx->cap_nodes));
+            HIPCHK(launch_clear_f(ctx->d_cap, 4 * ctx->cap_nodes, ctx->stream));
         }
         ctx->capture = value;
         return MPM_OK;
@@ -954,6 +970,133 @@ mpm_status mpm_get_order(mpm_ctx ctx, int *pid_out)
     if (ctx->N > 0)
         HIPCHK(hipMemcpy(pid_out, ctx->d_P[ctx->cur] + (size_t)PID * ctx->pstride, sizeof(int) * ctx->N,
                          hipMemcpyDeviceToHost));
+    return MPM_OK;
+}
+
+mpm_status mpm_set_scene_mask(mpm_ctx ctx, const int *active)
+{
+    ARGCHK(ctx, "null context");
+    hipSetDevice(ctx->dev);
+    std::vector<int> h(ctx->n_scenes, 1);
+    if (active)
+        for (int s = 0; s < ctx->n_scenes; s++) h[s] = active[s] != 0;
+    HIPCHK(hipMemcpyAsync(ctx->d_active, h.data(), sizeof(int) * ctx->n_scenes, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MPM_OK;
+}
+
+namespace {
+
+// The grid resolution shared by every scene, or 0.
+int common_res(mpm_ctx ctx)
+{
+    int r = ctx->n_scenes > 0 ? ctx->h_scenes[0].res : 0;
+    for (int s = 1; s < ctx->n_scenes; s++)
+        if (ctx->h_scenes[s].res != r) return 0;
+    return r;
+}
+
+}  // namespace
+
+mpm_status mpm_sur_features(mpm_ctx ctx, float *feat, int cf, float *grid0)
+{
+    ARGCHK(ctx, "null context");
+    ARGCHK(feat && grid0, "feat and grid0 must not be NULL");
+    ARGCHK(cf >= 8, "cf must be >= 8");
+    const int R = common_res(ctx);
+    ARGCHK(R > 0, "the surrogate needs one grid resolution for all scenes");
+    hipSetDevice(ctx->dev);
+    if (ctx->since_sort >= ctx->sort_every) {   // due, or the state was set: work lists and scatter bounds
+        mpm_status st = do_sort(ctx);
+        if (st != MPM_OK) return st;
+    }
+    StepArgs a = step_args(ctx, 0);
+    HIPCHK(launch_colliders_now(a, (int)ctx->h_cols.size(), ctx->d_col_scene, ctx->stream));
+    HIPCHK(launch_sur_dense(a, R, feat, cf, grid0, ctx->stream));
+    a.dense = grid0;
+    a.feat = feat;
+    a.cf = cf;
+    a.keep_bound = 1;   // the state does not change: its scatter bounds stay valid
+    HIPCHK(launch_p2g(a, ctx->CH, substep_wgs(ctx), ctx->stream));
+    HIPCHK(launch_grid(a, substep_wgs(ctx), ctx->stream));
+    HIPCHK(launch_fill_i(ctx->L.n_ovf, 1, 0, ctx->stream));   // the overflow list has been consumed
+    return MPM_OK;
+}
+
+mpm_status mpm_sur_block(mpm_ctx ctx, const float *pred, int cp, const float *grid0, float threshold, int flags,
+                         float *residual, int *n_fallback)
+{
+    ARGCHK(ctx, "null context");
+    ARGCHK(pred && grid0, "pred and grid0 must not be NULL");
+    ARGCHK(cp >= 4 && cp % 4 == 0, "cp must be a multiple of 4 and >= 4");
+    ARGCHK(threshold >= 0.0f, "threshold must be >= 0");
+    ARGCHK((flags & ~(MPM_SUR_NO_FALLBACK | MPM_SUR_SYNC)) == 0, "unknown flag");
+    const int R = common_res(ctx);
+    ARGCHK(R > 0, "the surrogate needs one grid resolution for all scenes");
+    ARGCHK(((long long)R * R * R) % 4096 == 0, "grid resolution too small for the surrogate (res^3 % 4096)");
+    hipSetDevice(ctx->dev);
+    if (!ctx->d_sur_gend) HIPCHK(dalloc(&ctx->d_sur_gend, (size_t)4 * ctx->cap_nodes));
+    if (!ctx->d_sur_acc) HIPCHK(dalloc(&ctx->d_sur_acc, (size_t)4 * ctx->n_scenes));
+    if (!ctx->d_sur_nfb) HIPCHK(dalloc(&ctx->d_sur_nfb, 1));
+    const int nsub = GRAPH_BLOCK;
+    const int fallback = !(flags & MPM_SUR_NO_FALLBACK);
+    if (ctx->since_sort >= ctx->sort_every) {
+        mpm_status st = do_sort(ctx);
+        if (st != MPM_OK) return st;
+    }
+    // snapshot into the sort's other buffer (dead until the next sort)
+    HIPCHK(hipMemcpyAsync(ctx->d_P[1 - ctx->cur], ctx->d_P[ctx->cur], sizeof(float) * NCOMP * ctx->pstride,
+                          hipMemcpyDeviceToDevice, ctx->stream));
+    StepArgs a = step_args(ctx, 0);
+    HIPCHK(launch_sur_advance(a, grid0, pred, cp, nsub, substep_wgs(ctx), ctx->stream));
+    // re-splat the advanced particles
+    StepArgs r = step_args(ctx, nsub);
+    HIPCHK(launch_clear_f(ctx->d_sur_gend, 4 * ctx->cap_nodes, ctx->stream));
+    r.dense = ctx->d_sur_gend;
+    r.keep_bound = 1;   // bounds now cover both the start and the advanced state
+    HIPCHK(launch_p2g(r, ctx->CH, substep_wgs(ctx), ctx->stream));
+    HIPCHK(launch_grid(r, substep_wgs(ctx), ctx->stream));
+    HIPCHK(launch_fill_i(ctx->L.n_ovf, 1, 0, ctx->stream));
+    HIPCHK(launch_clear_f(ctx->d_sur_acc, 4 * ctx->n_scenes, ctx->stream));
+    HIPCHK(launch_sur_residual(a, R, grid0, pred, cp, ctx->d_sur_gend, ctx->d_sur_acc, ctx->stream));
+    HIPCHK(launch_fill_i(ctx->d_sur_nfb, 1, 0, ctx->stream));
+    HIPCHK(launch_sur_decide(a, ctx->d_sur_acc, nsub, threshold, fallback, residual, ctx->d_active, ctx->d_sur_nfb,
+                             ctx->stream));
+    if (n_fallback)
+        HIPCHK(hipMemcpyAsync(n_fallback, ctx->d_sur_nfb, sizeof(int), hipMemcpyDeviceToDevice, ctx->stream));
+    bool run_plain = fallback;
+    if (fallback && (flags & MPM_SUR_SYNC)) {
+        int h = 0;
+        HIPCHK(hipMemcpyAsync(&h, ctx->d_sur_nfb, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        run_plain = h > 0;
+    }
+    if (run_plain) {
+        // scenes over the threshold: back to the snapshot, then plain substeps on those scenes only
+        HIPCHK(launch_sur_restore(ctx->d_P[1 - ctx->cur], ctx->d_P[ctx->cur], ctx->pstride, ctx->d_psc, ctx->d_active,
+                                  ctx->N, ctx->stream));
+        mpm_status st = queue_substeps(ctx, nsub);
+        HIPCHK(launch_fill_i(ctx->d_active, ctx->n_scenes, 1, ctx->stream));
+        if (st != MPM_OK) return st;
+    } else {
+        HIPCHK(launch_fill_i(ctx->d_active, ctx->n_scenes, 1, ctx->stream));
+        HIPCHK(launch_collider_advance(ctx->d_cols, (int)ctx->h_cols.size(), ctx->d_col_scene, ctx->d_scenes, nsub,
+                                       ctx->stream));
+        ctx->since_sort += nsub;
+    }
+    return MPM_OK;
+}
+
+mpm_status mpm_sur_targets(mpm_ctx ctx, const float *g0, const float *g1, float *target, int ct, float *mask)
+{
+    ARGCHK(ctx, "null context");
+    ARGCHK(g0 && g1 && target && mask, "null argument");
+    ARGCHK(ct >= 4, "ct must be >= 4");
+    const int R = common_res(ctx);
+    ARGCHK(R > 0, "the surrogate needs one grid resolution for all scenes");
+    hipSetDevice(ctx->dev);
+    StepArgs a = step_args(ctx, 0);
+    HIPCHK(launch_sur_targets(a, R, g0, g1, ct, target, mask, ctx->stream));
     return MPM_OK;
 }
 

@@ -16,96 +16,9 @@
 // few substeps by a counting sort (k_keys .. k_gather).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
-#include "mpm_kernels.hpp"
-#include "mpm_math.hpp"
+#include "mpm_device.hpp"
 
 namespace mpm {
-
-static constexpr int WG = 256;
-
-__device__ __forceinline__ int xcd_remap(int b, int G)
-{
-    // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-    // contiguous run of work items so neighbouring grid blocks share an L2.
-    return (b & 7) * (G >> 3) + (b >> 3);
-}
-
-__device__ __forceinline__ int cvt_rpi(float x)
-{
-    int r;
-    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
-    return r;
-}
-
-// Particle component c of slot j: base pointer per component (uniform) plus a
-// 32-bit byte offset, so loads and stores use scalar-base addressing.
-__device__ __forceinline__ float pload(const float *P, long long ps, int c, unsigned joff)
-{
-    return *(const float *)((const char *)(P + c * ps) + joff);
-}
-
-__device__ __forceinline__ void pstore(float *P, long long ps, int c, unsigned joff, float v)
-{
-    *(float *)((char *)(P + c * ps) + joff) = v;
-}
-
-__device__ __forceinline__ long long node_index(const SceneDev &S, int B, int i, int j, int k)
-{
-    int nb = S.nb;
-    int lb = ((i / B) * nb + (j / B)) * nb + (k / B);
-    int l = ((i % B) * B + (j % B)) * B + (k % B);
-    return S.grid_off + (long long)lb * (B * B * B) + l;
-}
-
-__device__ __forceinline__ int scene_of_bin(const int *off, int n_scenes, int b)
-{
-    int lo = 0, hi = n_scenes;          // off[lo] <= b < off[hi]
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (off[mid] <= b) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ void particle_base(const SceneDev &S, float x, int &b, float &f, int &clamped)
-{
-    float xi = x * S.inv_dx;
-    float fb = floorf(xi - 0.5f);
-    int bi = (int)fb;
-    int c = bi < 0 ? 0 : (bi > S.res - 3 ? S.res - 3 : bi);
-    clamped |= (c != bi) || !(fb == fb);
-    b = c;
-    f = xi - (float)c;
-}
-
-__device__ __forceinline__ Material material_of(const SceneDev &S)
-{
-    Material m;
-    m.model = S.model;
-    m.plastic = S.plastic;
-    m.mu = S.mu;
-    m.la = S.la;
-    m.yield_eps = S.yield_eps;
-    return m;
-}
-
-// Bound on |m v_c + (A d)_c| over the 27 stencil offsets d (|d_e| <= 1.5 dx).
-__device__ __forceinline__ float scatter_bound(float mass, float dx, const float v[3], const float A[9])
-{
-    float b = 0.0f;
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-        float row = fabsf(A[3 * c]) + fabsf(A[3 * c + 1]) + fabsf(A[3 * c + 2]);
-        b = fmaxf(b, fmaf(mass, fabsf(v[c]), 1.5f * dx * row));
-    }
-    return b;
-}
-
-__device__ __forceinline__ float wave_max(float v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
-}
 
 // ====================================================================== sort
 // Runs of equal keys in consecutive lanes (the particles are nearly sorted
@@ -431,7 +344,7 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
     const float bmax = a.L.ibound[it];
     if (it == a.L.scene_item_begin[s]) write_colliders_now(a, S);
     __syncthreads();
-    if (t == 0) a.L.ibound[it] = 0.0f;     // this substep's G2P accumulates the next bound
+    if (t == 0 && !a.keep_bound) a.L.ibound[it] = 0.0f;   // this substep's G2P accumulates the next bound
 
     // Power-of-two fixed-point scales keeping every node sum below 2^30:
     // |contribution| <= w * bound, w <= 0.421875, at most item.count particles.
@@ -523,6 +436,7 @@ __global__ __launch_bounds__(WG) void k_p2g(StepArgs a)
     const int n_items = *a.L.n_items;
     for (int it = xcd_remap(blockIdx.x, gridDim.x); it < n_items; it += gridDim.x) {
         Item item = a.L.items[it];
+        if (!a.active[item.scene]) continue;
         p2g_item<B>(a, it, item, tile);
     }
 }
@@ -559,6 +473,19 @@ __device__ void grid_block(const StepArgs &a, int s, int lb, int lane)
         for (int d = 0; d < 3; d++) {
             if (ii[d] < S.bound && v[d] < 0.0f) v[d] = 0.0f;
             if (ii[d] >= S.res - S.bound && v[d] > 0.0f) v[d] = 0.0f;
+        }
+        if (a.dense) {   // (m, p / m) of the P2G, before gravity, colliders and walls
+            const long long c = a.cap_off[s] + ((long long)ii[0] * S.res + ii[1]) * S.res + ii[2];
+            const float im = m > 0.0f ? 1.0f / m : 0.0f;
+            *(float4 *)(a.dense + 4 * c) = make_float4(m, px * im, py * im, pz * im);
+            if (a.feat) {
+                const float inv = S.vol / (S.mass * S.dx * S.dx * S.dx);   // 1 / (rho dx^3)
+                float *fp = a.feat + c * a.cf;
+                fp[0] = m * inv;
+                fp[1] = px * inv * (1.0f / SUR_VEL);
+                fp[2] = py * inv * (1.0f / SUR_VEL);
+                fp[3] = pz * inv * (1.0f / SUR_VEL);
+            }
         }
         a.gvx[idx] = v[0];
         a.gvy[idx] = v[1];
@@ -742,6 +669,7 @@ __global__ __launch_bounds__(WG, 4) void k_g2p(StepArgs a)
     const int n_items = *a.L.n_items;
     for (int it = xcd_remap(blockIdx.x, gridDim.x); it < n_items; it += gridDim.x) {
         Item item = a.L.items[it];
+        if (!a.active[item.scene]) continue;
         g2p_item<B>(a, it, item, vt);
     }
 }
@@ -996,6 +924,21 @@ __global__ void k_reset_counters(int *queue, int *scene_done, int n, int *n_ovf)
 hipError_t launch_reset_scene_counters(int *queue, int *scene_done, int n_scenes, int *n_ovf, hipStream_t st)
 {
     k_reset_counters<<<1, WG, 0, st>>>(queue, scene_done, n_scenes, n_ovf);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_i(int *p, long long n, int v)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_i(int *p, long long n, int v, hipStream_t st)
+{
+    if (n > 0) {
+        long long nb = (n + WG - 1) / WG;
+        k_fill_i<<<(unsigned)(nb < 4096 ? nb : 4096), WG, 0, st>>>(p, n, v);
+    }
     return hipGetLastError();
 }
 

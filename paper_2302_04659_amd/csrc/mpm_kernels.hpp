@@ -24,6 +24,11 @@ struct StepArgs {
     int *queue;               // persistent mode: [0] queue cursor, [1] workgroups finished
     int *scene_done;          // persistent mode: [n_scenes] P2G items done, [n_scenes] grid entries done
     int n_wg;                 // persistent mode: number of workgroups launched
+    const int *active;        // per scene: 0 = leave this scene's particles as they are (P2G / G2P skip it)
+    float *dense;             // optional grid-update output, dense per scene [res^3][4] = (m, v), or null
+    float *feat;              // optional surrogate input channels 0-3 (m, p normalised) [res^3][cf], or null
+    int cf;
+    int keep_bound;           // 1: a P2G with no G2P after it (leave the per-item scatter bounds as they are)
 };
 
 
@@ -64,5 +69,20 @@ hipError_t launch_get_state(const SceneDev *scenes, const int *psc, const float 
                             int end, float *x, float *v, float *C, float *F, hipStream_t st);
 hipError_t launch_clear_f(float *p, long long n, hipStream_t st);
 hipError_t launch_reset_scene_counters(int *queue, int *scene_done, int n_scenes, int *n_ovf, hipStream_t st);
+hipError_t launch_fill_i(int *p, long long n, int v, hipStream_t st);
+
+// Grid surrogate support (all scenes share one resolution `res`).
+hipError_t launch_colliders_now(const StepArgs &a, int n_cols, const int *col_scene, hipStream_t st);
+hipError_t launch_sur_dense(const StepArgs &a, int res, float *feat, int cf, float *grid0, hipStream_t st);
+hipError_t launch_sur_advance(const StepArgs &a, const float *grid0, const float *pred, int cp, int n_sub, int n_wg,
+                              hipStream_t st);
+hipError_t launch_sur_residual(const StepArgs &a, int res, const float *grid0, const float *pred, int cp,
+                               const float *gend, float *acc, hipStream_t st);
+hipError_t launch_sur_decide(const StepArgs &a, const float *acc, int n_sub, float threshold, int fallback,
+                             float *residual, int *active, int *n_fallback, hipStream_t st);
+hipError_t launch_sur_restore(const float *Psnap, float *P, long long pstride, const int *psc, const int *active, int N,
+                              hipStream_t st);
+hipError_t launch_sur_targets(const StepArgs &a, int res, const float *g0, const float *g1, int ct, float *target,
+                              float *mask, hipStream_t st);
 
 }  // namespace mpm

@@ -105,12 +105,12 @@ int mpm_nn_to_bf16(const float *x, int cs, long long voxels, int c, uint16_t *y,
 }
 
 int mpm_nn_masked_mse(const float *pred, int cp, const float *target, const float *mask, long long voxels, int c,
-                      float inv_count, uint16_t *g, int cg, float *loss_parts, int nparts, void *stream)
+                      uint16_t *g, int cg, float *loss_parts, int nparts, void *stream)
 {
     if (!pred || !target || !mask || !g || !loss_parts || voxels <= 0 || c <= 0 || cp < c || cg < c || nparts <= 0)
         return -1;
-    return st_of(nn::masked_mse(pred, cp, target, mask, voxels, c, inv_count, g, cg, loss_parts, nparts,
-                                (hipStream_t)stream));
+    if (nparts > 65535 || voxels >= (1LL << 24)) return -1;
+    return st_of(nn::masked_mse(pred, cp, target, mask, voxels, c, g, cg, loss_parts, nparts, (hipStream_t)stream));
 }
 
 int mpm_nn_adam(float *p, const float *g, float *m, float *v, long long n, float lr, float beta1, float beta2,

@@ -352,12 +352,31 @@ __global__ void k_to_bf16(const float *x, int cs, long long nvox, int c, uint16_
     }
 }
 
-// Masked mean-squared error and its gradient (BF16, scaled by 1 / count):
-// loss_parts[block] = partial sums of mask (pred - target)^2
+// Number of masked voxels (mask != 0), counted in integers by one workgroup
+// and stored as a float (exact below 2^24 voxels).
+__global__ void k_mask_count(const float *mask, long long nvox, float *count)
+{
+    __shared__ int red[256];
+    int c = 0;
+    for (long long v = threadIdx.x; v < nvox; v += blockDim.x) c += mask[v] != 0.0f;
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = (float)red[0];
+}
+
+// Masked mean-squared error and its gradient (BF16):
+// loss_parts[block] = partial sums of mask (pred - target)^2, g = 2 (pred - target) / (count c)
+// on masked voxels, 0 elsewhere (all cg channels written).
 __global__ void k_masked_mse(const float *pred, int cp, const float *target, const float *mask, long long nvox, int c,
-                             float inv_count, uint16_t *g, int cg, float *loss_parts)
+                             const float *count, uint16_t *g, int cg, float *loss_parts)
 {
     __shared__ float red[256];
+    const float cnt = *count * (float)c;
+    const float inv_count = cnt > 0.0f ? 1.0f / cnt : 0.0f;
     float s = 0.0f;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nvox * cg; e += (long long)gridDim.x * blockDim.x) {
         long long v = e / cg;
@@ -478,9 +497,10 @@ hipError_t to_bf16(const float *x, int cs, long long nvox, int c, uint16_t *y, i
 }
 
 hipError_t masked_mse(const float *pred, int cp, const float *target, const float *mask, long long nvox, int c,
-                      float inv_count, uint16_t *g, int cg, float *loss_parts, int nparts, hipStream_t st)
+                      uint16_t *g, int cg, float *loss_parts, int nparts, hipStream_t st)
 {
-    k_masked_mse<<<nparts, 256, 0, st>>>(pred, cp, target, mask, nvox, c, inv_count, g, cg, loss_parts);
+    k_mask_count<<<1, 256, 0, st>>>(mask, nvox, loss_parts + nparts);
+    k_masked_mse<<<nparts, 256, 0, st>>>(pred, cp, target, mask, nvox, c, loss_parts + nparts, g, cg, loss_parts);
     return hipGetLastError();
 }
 

@@ -50,7 +50,7 @@ hipError_t down_dgrad(const uint16_t *g, int cg, int g_off, const float *w, int 
 hipError_t to_bf16(const float *x, int cs, long long nvox, int c, uint16_t *y, int cy, int y_off, int c_pad,
                    hipStream_t st);
 hipError_t masked_mse(const float *pred, int cp, const float *target, const float *mask, long long nvox, int c,
-                      float inv_count, uint16_t *g, int cg, float *loss_parts, int nparts, hipStream_t st);
+                      uint16_t *g, int cg, float *loss_parts, int nparts, hipStream_t st);
 hipError_t adam(float *p, const float *g, float *m, float *v, long long n, float lr, float b1, float b2, float eps, int t,
                 hipStream_t st);
 

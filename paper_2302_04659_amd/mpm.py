@@ -75,6 +75,10 @@ def lib():
         L.mpm_autotune.argtypes = [vp, ct.c_int, ct.c_char_p, ct.c_size_t]
         L.mpm_get_order.argtypes = [vp, vp]
         L.mpm_get_timing.argtypes = [vp, vp, vp, ct.c_int]
+        L.mpm_set_scene_mask.argtypes = [vp, vp]
+        L.mpm_sur_features.argtypes = [vp, vp, ct.c_int, vp]
+        L.mpm_sur_block.argtypes = [vp, vp, ct.c_int, vp, ct.c_float, ct.c_int, vp, vp]
+        L.mpm_sur_targets.argtypes = [vp, vp, vp, vp, ct.c_int, vp]
         for name in ("mpm_num_scenes", "mpm_max_colliders"):
             getattr(L, name).argtypes = [vp]
         L.mpm_num_particles.argtypes = [vp, ct.c_int]
@@ -88,10 +92,14 @@ def lib():
 
 
 def declared_functions() -> List[str]:
-    """Names of the functions include/mpm.h declares."""
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(mpm_[a-z_]+)\s*\(", txt)))
+    """Names of the functions the headers under include/ declare."""
+    names = set()
+    for h in sorted(os.listdir(os.path.dirname(HEADER))):
+        if h.endswith(".h"):
+            txt = open(os.path.join(os.path.dirname(HEADER), h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names.update(re.findall(r"\b(mpm_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
 
 
 def _ptr(a) -> Optional[int]:
@@ -107,6 +115,10 @@ def _ptr(a) -> Optional[int]:
 def _f32(a, shape) -> np.ndarray:
     out = np.ascontiguousarray(a, dtype=np.float32)
     return out.reshape(shape)
+
+
+SUR_NO_FALLBACK = 1
+SUR_SYNC = 2
 
 
 class Sim:
@@ -146,6 +158,7 @@ class Sim:
         if st != OK:
             raise MPMError(st, "mpm_create failed: " + self.L.mpm_status_string(st).decode())
         self.h = h
+        self.stream = stream          # the caller's stream handle (None: the library's own stream)
         self._keep = []
         self.n_scenes = n
         self.N = int(self.L.mpm_num_particles(self.h, -1))
@@ -194,6 +207,30 @@ class Sim:
     def step(self, n: int = 1):
         return self._check(self.L.mpm_step(self.h, int(n)), "step")
 
+    def set_scene_mask(self, active=None):
+        """Step only the scenes with active[s] != 0 (None: all scenes)."""
+        if active is None:
+            return self._check(self.L.mpm_set_scene_mask(self.h, None), "set_scene_mask")
+        a = np.ascontiguousarray(np.asarray(active) != 0, dtype=np.int32).reshape(self.n_scenes)
+        return self._check(self.L.mpm_set_scene_mask(self.h, a.ctypes.data), "set_scene_mask")
+
+    # ----------------------------------------------------------------- grid surrogate (device tensors)
+    def sur_features(self, feat, grid0):
+        """feat [n_scenes, R, R, R, cf] and grid0 [n_scenes, R, R, R, 4] FP32 device tensors."""
+        return self._check(self.L.mpm_sur_features(self.h, _ptr(feat), int(feat.shape[-1]), _ptr(grid0)),
+                           "sur_features")
+
+    def sur_block(self, pred, grid0, threshold: float = 1e-3, fallback: bool = True, sync: bool = False,
+                  residual=None, n_fallback=None):
+        flags = (0 if fallback else SUR_NO_FALLBACK) | (SUR_SYNC if sync else 0)
+        return self._check(self.L.mpm_sur_block(self.h, _ptr(pred), int(pred.shape[-1]), _ptr(grid0),
+                                                float(threshold), flags, _ptr(residual), _ptr(n_fallback)),
+                           "sur_block")
+
+    def sur_targets(self, g0, g1, target, mask):
+        return self._check(self.L.mpm_sur_targets(self.h, _ptr(g0), _ptr(g1), _ptr(target), int(target.shape[-1]),
+                                                  _ptr(mask)), "sur_targets")
+
     def sync(self):
         return self._check(self.L.mpm_sync(self.h), "sync")
 
@@ -227,6 +264,13 @@ class Sim:
         """Copy into torch device tensors (stream-ordered, no host round trip)."""
         return self._check(self.L.mpm_get_particles(self.h, scene, _ptr(x), _ptr(v), _ptr(F), 1),
                            "get_particles")
+
+    def get_state_device(self, x, v, C, F, scene: int = -1):
+        """Copy the state (creation order) into device tensors, stream-ordered."""
+        return self._check(self.L.mpm_get_state(self.h, scene, _ptr(x), _ptr(v), _ptr(C), _ptr(F), 1), "get_state")
+
+    def set_state_device(self, x, v, C, F, scene: int = -1):
+        return self._check(self.L.mpm_set_state(self.h, scene, _ptr(x), _ptr(v), _ptr(C), _ptr(F), 1), "set_state")
 
     def set_state(self, x, v, C, F, scene: int = -1):
         n = self._count(scene)

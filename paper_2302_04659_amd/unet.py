@@ -37,6 +37,22 @@ LAYERS = [
 ]
 
 
+NPARTS = 1024
+
+
+class LossHandle:
+    """Partial sums written by the masked-MSE kernel; value() copies them
+    back and forms sum / (count * channels) on the host."""
+
+    def __init__(self, parts, c):
+        self.parts, self.c = parts, c
+
+    def value(self) -> float:
+        p = self.parts.cpu().numpy().astype(np.float64)
+        n = p[-1] * self.c
+        return float(p[:-1].sum() / n) if n > 0 else 0.0
+
+
 def _ceil16(c):
     return (c + 15) // 16 * 16
 
@@ -53,7 +69,7 @@ def nn_lib():
         L.mpm_nn_up_bwd.argtypes = [vp, i, i, vp, i, i, i, i, i, i, i, vp]
         L.mpm_nn_down_dgrad.argtypes = [vp, i, i, vp, i, i, vp, i, i, i, i, i, i, i, vp]
         L.mpm_nn_to_bf16.argtypes = [vp, i, ll, i, vp, i, i, i, vp]
-        L.mpm_nn_masked_mse.argtypes = [vp, i, vp, vp, ll, i, f, vp, i, vp, i, vp]
+        L.mpm_nn_masked_mse.argtypes = [vp, i, vp, vp, ll, i, vp, i, vp, i, vp]
         L.mpm_nn_adam.argtypes = [vp, vp, vp, vp, ll, f, f, f, f, i, vp]
         L._nn_ready = True
     return L
@@ -172,14 +188,19 @@ class UNet:
                                self.stream)
         _chk(r, "conv " + name)
 
-    def forward(self, x32):
-        """x32: FP32 tensor [n, R, R, R, cin] on the device -> FP32 [n, R, R, R, cout]."""
+    def forward(self, x32, out=None):
+        """x32: FP32 tensor [n, R, R, R, >= cin channels] on the device -> FP32
+        [n, R, R, R, cout] (written into `out` when given, a contiguous tensor)."""
         n, R = x32.shape[0], x32.shape[1]
-        assert R % 4 == 0
+        assert R % 4 == 0 and x32.is_contiguous() and x32.shape[-1] >= self.cin
         b = self._alloc(n, R)
+        pred = b["pred"]
+        if out is not None:
+            assert out.is_contiguous() and tuple(out.shape) == (n, R, R, R, self.cout)
+            pred = out
         w = self.width
         c1, c2, c3 = 32 // w, 64 // w, 128 // w
-        _chk(self.L.mpm_nn_to_bf16(x32.data_ptr(), self.cin, n * R ** 3, self.cin, b["x"].ptr, b["x"].c, 0,
+        _chk(self.L.mpm_nn_to_bf16(x32.data_ptr(), x32.shape[-1], n * R ** 3, self.cin, b["x"].ptr, b["x"].c, 0,
                                    b["x"].c, self.stream), "to_bf16")
         self._conv("e1a", b["x"], 0, b["x"].c, b["a1"], 0)
         self._conv("e1b", b["a1"], 0, c1, b["cat1"], c1)
@@ -195,8 +216,8 @@ class UNet:
         self._conv("u1", b["a8"], 0, c2, b["cat1"], 0)
         self._conv("c1a", b["cat1"], 0, 2 * c1, b["a9"], 0)
         self._conv("c1b", b["a9"], 0, c1, b["a10"], 0)
-        self._conv("head", b["a10"], 0, c1, None, 0, b["pred"], self.cout)
-        return b["pred"]
+        self._conv("head", b["a10"], 0, c1, None, 0, pred, self.cout)
+        return pred
 
     # ------------------------------------------------------------------ backward
     def _wgrad(self, name, x: Act, x_off, cin, g: Act, g_off):
@@ -305,15 +326,15 @@ class UNet:
 
     # ------------------------------------------------------------------ training
     def loss_and_grad(self, pred, target, mask):
-        """Masked MSE on the device; writes the output gradient buffer."""
+        """Masked MSE on the device; writes the output gradient buffer.
+        Returns (loss handle, gradient); the handle's value() reads it back."""
         b = self._bufs
         n_vox = pred.shape[0] * pred.shape[1] * pred.shape[2] * pred.shape[3]
-        count = float(mask.sum().item()) * self.cout
-        parts = self.torch.zeros(1024, dtype=self.torch.float32, device=self.device)
-        _chk(self.L.mpm_nn_masked_mse(pred.data_ptr(), self.cout, target.data_ptr(), mask.data_ptr(), n_vox,
-                                      self.cout, 1.0 / max(count, 1.0), b["gpred"].ptr, b["gpred"].c,
-                                      parts.data_ptr(), 1024, self.stream), "masked_mse")
-        return parts.sum() / max(count, 1.0), b["gpred"]
+        parts = self.torch.zeros(NPARTS + 1, dtype=self.torch.float32, device=self.device)
+        _chk(self.L.mpm_nn_masked_mse(pred.data_ptr(), pred.shape[-1], target.data_ptr(), mask.data_ptr(), n_vox,
+                                      self.cout, b["gpred"].ptr, b["gpred"].c, parts.data_ptr(), NPARTS,
+                                      self.stream), "masked_mse")
+        return LossHandle(parts, self.cout), b["gpred"]
 
     def adam(self, lr=3e-4, b1=0.9, b2=0.999, eps=1e-8):
         self.step_t += 1

@@ -1,5 +1,5 @@
 """Host-side checks that need no GPU: the C-ABI library loads and exports
-every function include/mpm.h declares, and the seeded scene generators are
+every function the headers under include/ declare, and the seeded scene generators are
 reproducible and shaped like the workloads they stand for."""
 import os
 

@@ -328,11 +328,13 @@ def test_masked_mse_and_adam(nn):
     L, s = nn.nn_lib(), _stream()
     p_d, t_d, m_d = _f32_dev(pred), _f32_dev(tgt), _f32_dev(mask)
     g = torch.zeros((nv, 16), dtype=torch.int16, device="cuda")
-    parts = torch.zeros(64, dtype=torch.float32, device="cuda")
-    assert L.mpm_nn_masked_mse(p_d.data_ptr(), c, t_d.data_ptr(), m_d.data_ptr(), nv, c, 1.0 / count, g.data_ptr(),
+    parts = torch.zeros(65, dtype=torch.float32, device="cuda")
+    assert L.mpm_nn_masked_mse(p_d.data_ptr(), c, t_d.data_ptr(), m_d.data_ptr(), nv, c, g.data_ptr(),
                                16, parts.data_ptr(), 64, s) == 0
     torch.cuda.synchronize()
-    got_loss = float(parts.sum().item()) / count
+    hp = parts.cpu().numpy().astype(np.float64)
+    assert hp[64] == mask.sum()
+    got_loss = hp[:64].sum() / count
     assert abs(got_loss - loss) <= 1e-5 * loss
     gg = _from_bf16(g)
     assert np.all(gg[:, c:] == 0.0)
@@ -371,11 +373,16 @@ def _oracle_params(net):
 
 def test_network_forward_backward_vs_oracle(nn):
     """Whole U-Net against the oracle run with the same BF16 storage points
-    (tight bars: what is left is FP32-vs-FP64 accumulation and the rare BF16
-    rounding flip it causes), and against the exact FP64 network (forward
-    <= 2e-2; each gradient no further from it than 1.5x the BF16-storage
-    oracle's own distance + 5e-3: BF16 gradient storage alone moves the
-    deepest layers' gradients by ~1e-1 at this initialisation)."""
+    and against the exact FP64 network.  Forward: <= 2e-3 from the
+    BF16-storage oracle, <= 2e-2 from the exact one.  Gradients: BF16
+    storage of the backward signal alone moves the deepest layers'
+    gradients by ~1e-1 from the exact ones at this initialisation, and
+    FP32-vs-FP64 accumulation flips BF16 roundings, which the deep layers
+    amplify the same way; so each gradient must be closer to the
+    BF16-storage oracle than half that oracle's distance from exact
+    (+ 2e-3), and no further from exact than 1.5x that distance (+ 5e-3).
+    A wiring mistake (a lost skip gradient, a wrong ReLU mask) moves a
+    gradient by O(1)."""
     import torch
     announce("nn network width 2, 16^3 x 2")
     cin, cout, width, R, n = 8, 4, 2, 16, 2
@@ -406,7 +413,7 @@ def test_network_forward_backward_vs_oracle(nn):
     loss, g = net.loss_and_grad(pred, _f32_dev(tgt.reshape(-1, cout)), _f32_dev(mask.reshape(-1)))
     grads = net.backward(g)
     torch.cuda.synchronize()
-    assert abs(float(loss.item()) - loss_ref) <= 2e-2 * loss_ref
+    assert abs(loss.value() - loss_ref) <= 2e-2 * loss_ref
     bad = []
     for name, kind, ci, co, _ in net.layers:
         k = KS[kind]
@@ -422,6 +429,6 @@ def test_network_forward_backward_vs_oracle(nn):
             e_x = rel_l2(got_g[part], ref_grads[key])
             e_ox = rel_l2(q_grads[key], ref_grads[key])
             print(f"{key}: vs bf16-storage {e_q:.2e}  vs exact {e_x:.2e} (bf16-storage oracle vs exact {e_ox:.2e})")
-            if e_q > 2e-2 or e_x > 1.5 * e_ox + 5e-3:
+            if e_q > 0.5 * e_ox + 2e-3 or e_x > 1.5 * e_ox + 5e-3:
                 bad.append(key)
     assert not bad, bad

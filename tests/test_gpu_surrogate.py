@@ -1,0 +1,268 @@
+"""Surrogate support of the library (include/mpm.h, grid surrogate calls)
+and the per-scene stepping mask, through the C ABI.
+
+  * stepping mask: masked scenes stay bit-identical, stepped scenes match
+    the oracle (free-running bar, 1e-3 dx);
+  * features: mass / momentum channels and the start grid (m, p / m)
+    against the oracle's P2G (the P2G bars, 1e-6 / 1e-5), collider
+    channels against the oracle's SDF and the collider velocity;
+  * particle advance: closed form on a linear velocity field (APIC
+    reproduces it exactly, so x, v, C and F follow in closed form);
+  * residual gate: scenes over the threshold are put back and run the plain
+    substeps (oracle bar); scenes under it are untouched by the fallback;
+  * training targets: the definition on seeded arrays.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from gpu_util import announce, momentum_floor, random_state, rel_l2
+from paper_2302_04659_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+VEL = 0.2   # velocity unit of the surrogate's channels (m/s)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need the MI355X"
+    from paper_2302_04659_amd import mpm
+    mpm.lib()
+    return torch, mpm
+
+
+def _batch(n_scenes=3, res=32, colliders=True, n=3000, dt=1e-4):
+    return [scenes.small_scene(40 + s, n=n, res=res, model=scenes.HENCKY_VM, colliders=colliders, dt=dt,
+                               speed=0.3, n_ctrl=2) for s in range(n_scenes)]
+
+
+def _new_stream(torch):
+    """Library calls and torch buffer work of a test share one torch stream."""
+    return torch.cuda.Stream()
+
+
+def test_scene_mask_steps_only_active_scenes(env, orc):
+    torch, mpm = env
+    batch = _batch()
+    announce("scene mask", len(batch))
+    sim = mpm.Sim(batch)
+    sim.set_colliders_ctrl(0)
+    x0 = [sim.get_state(s) for s in range(len(batch))]
+    sim.set_scene_mask([1, 0, 1])
+    sim.step(25)
+    st = sim.sync()
+    assert st >= 0
+    for s, sc in enumerate(batch):
+        x, v, C, F = sim.get_state(s)
+        if s == 1:
+            for a, b in zip((x, v, C, F), x0[s]):
+                assert np.array_equal(a, b)
+        else:
+            o = orc.Oracle(sc)
+            o.set_colliders(sc.ctrl_poses[0], sc.ctrl_vels[0])
+            o.step(25)
+            assert np.abs(x - o.x).max() <= 1e-3 * sc.dx
+    # the complementary mask steps scene 1 alone
+    sim2 = mpm.Sim(batch)
+    sim2.set_colliders_ctrl(0)
+    sim2.set_scene_mask([0, 1, 0])
+    sim2.step(25)
+    assert sim2.sync() >= 0
+    sc = batch[1]
+    o = orc.Oracle(sc)
+    o.set_colliders(sc.ctrl_poses[0], sc.ctrl_vels[0])
+    o.step(25)
+    x, *_ = sim2.get_state(1)
+    assert np.abs(x - o.x).max() <= 1e-3 * sc.dx
+    sim2.close()
+    # all scenes again
+    sim.set_scene_mask(None)
+    sim.step(1)
+    sim.sync()
+    x1, *_ = sim.get_state(1)
+    assert not np.array_equal(x1, x0[1][0])
+    sim.close()
+
+
+def test_features_match_oracle(env, orc):
+    torch, mpm = env
+    batch = _batch()
+    announce("surrogate features", len(batch))
+    S, R = len(batch), batch[0].res
+    ts = _new_stream(torch)
+    sim = mpm.Sim(batch, stream=ts.cuda_stream)
+    states = []
+    for s, sc in enumerate(batch):
+        C, F = random_state(sc, 70 + s, c_scale=2.0, f_scale=0.05)
+        sim.set_state(sc.x, sc.v, C, F, scene=s)
+        states.append((C, F))
+    sim.set_colliders_ctrl(0)
+    with torch.cuda.stream(ts):
+        feat = torch.zeros((S, R, R, R, 12), dtype=torch.float32, device="cuda")
+        grid0 = torch.zeros((S, R, R, R, 4), dtype=torch.float32, device="cuda")
+        sim.sur_features(feat, grid0)
+    torch.cuda.synchronize()
+    assert sim.sync() >= 0
+    fh = feat.cpu().numpy().astype(np.float64)
+    gh = grid0.cpu().numpy().astype(np.float64)
+    assert np.all(fh[..., 8:] == 0.0)
+    for s, sc in enumerate(batch):
+        C, F = states[s]
+        o = orc.Oracle(sc, x=sc.x, v=sc.v, C=C, F=F)
+        o.set_colliders(sc.ctrl_poses[0], sc.ctrl_vels[0])
+        om, op = o.p2g()
+        mu = sc.rho * sc.dx ** 3
+        assert rel_l2(fh[s, ..., 0] * mu, om) <= 1e-6
+        floor = momentum_floor(sc, om.sum())
+        assert rel_l2(fh[s, ..., 1:4] * mu * VEL, op, floor) <= 1e-5
+        assert rel_l2(gh[s, ..., 0], om) <= 1e-6
+        assert np.all(gh[s, ..., 1:4][om == 0.0] == 0.0)
+        assert rel_l2(gh[s, ..., 0:1] * gh[s, ..., 1:4], op, floor) <= 1e-5     # v = p / m of the P2G
+        cols = [orc.make_collider(c, sc.ctrl_poses[0][k], sc.ctrl_vels[0][k]) for k, c in enumerate(sc.colliders)]
+        # collider channels
+        ii = np.stack(np.meshgrid(np.arange(R), np.arange(R), np.arange(R), indexing="ij"), -1).reshape(-1, 3)
+        rng = np.random.default_rng(s)
+        pick = rng.choice(ii.shape[0], 4000, replace=False)
+        for q in pick:
+            xi = ii[q] * sc.dx
+            phis = [orc.sdf(c, xi)[0] for c in cols]
+            k = int(np.argmin(phis))
+            phi = phis[k]
+            got = fh[s].reshape(-1, 12)[q]
+            assert abs(got[4] - np.clip(min(phi, 3 * sc.dx) / sc.dx, -3, 3)) <= 1e-4
+            ambiguous = abs(phi - 3 * sc.dx) < 1e-5 * sc.dx or (len(phis) > 1 and abs(phis[0] - phis[1]) < 1e-5 * sc.dx)
+            if ambiguous:
+                continue
+            if phi < 3 * sc.dx:
+                c = cols[k]
+                vc = np.array(c.vlin) + np.cross(np.array(c.omega), xi - np.array(c.pos))
+                assert np.abs(got[5:8] - vc / VEL).max() <= 1e-5
+            else:
+                assert np.all(got[5:8] == 0.0)
+    sim.close()
+
+
+def _linear_field_scene(seed):
+    sc = scenes.small_scene(seed, n=4000, res=32, model=scenes.NEO_HOOKEAN, colliders=False, dt=1e-4)
+    return dataclasses.replace(sc, gravity=(0.0, 0.0, 0.0))
+
+
+@pytest.mark.parametrize("u", [(0.0, 0.0, 0.0), (0.01, 0.02, -0.01)])
+def test_advance_reproduces_linear_field(env, u):
+    """v = v0 + A x, C = A, F = I, no gravity, colliders or walls in reach,
+    prediction dv = u everywhere: x' = x + T (v0 + A x + u/2),
+    v' = v0 + A x + u, C' = A, F' = I + T A."""
+    torch, mpm = env
+    batch = [_linear_field_scene(60), _linear_field_scene(61)]
+    announce("surrogate advance linear field u", u)
+    S, R = len(batch), batch[0].res
+    rng = np.random.default_rng(5)
+    v0 = np.array([0.05, -0.02, 0.03])
+    A = 0.5 * rng.normal(size=(3, 3))
+    ts = _new_stream(torch)
+    sim = mpm.Sim(batch, stream=ts.cuda_stream)
+    for s, sc in enumerate(batch):
+        x = sc.x.astype(np.float64)
+        v = v0 + x @ A.T
+        sim.set_state(sc.x, v.astype(np.float32), np.tile(A, (sc.n, 1, 1)).astype(np.float32),
+                      np.tile(np.eye(3), (sc.n, 1, 1)).astype(np.float32), scene=s)
+    with torch.cuda.stream(ts):
+        feat = torch.zeros((S, R, R, R, 8), dtype=torch.float32, device="cuda")
+        grid0 = torch.zeros((S, R, R, R, 4), dtype=torch.float32, device="cuda")
+        pred = torch.zeros((S, R, R, R, 4), dtype=torch.float32, device="cuda")
+        pred[..., 0:3] = torch.tensor(np.asarray(u) / VEL, dtype=torch.float32)
+        residual = torch.zeros(S, dtype=torch.float32, device="cuda")
+        nfb = torch.zeros(1, dtype=torch.int32, device="cuda")
+        sim.sur_features(feat, grid0)
+        sim.sur_block(pred, grid0, threshold=1e-3, fallback=False, residual=residual, n_fallback=nfb)
+    torch.cuda.synchronize()
+    assert sim.sync() >= 0
+    r = residual.cpu().numpy()
+    assert np.all(np.isfinite(r)) and np.all(r >= 0.0)
+    assert int(nfb.item()) == int((r > 1e-3).sum())
+    for s, sc in enumerate(batch):
+        T = 25 * sc.dt
+        x0 = sc.x.astype(np.float64)
+        x, v, C, F = sim.get_state(s)
+        vp = v0 + x0 @ A.T
+        x_exp = x0 + T * (vp + 0.5 * np.asarray(u))
+        assert np.abs(x - x_exp).max() <= 1e-5 * sc.dx
+        assert np.abs(v - (vp + np.asarray(u))).max() <= 1e-5 * np.abs(vp).max()
+        assert np.abs(C - A).max() <= 1e-3 * np.abs(A).max()
+        assert np.abs(F - (np.eye(3) + T * A)).max() <= 1e-5
+    sim.close()
+
+
+def test_residual_gate_falls_back_per_scene(env, orc):
+    """Scene 1 gets a wild prediction and falls back (plain substeps, oracle
+    bar); scenes 0 and 2 stay on the surrogate, bit-identical to a second
+    context given the same start grid and prediction with the fallback
+    switched off (the particle advance is deterministic)."""
+    torch, mpm = env
+    batch = _batch()
+    announce("surrogate residual gate", len(batch))
+    S, R = len(batch), batch[0].res
+    ts = _new_stream(torch)
+    with torch.cuda.stream(ts):
+        feat = torch.zeros((S, R, R, R, 8), dtype=torch.float32, device="cuda")
+        grid0 = torch.zeros((S, R, R, R, 4), dtype=torch.float32, device="cuda")
+        pred = torch.zeros((S, R, R, R, 4), dtype=torch.float32, device="cuda")
+        pred[1, ..., 3] = 50.0                     # a mass change no re-splat can match
+    outs = []
+    for fallback in (True, False):
+        sim = mpm.Sim(batch, stream=ts.cuda_stream)
+        sim.set_colliders_ctrl(0)
+        with torch.cuda.stream(ts):
+            residual = torch.zeros(S, dtype=torch.float32, device="cuda")
+            nfb = torch.zeros(1, dtype=torch.int32, device="cuda")
+            if fallback:
+                sim.sur_features(feat, grid0)
+            sim.sur_block(pred, grid0, threshold=10.0, fallback=fallback, residual=residual, n_fallback=nfb)
+        torch.cuda.synchronize()
+        assert sim.sync() >= 0
+        r = residual.cpu().numpy()
+        print("fallback", fallback, "residuals", r)
+        assert r[1] > 10.0 and r[0] <= 10.0 and r[2] <= 10.0
+        assert int(nfb.item()) == 1
+        outs.append([sim.get_state(s) for s in range(S)])
+        sim.close()
+    with_fb, without = outs
+    for s in (0, 2):
+        for a, b in zip(with_fb[s], without[s]):
+            assert np.array_equal(a, b)
+    sc = batch[1]
+    o = orc.Oracle(sc)
+    o.set_colliders(sc.ctrl_poses[0], sc.ctrl_vels[0])
+    o.step(25)
+    x = with_fb[1][0]
+    assert np.abs(x - o.x).max() <= 1e-3 * sc.dx
+
+
+def test_targets_definition(env):
+    torch, mpm = env
+    batch = _batch(n_scenes=2, colliders=False, n=500)
+    announce("surrogate targets")
+    S, R = len(batch), batch[0].res
+    ts = _new_stream(torch)
+    sim = mpm.Sim(batch, stream=ts.cuda_stream)
+    rng = np.random.default_rng(3)
+    g0 = rng.normal(size=(S, R, R, R, 4)).astype(np.float32)
+    g1 = rng.normal(size=(S, R, R, R, 4)).astype(np.float32)
+    g0[..., 0] = np.where(rng.random((S, R, R, R)) < 0.5, 0.0, np.abs(g0[..., 0]))
+    g1[..., 0] = np.where(rng.random((S, R, R, R)) < 0.5, 0.0, np.abs(g1[..., 0]))
+    with torch.cuda.stream(ts):
+        t = torch.zeros((S, R, R, R, 4), dtype=torch.float32, device="cuda")
+        m = torch.zeros((S, R, R, R), dtype=torch.float32, device="cuda")
+        sim.sur_targets(torch.tensor(g0).cuda(), torch.tensor(g1).cuda(), t, m)
+    torch.cuda.synchronize()
+    th, mh = t.cpu().numpy().astype(np.float64), m.cpu().numpy()
+    a, b = g0.astype(np.float64), g1.astype(np.float64)
+    for s, sc in enumerate(batch):
+        mu = sc.rho * sc.dx ** 3
+        assert np.allclose(th[s, ..., :3], (b[s, ..., 1:4] - a[s, ..., 1:4]) / VEL, rtol=1e-6, atol=1e-6)
+        assert np.allclose(th[s, ..., 3], (b[s, ..., 0] - a[s, ..., 0]) / mu, rtol=1e-5, atol=1e-3)
+        assert np.array_equal(mh[s], ((a[s, ..., 0] > 0) | (b[s, ..., 0] > 0)).astype(np.float32))
+    sim.close()
