@@ -102,12 +102,15 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="grid block edge (0 = library default / autotuned)")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--sort-every", type=int, default=0)
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the library defaults (block 4, chunk 2048, re-sort every 25) unless given")
     ap.add_argument("--graph", type=int, default=-1)
     ap.add_argument("--persistent", type=int, default=-1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-scenes", type=int, default=64)
     ap.add_argument("--cpu-substeps", type=int, default=50)
+    ap.add_argument("--train-steps", type=int, default=400, help="cfg5: surrogate training steps")
+    ap.add_argument("--eval-scenes", type=int, default=64, help="cfg5: held-out scenes timed")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed region, run a plain device-to-device copy of this many MiB three "
                          "times (the reference kernel for scaling HBM byte counters)")
@@ -121,6 +124,8 @@ def main():
     from paper_2302_04659_amd import mpm
     assert torch.cuda.is_available(), "needs the MI355X"
     torch.cuda.set_device(0)
+    if args.workload == "cfg5":
+        return bench_surrogate(args)
 
     scene_list, desc = workload(args.workload)
     sim = mpm.Sim(scene_list)
@@ -138,7 +143,7 @@ def main():
     if args.persistent >= 0:
         sim.set_option(mpm.OPT_PERSISTENT, args.persistent)
     tune = None
-    if args.autotune:
+    if args.autotune and not (args.block or args.chunk or args.sort_every):
         tune = sim.autotune(10)
 
     ctrl = [0]
@@ -223,6 +228,105 @@ def main():
         out["cpu_baseline"] = cpu_baseline(scene_list, min(args.cpu_scenes, len(scene_list)), args.cpu_substeps)
     print(json.dumps(out), flush=True)
     sim.close()
+
+
+def unet_forward_flop(R: int, cin: int = 8, cout: int = 4, width: int = 1) -> float:
+    """Multiply-add FLOPs (2 per MAC) of one U-Net forward on an R^3 grid."""
+    from paper_2302_04659_amd.unet import LAYERS, TAPS
+    flop = 0.0
+    for name, kind, ci, co, _ in LAYERS:
+        ci = cin if ci is None else ci // width
+        co = cout if co is None else co // width
+        vox = {"e1": R, "d1": R // 2, "e2": R // 2, "d2": R // 4, "e3": R // 4, "u2": R // 2, "c2": R // 2,
+               "u1": R, "c1": R, "he": R}[name[:2]] ** 3
+        flop += 2.0 * vox * TAPS[kind] * ci * co
+    return flop
+
+
+def bench_surrogate(args):
+    """cfg5: the grid U-Net surrogate with residual gate and fallback against
+    plain batched MPM on held-out slab-pushing scenes, one control step
+    (25 substeps) at a time."""
+    import numpy as np
+    import torch
+    from paper_2302_04659_amd import mpm, scenes, surrogate, unet
+    t_start = time.perf_counter()
+    train_scenes = [scenes.cfg2(seed=s) for s in range(16)]
+    data = surrogate.RolloutData(train_scenes, n_blocks=8)
+    net = unet.UNet(cin=surrogate.CIN, cout=surrogate.COUT, width=1, seed=0)
+    t0 = time.perf_counter()
+    log = surrogate.train(net, data, steps=args.train_steps, batch=8, lr=1e-3, log_every=max(args.train_steps // 4, 1))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del data
+    ev = [scenes.cfg2(seed=2000 + s) for s in range(args.eval_scenes)]
+    n_blocks = 4
+    # plain batched MPM (graph replay of 25-substep blocks)
+    plain = mpm.Sim(ev)
+    plain.set_option(mpm.OPT_GRAPH, 1)
+    plain.set_colliders_ctrl(0)
+    plain.step(25)
+    plain.sync()
+    t0 = time.perf_counter()
+    for b in range(1, n_blocks + 1):
+        plain.set_colliders_ctrl(b)
+        plain.step(25)
+    plain.sync()
+    t_plain = (time.perf_counter() - t0) / n_blocks
+    plain.close()
+    # surrogate with the residual gate and per-scene fallback
+    sim = surrogate.make_sim(ev)
+    sim.set_option(mpm.OPT_GRAPH, 1)
+    gs = surrogate.GridSurrogate(sim, net, threshold=1e-3, chunk=16)
+    sim.set_colliders_ctrl(0)
+    gs.block()
+    torch.cuda.synchronize()
+    fb = 0
+    t0 = time.perf_counter()
+    for b in range(1, n_blocks + 1):
+        sim.set_colliders_ctrl(b)
+        gs.block()
+        fb += int(gs.n_fallback.item())
+    torch.cuda.synchronize()
+    t_sur = (time.perf_counter() - t0) / n_blocks
+    st = sim.sync()
+    # the network alone, timed with events on its stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(gs.ts):
+        ev0.record()
+        gs.predict()
+        ev1.record()
+    torch.cuda.synchronize()
+    t_net = ev0.elapsed_time(ev1) * 1e-3
+    flop = unet_forward_flop(ev[0].res) * len(ev)
+    sim.close()
+    out = {
+        "metric": "surrogate+fallback speedup over plain batched MPM (one control step)",
+        "value": t_plain / t_sur,
+        "unit": "x",
+        "n_gpus": 1,
+        "steps": n_blocks * 25,
+        "warmup": 25,
+        "ms_per_step": t_sur * 1e3 / 25,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"cfg5: grid U-Net (3 levels, 32/64/128, 3^3 convs) trained {args.train_steps} steps "
+                               f"on 16 cfg2 rollouts x 8 control steps; timed on {len(ev)} held-out cfg2 scenes "
+                               f"(65,536 particles, 64^3 each), threshold 1e-3",
+                   "scenes": len(ev), "particles": int(sum(sc.n for sc in ev))},
+        "plain_ms_per_control_step": t_plain * 1e3,
+        "surrogate_ms_per_control_step": t_sur * 1e3,
+        "fallback_fraction": fb / (n_blocks * len(ev)),
+        "status": int(st),
+        "train": {"steps": args.train_steps, "seconds": t_train, "log": log},
+        "roofline": {"bound": "mfma", "kernel": "U-Net forward (all convolutions)", "achieved": flop / t_net / 1e12,
+                     "peak": 2500.0, "unit": "TFLOP/s", "frac": flop / t_net / 1e12 / 2500.0, "traffic": None},
+        "wall_s": time.perf_counter() - t_start,
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -200,7 +200,8 @@ mpm_status mpm_set_scene_mask(mpm_ctx ctx, const int *active);
  * control step), with the plain substeps above as the per-scene fallback.
  * All scenes must share one grid resolution R; every pointer is a device
  * pointer on the context's device; work is queued on the context stream.
- * Units: velocities in 0.2 m/s, masses in rho dx^3 of the scene. */
+ * Units: velocities in 0.2 m/s, masses in rho dx^3 of the scene, predicted
+ * mass changes in rho dx^3 / 32. */
 
 /* Network input and start grid of the current state at the current
  * collider poses: a P2G and grid update (the state is not changed).
@@ -236,8 +237,8 @@ mpm_status mpm_sur_block(mpm_ctx ctx, const float *pred, int cp, const float *gr
 
 /* Training targets between the start grids g0, g1 of two consecutive
  * control steps (both from mpm_sur_features): target [n][R^3][ct] (ct >= 4)
- * = ((v1 - v0) in 0.2 m/s, (m1 - m0) in rho dx^3), mask [n][R^3] = 1 where
- * m0 > 0 or m1 > 0, else 0. */
+ * = ((v1 - v0) in 0.2 m/s, (m1 - m0) in rho dx^3 / 32), mask [n][R^3] = 1
+ * where m0 > 0 or m1 > 0, else 0. */
 mpm_status mpm_sur_targets(mpm_ctx ctx, const float *g0, const float *g1, float *target, int ct, float *mask);
 
 /* Introspection. */

@@ -9,6 +9,8 @@ namespace mpm {
 
 constexpr int WG = 256;
 constexpr float SUR_VEL = 0.2f;   // velocity unit of the surrogate's inputs and outputs (m/s)
+constexpr float SUR_DM = 1.0f / 32.0f;   // unit of the predicted mass change, in rho dx^3 (a change over one
+                                         // control step is ~1e-3 rho dx^3; this unit brings it to O(1e-2))
 
 __device__ __forceinline__ int xcd_remap(int b, int G)
 {

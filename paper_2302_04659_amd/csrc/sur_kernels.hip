@@ -255,7 +255,7 @@ __global__ __launch_bounds__(WG) void k_sur_residual(StepArgs a, int res, const 
     const long long c0 = (long long)blockIdx.x * RES_CHUNK;
     const int s = (int)(c0 / R3);
     const SceneDev &S = a.scenes[s];
-    const float mu = S.mass / S.vol * S.dx * S.dx * S.dx;   // rho dx^3
+    const float mu = S.mass / S.vol * S.dx * S.dx * S.dx * SUR_DM;   // mass unit of the prediction
     float sm = 0.0f, sp = 0.0f, m0 = 0.0f, p0 = 0.0f;
     for (int q = threadIdx.x; q < RES_CHUNK; q += WG) {
         const long long c = c0 + q;
@@ -343,14 +343,14 @@ hipError_t launch_sur_restore(const float *Psnap, float *P, long long pstride, c
 }
 
 // Training targets from the start grids of two consecutive control steps:
-// target = ((v1 - v0) / vel unit, (m1 - m0) / (rho dx^3)), mask = m0 > 0 or m1 > 0.
+// target = ((v1 - v0) / vel unit, (m1 - m0) / mass-change unit), mask = m0 > 0 or m1 > 0.
 __global__ __launch_bounds__(WG) void k_sur_targets(StepArgs a, int res, const float *g0, const float *g1, int ct,
                                                     float *target, float *mask)
 {
     const long long R3 = (long long)res * res * res, total = R3 * a.n_scenes;
     for (long long e = (long long)blockIdx.x * WG + threadIdx.x; e < total; e += (long long)gridDim.x * WG) {
         const SceneDev &S = a.scenes[e / R3];
-        const float inv_mu = S.vol / (S.mass * S.dx * S.dx * S.dx);
+        const float inv_mu = S.vol / (S.mass * S.dx * S.dx * S.dx * SUR_DM);
         const float4 u = *(const float4 *)(g0 + 4 * e);
         const float4 w = *(const float4 *)(g1 + 4 * e);
         float *tp = target + e * ct;

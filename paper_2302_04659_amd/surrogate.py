@@ -17,6 +17,7 @@ slab-pushing workload (seeded scenes), generated on the device.
 """
 from __future__ import annotations
 
+import sys
 import time
 from typing import Dict, List, Optional, Sequence
 
@@ -166,7 +167,7 @@ def train(net: UNet, data: RolloutData, steps: int, batch: int = 8, lr: float = 
             if holdout is not None:
                 rec["holdout_loss"] = evaluate_loss(net, holdout, batch)
             log.append(rec)
-            print("[train]", rec, flush=True)
+            print("[train]", rec, file=sys.stderr, flush=True)
     return log
 
 

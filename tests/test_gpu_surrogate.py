@@ -210,7 +210,7 @@ def test_residual_gate_falls_back_per_scene(env, orc):
         feat = torch.zeros((S, R, R, R, 8), dtype=torch.float32, device="cuda")
         grid0 = torch.zeros((S, R, R, R, 4), dtype=torch.float32, device="cuda")
         pred = torch.zeros((S, R, R, R, 4), dtype=torch.float32, device="cuda")
-        pred[1, ..., 3] = 50.0                     # a mass change no re-splat can match
+        pred[1, ..., 3] = 1600.0                   # a mass change (50 rho dx^3) no re-splat can match
     outs = []
     for fallback in (True, False):
         sim = mpm.Sim(batch, stream=ts.cuda_stream)
@@ -261,8 +261,8 @@ def test_targets_definition(env):
     th, mh = t.cpu().numpy().astype(np.float64), m.cpu().numpy()
     a, b = g0.astype(np.float64), g1.astype(np.float64)
     for s, sc in enumerate(batch):
-        mu = sc.rho * sc.dx ** 3
+        mu = sc.rho * sc.dx ** 3 / 32.0          # unit of the mass change
         assert np.allclose(th[s, ..., :3], (b[s, ..., 1:4] - a[s, ..., 1:4]) / VEL, rtol=1e-6, atol=1e-6)
-        assert np.allclose(th[s, ..., 3], (b[s, ..., 0] - a[s, ..., 0]) / mu, rtol=1e-5, atol=1e-3)
+        assert np.allclose(th[s, ..., 3], (b[s, ..., 0] - a[s, ..., 0]) / mu, rtol=1e-5, atol=3e-2)
         assert np.array_equal(mh[s], ((a[s, ..., 0] > 0) | (b[s, ..., 0] > 0)).astype(np.float32))
     sim.close()
