@@ -196,6 +196,15 @@ __global__ __launch_bounds__(WG) void k_scan_emit(SortArgs a)
     }
 }
 
+// Inside its bin a particle's slot is scrambled (local rank r -> r * 104729 mod
+// bin size, a bijection unless the prime divides the size, which then keeps
+// r), so a bin's
+// particles end up in an order unrelated to space: consecutive lanes of a
+// P2G wave then land on distant cells, and their LDS atomics rarely collide
+// on an address or a bank.  (In the order of the previous sort they arrive
+// clustered cell by cell.)
+constexpr long long BIN_SCRAMBLE = 104729;   // prime
+
 __global__ __launch_bounds__(WG) void k_scatter(SortArgs a)
 {
     const int j = blockIdx.x * WG + threadIdx.x;
@@ -206,9 +215,15 @@ __global__ __launch_bounds__(WG) void k_scatter(SortArgs a)
     int old = 0;
     if (valid && r.head_lane == lane) old = atomicSub(&a.count[key], r.len);
     old = __shfl(old, r.head_lane, 64);
-    // the run takes the slots [start + old - len, start + old) in lane order
+    // the run takes the local ranks [old - len, old) in lane order
     const int len = __shfl(r.len, r.head_lane, 64);
-    if (valid) a.perm[a.pstart[key] + old - len + (lane - r.head_lane)] = j;
+    if (valid) {
+        const int b0 = a.pstart[key];
+        const int size = ((int)key + 1 < a.T ? a.pstart[key + 1] : a.N) - b0;
+        const int local = old - len + (lane - r.head_lane);
+        const long long mul = (size % BIN_SCRAMBLE) ? BIN_SCRAMBLE : 1;   // a bijection for any size
+        a.perm[b0 + (int)(((long long)local * mul) % size)] = j;
+    }
 }
 
 __global__ __launch_bounds__(WG) void k_gather(SortArgs a)

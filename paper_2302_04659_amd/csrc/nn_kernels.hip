@@ -61,52 +61,7 @@ __device__ __forceinline__ bool tap_source(int kind, int z, int y, int x, int a,
 
 // ---------------------------------------------------------------- convolution (forward / dgrad)
 // One wave computes 64 consecutive output voxels (4 row fragments) x 16 NF
-// output channels.  The K loop runs over (tap, 16-channel chunk) steps; the
-// operands of step s + 1 are loaded while the MFMAs of step s run.
-template <int NF>
-struct ConvOps {
-    s4 A[4];
-    s4 B[NF];
-};
-
-__device__ __forceinline__ s4 unpack4(uint2 raw)
-{
-    return s4{(short)(raw.x & 0xffff), (short)(raw.x >> 16), (short)(raw.y & 0xffff), (short)(raw.y >> 16)};
-}
-
-template <int NF>
-__device__ __forceinline__ void conv_load(const ConvArgs &a, int step, int kc, int ks, int lane, const int vz[4],
-                                          const int vy[4], const int vx[4], const int vn[4], const bool vok[4],
-                                          ConvOps<NF> &op)
-{
-    const int t = step / kc, c = step - t * kc;
-    const int ta = t / (ks * ks), tb = (t / ks) % ks, tc = t % ks;
-    const int kq = 4 * (lane >> 4);
-#pragma unroll
-    for (int f = 0; f < 4; f++) {
-        int sz, sy, sx;
-        const bool ok = vok[f] && tap_source(a.kind, vz[f], vy[f], vx[f], ta, tb, tc, a.id, a.ih, a.iw, sz, sy, sx);
-        if (ok) {
-            const long long src = ((((long long)vn[f] * a.id + sz) * a.ih + sy) * a.iw + sx) * a.cx + a.x_off + kq + 16 * c;
-            op.A[f] = unpack4(*(const uint2 *)(a.x + src));
-        } else {
-            op.A[f] = s4{0, 0, 0, 0};
-        }
-    }
-    const uint16_t *wt = a.w + ((size_t)step * NF) * 256 + 4 * lane;
-#pragma unroll
-    for (int n = 0; n < NF; n++) op.B[n] = unpack4(*(const uint2 *)(wt + (size_t)n * 256));
-}
-
-template <int NF>
-__device__ __forceinline__ void conv_mfma(const ConvOps<NF> &op, f4 (&acc)[4][NF])
-{
-#pragma unroll
-    for (int n = 0; n < NF; n++)
-#pragma unroll
-        for (int f = 0; f < 4; f++) acc[f][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(op.A[f], op.B[n], acc[f][n], 0, 0, 0);
-}
-
+// output channels.
 template <int NF>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
 {
@@ -118,7 +73,6 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
     const int ks = ksize(a.kind);
     const int ntap = ks * ks * ks;
     const int kc = a.cin / 16;
-    const int nsteps = ntap * kc;
     f4 acc[4][NF];
 #pragma unroll
     for (int f = 0; f < 4; f++)
@@ -139,14 +93,36 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
         vz[f] = (int)(r % a.od);
         vn[f] = (int)(r / a.od);
     }
-    ConvOps<NF> op0, op1;
-    conv_load<NF>(a, 0, kc, ks, lane, vz, vy, vx, vn, vok, op0);
-    for (int step = 0; step < nsteps; step += 2) {
-        if (step + 1 < nsteps) conv_load<NF>(a, step + 1, kc, ks, lane, vz, vy, vx, vn, vok, op1);
-        conv_mfma<NF>(op0, acc);
-        if (step + 1 < nsteps) {
-            if (step + 2 < nsteps) conv_load<NF>(a, step + 2, kc, ks, lane, vz, vy, vx, vn, vok, op0);
-            conv_mfma<NF>(op1, acc);
+    const int kq = 4 * (lane >> 4);          // this lane's first K element within a fragment
+    for (int t = 0; t < ntap; t++) {
+        const int ta = t / (ks * ks), tb = (t / ks) % ks, tc = t % ks;
+        long long src[4];
+        bool ok[4];
+#pragma unroll
+        for (int f = 0; f < 4; f++) {
+            int sz, sy, sx;
+            ok[f] = vok[f] && tap_source(a.kind, vz[f], vy[f], vx[f], ta, tb, tc, a.id, a.ih, a.iw, sz, sy, sx);
+            src[f] = ok[f] ? ((((long long)vn[f] * a.id + sz) * a.ih + sy) * a.iw + sx) * a.cx + a.x_off + kq : 0;
+        }
+        const uint16_t *wt = a.w + (size_t)t * kc * NF * 256;
+        for (int c = 0; c < kc; c++) {
+            s4 A[4];
+#pragma unroll
+            for (int f = 0; f < 4; f++) {
+                if (ok[f]) {
+                    const uint2 raw = *(const uint2 *)(a.x + src[f] + 16 * c);
+                    A[f] = s4{(short)(raw.x & 0xffff), (short)(raw.x >> 16), (short)(raw.y & 0xffff), (short)(raw.y >> 16)};
+                } else {
+                    A[f] = s4{0, 0, 0, 0};
+                }
+            }
+#pragma unroll
+            for (int n = 0; n < NF; n++) {
+                const uint2 raw = *(const uint2 *)(wt + ((size_t)c * NF + n) * 256 + 4 * lane);
+                const s4 Bv = s4{(short)(raw.x & 0xffff), (short)(raw.x >> 16), (short)(raw.y & 0xffff), (short)(raw.y >> 16)};
+#pragma unroll
+                for (int f = 0; f < 4; f++) acc[f][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[f], Bv, acc[f][n], 0, 0, 0);
+            }
         }
     }
     // epilogue: D[i][j] -> voxel v0 + 16 f + 4 (lane/16) + r, channel 16 n + lane % 16

@@ -155,26 +155,28 @@ class UNet:
         self.repack()
 
     # ------------------------------------------------------------------ buffers
-    def _alloc(self, n, R):
-        key = (n, R)
+    def _alloc(self, n, shape):
+        key = (n,) + tuple(shape)
         if self._bufs is not None and self._bufs["key"] == key:
             return self._bufs
         torch, dev, w = self.torch, self.device, self.width
         c1, c2, c3 = 32 // w, 64 // w, 128 // w
-        R2, R4 = R // 2, R // 4
-        A = lambda r, c: Act(torch, n, r, r, r, c, dev)
+        L1 = tuple(shape)
+        L2 = tuple(d // 2 for d in shape)
+        L3 = tuple(d // 4 for d in shape)
+        A = lambda lv, c: Act(torch, n, lv[0], lv[1], lv[2], c, dev)
         b = {"key": key}
-        b["x"] = A(R, _ceil16(self.cin))
-        b["a1"], b["cat1"], b["a2"], b["a3"] = A(R, c1), A(R, 2 * c1), A(R2, c2), A(R2, c2)
-        b["cat2"], b["a4"], b["a5"], b["a6"] = A(R2, 2 * c2), A(R4, c3), A(R4, c3), A(R4, c3)
-        b["a7"], b["a8"], b["a9"], b["a10"] = A(R2, c2), A(R2, c2), A(R, c1), A(R, c1)
-        b["pred"] = torch.zeros((n, R, R, R, self.cout), dtype=torch.float32, device=dev)
+        b["x"] = A(L1, _ceil16(self.cin))
+        b["a1"], b["cat1"], b["a2"], b["a3"] = A(L1, c1), A(L1, 2 * c1), A(L2, c2), A(L2, c2)
+        b["cat2"], b["a4"], b["a5"], b["a6"] = A(L2, 2 * c2), A(L3, c3), A(L3, c3), A(L3, c3)
+        b["a7"], b["a8"], b["a9"], b["a10"] = A(L2, c2), A(L2, c2), A(L1, c1), A(L1, c1)
+        b["pred"] = torch.zeros((n,) + L1 + (self.cout,), dtype=torch.float32, device=dev)
         # gradients
-        b["gpred"] = A(R, 16)
-        b["g10"], b["g9"], b["gcat1"], b["gf1"] = A(R, c1), A(R, c1), A(R, 2 * c1), A(R, c2)
-        b["g8"], b["g7"], b["gcat2"], b["gf2"] = A(R2, c2), A(R2, c2), A(R2, 2 * c2), A(R2, c3)
-        b["g6"], b["g5"], b["g4"], b["g3"], b["g2"], b["g1"] = (A(R4, c3), A(R4, c3), A(R4, c3), A(R2, c2),
-                                                               A(R2, c2), A(R, c1))
+        b["gpred"] = A(L1, 16)
+        b["g10"], b["g9"], b["gcat1"], b["gf1"] = A(L1, c1), A(L1, c1), A(L1, 2 * c1), A(L1, c2)
+        b["g8"], b["g7"], b["gcat2"], b["gf2"] = A(L2, c2), A(L2, c2), A(L2, 2 * c2), A(L2, c3)
+        b["g6"], b["g5"], b["g4"], b["g3"], b["g2"], b["g1"] = (A(L3, c3), A(L3, c3), A(L3, c3), A(L2, c2),
+                                                               A(L2, c2), A(L1, c1))
         self._bufs = b
         return b
 
@@ -189,18 +191,20 @@ class UNet:
         _chk(r, "conv " + name)
 
     def forward(self, x32, out=None):
-        """x32: FP32 tensor [n, R, R, R, >= cin channels] on the device -> FP32
-        [n, R, R, R, cout] (written into `out` when given, a contiguous tensor)."""
-        n, R = x32.shape[0], x32.shape[1]
-        assert R % 4 == 0 and x32.is_contiguous() and x32.shape[-1] >= self.cin
-        b = self._alloc(n, R)
+        """x32: FP32 tensor [n, D, H, W, >= cin channels] on the device (D, H, W
+        multiples of 4) -> FP32 [n, D, H, W, cout] (written into `out` when
+        given, a contiguous tensor)."""
+        n, shape = x32.shape[0], tuple(x32.shape[1:4])
+        assert all(d % 4 == 0 for d in shape) and x32.is_contiguous() and x32.shape[-1] >= self.cin
+        nvox = n * shape[0] * shape[1] * shape[2]
+        b = self._alloc(n, shape)
         pred = b["pred"]
         if out is not None:
-            assert out.is_contiguous() and tuple(out.shape) == (n, R, R, R, self.cout)
+            assert out.is_contiguous() and tuple(out.shape) == (n,) + shape + (self.cout,)
             pred = out
         w = self.width
         c1, c2, c3 = 32 // w, 64 // w, 128 // w
-        _chk(self.L.mpm_nn_to_bf16(x32.data_ptr(), x32.shape[-1], n * R ** 3, self.cin, b["x"].ptr, b["x"].c, 0,
+        _chk(self.L.mpm_nn_to_bf16(x32.data_ptr(), x32.shape[-1], nvox, self.cin, b["x"].ptr, b["x"].c, 0,
                                    b["x"].c, self.stream), "to_bf16")
         self._conv("e1a", b["x"], 0, b["x"].c, b["a1"], 0)
         self._conv("e1b", b["a1"], 0, c1, b["cat1"], c1)

@@ -71,3 +71,16 @@ def test_cfg4_heap_shape():
     assert s.n == 1048576 and s.res == 128 and s.n_colliders == 3
     r = np.linalg.norm(s.x.astype(np.float64) - [0.5, 3 / 128, 0.5], axis=1)
     assert r.max() <= 0.311 and (s.x[:, 1] >= 3 / 128 - 1e-6).all()
+
+
+def test_bin_scramble_multiplier_is_prime():
+    """The sort places the r-th particle of a bin at r * M mod size (or r when
+    M divides size): a bijection for every size exactly when M is prime."""
+    import re
+    src = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "paper_2302_04659_amd", "csrc", "mpm_kernels.hip")).read()
+    M = int(re.search(r"BIN_SCRAMBLE\s*=\s*(\d+)", src).group(1))
+    assert M > 2 and all(M % d for d in range(2, int(M ** 0.5) + 1))
+    for size in (1, 2, 3, 63, 64, 512, 4097, M, 2 * M):
+        mul = M if size % M else 1
+        assert len(set((r * mul) % size for r in range(size))) == size
