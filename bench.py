@@ -109,8 +109,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-scenes", type=int, default=64)
     ap.add_argument("--cpu-substeps", type=int, default=50)
-    ap.add_argument("--train-steps", type=int, default=400, help="cfg5: surrogate training steps")
-    ap.add_argument("--eval-scenes", type=int, default=64, help="cfg5: held-out scenes timed")
+    ap.add_argument("--train-steps", type=int, default=1500, help="cfg5: surrogate training steps")
+    ap.add_argument("--eval-scenes", type=int, default=256, help="cfg5: held-out scenes timed")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed region, run a plain device-to-device copy of this many MiB three "
                          "times (the reference kernel for scaling HBM byte counters)")
@@ -230,15 +230,16 @@ def main():
     sim.close()
 
 
-def unet_forward_flop(R: int, cin: int = 8, cout: int = 4, width: int = 1) -> float:
-    """Multiply-add FLOPs (2 per MAC) of one U-Net forward on an R^3 grid."""
+def unet_forward_flop(shape, cin: int = 8, cout: int = 4, width: int = 1) -> float:
+    """Multiply-add FLOPs (2 per MAC) of one U-Net forward on a (D, H, W) grid."""
     from paper_2302_04659_amd.unet import LAYERS, TAPS
+    D, H, W = shape
+    level = {"e1": 1, "d1": 8, "e2": 8, "d2": 64, "e3": 64, "u2": 8, "c2": 8, "u1": 1, "c1": 1, "he": 1}
     flop = 0.0
     for name, kind, ci, co, _ in LAYERS:
         ci = cin if ci is None else ci // width
         co = cout if co is None else co // width
-        vox = {"e1": R, "d1": R // 2, "e2": R // 2, "d2": R // 4, "e3": R // 4, "u2": R // 2, "c2": R // 2,
-               "u1": R, "c1": R, "he": R}[name[:2]] ** 3
+        vox = D * H * W / level[name[:2]]
         flop += 2.0 * vox * TAPS[kind] * ci * co
     return flop
 
@@ -253,6 +254,7 @@ def bench_surrogate(args):
     t_start = time.perf_counter()
     train_scenes = [scenes.cfg2(seed=s) for s in range(16)]
     data = surrogate.RolloutData(train_scenes, n_blocks=8)
+    train_shape = data.shape
     net = unet.UNet(cin=surrogate.CIN, cout=surrogate.COUT, width=1, seed=0)
     t0 = time.perf_counter()
     log = surrogate.train(net, data, steps=args.train_steps, batch=8, lr=1e-3, log_every=max(args.train_steps // 4, 1))
@@ -274,31 +276,44 @@ def bench_surrogate(args):
     plain.sync()
     t_plain = (time.perf_counter() - t0) / n_blocks
     plain.close()
-    # surrogate with the residual gate and per-scene fallback
-    sim = surrogate.make_sim(ev)
-    sim.set_option(mpm.OPT_GRAPH, 1)
-    gs = surrogate.GridSurrogate(sim, net, threshold=1e-3, chunk=16)
-    sim.set_colliders_ctrl(0)
-    gs.block()
-    torch.cuda.synchronize()
-    fb = 0
-    t0 = time.perf_counter()
-    for b in range(1, n_blocks + 1):
-        sim.set_colliders_ctrl(b)
-        gs.block()
-        fb += int(gs.n_fallback.item())
-    torch.cuda.synchronize()
-    t_sur = (time.perf_counter() - t0) / n_blocks
-    st = sim.sync()
-    # the network alone, timed with events on its stream
+
+    def run_surrogate(threshold, fallback=True):
+        sim = surrogate.make_sim(ev)
+        sim.set_option(mpm.OPT_GRAPH, 1)
+        gs = surrogate.GridSurrogate(sim, net, threshold=threshold, chunk=16)
+        sim.set_colliders_ctrl(0)
+        gs.block(fallback=fallback)
+        torch.cuda.synchronize()
+        fb, res = 0, []
+        t0 = time.perf_counter()
+        for b in range(1, n_blocks + 1):
+            sim.set_colliders_ctrl(b)
+            gs.block(fallback=fallback)
+            fb += int(gs.n_fallback.item())
+            res.append(gs.residual.cpu().numpy())
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / n_blocks
+        st = sim.sync()
+        return sim, gs, t, fb / (n_blocks * len(ev)), np.concatenate(res), st
+
+    sim, gs, t_sur, fb_frac, res, st = run_surrogate(1e-3)
+    # the network alone on the last crop, timed with events on its stream
+    _, fc, pc = gs._cbuf
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(gs.ts):
         ev0.record()
-        gs.predict()
+        for i in range(0, len(ev), gs.chunk):
+            j = min(len(ev), i + gs.chunk)
+            net.forward(fc[i:j], out=pc[i:j])
         ev1.record()
     torch.cuda.synchronize()
     t_net = ev0.elapsed_time(ev1) * 1e-3
-    flop = unet_forward_flop(ev[0].res) * len(ev)
+    crop = gs.crop_shape
+    flop = unet_forward_flop(crop) * len(ev)
+    sim.close()
+    sim, gs, t_sur2, fb_frac2, _, _ = run_surrogate(1e-2)
+    sim.close()
+    sim, gs, t_nofb, _, _, _ = run_surrogate(1e-3, fallback=False)
     sim.close()
     out = {
         "metric": "surrogate+fallback speedup over plain batched MPM (one control step)",
@@ -313,17 +328,24 @@ def bench_surrogate(args):
         "vs_baseline": None,
         "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": f"cfg5: grid U-Net (3 levels, 32/64/128, 3^3 convs) trained {args.train_steps} steps "
-                               f"on 16 cfg2 rollouts x 8 control steps; timed on {len(ev)} held-out cfg2 scenes "
-                               f"(65,536 particles, 64^3 each), threshold 1e-3",
-                   "scenes": len(ev), "particles": int(sum(sc.n for sc in ev))},
+        "config": {"workload": f"cfg5: grid U-Net (3 levels, 32/64/128, 3^3 convs) on a box around the material, "
+                               f"trained {args.train_steps} steps on 16 cfg2 rollouts x 8 control steps; timed on "
+                               f"{len(ev)} held-out cfg2 scenes (65,536 particles, 64^3 each), residual gate 1e-3",
+                   "scenes": len(ev), "particles": int(sum(sc.n for sc in ev)), "crop": list(crop),
+                   "train_crop": list(train_shape)},
         "plain_ms_per_control_step": t_plain * 1e3,
         "surrogate_ms_per_control_step": t_sur * 1e3,
-        "fallback_fraction": fb / (n_blocks * len(ev)),
+        "fallback_fraction": fb_frac,
+        "residual": {"median": float(np.median(res)), "p10": float(np.percentile(res, 10)),
+                     "p90": float(np.percentile(res, 90))},
+        "at_threshold_1e-2": {"speedup": t_plain / t_sur2, "fallback_fraction": fb_frac2,
+                              "surrogate_ms_per_control_step": t_sur2 * 1e3},
+        "without_fallback": {"speedup": t_plain / t_nofb, "surrogate_ms_per_control_step": t_nofb * 1e3},
         "status": int(st),
         "train": {"steps": args.train_steps, "seconds": t_train, "log": log},
-        "roofline": {"bound": "mfma", "kernel": "U-Net forward (all convolutions)", "achieved": flop / t_net / 1e12,
-                     "peak": 2500.0, "unit": "TFLOP/s", "frac": flop / t_net / 1e12 / 2500.0, "traffic": None},
+        "roofline": {"bound": "mfma", "kernel": "U-Net forward (all convolutions, BF16)",
+                     "achieved": flop / t_net / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": flop / t_net / 1e12 / 2500.0, "traffic": None},
         "wall_s": time.perf_counter() - t_start,
     }
     print(json.dumps(out), flush=True)

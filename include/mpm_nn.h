@@ -88,6 +88,21 @@ int mpm_nn_masked_mse(const float *pred, int cp, const float *target, const floa
 int mpm_nn_adam(float *p, const float *g, float *m, float *v, long long n, float lr, float beta1, float beta2,
                 float eps, int t, void *stream);
 
+/* Crops of dense per-scene grids [n][R][R][R][c] (the surrogate runs on a
+ * box around the material instead of the whole grid).
+ * mpm_nn_bbox: bbox[g] (device, [n][6] ints) = (lo x, y, z, hi x, y, z) of
+ *   the nodes whose channel 0 of field [n][R^3][cf] is positive, hi
+ *   exclusive; all zeros for a grid with none.
+ * mpm_nn_crop_origin: origin[g] (device, [n][3]) of a (D, H, W) box centred
+ *   on bbox[g] and moved inside the grid (D, H, W <= R).
+ * mpm_nn_crop: uncrop = 0: dst [n][D][H][W][c] = src [n][R^3][c] at
+ *   origin + (z, y, x); uncrop = 1: dst [n][R^3][c] = src [n][D][H][W][c]
+ *   inside the box, 0 outside. */
+int mpm_nn_bbox(const float *field, int cf, int n, int R, int *bbox, void *stream);
+int mpm_nn_crop_origin(const int *bbox, int n, int R, int D, int H, int W, int *origin, void *stream);
+int mpm_nn_crop(const float *src, int c, int n, int R, const int *origin, int D, int H, int W, float *dst, int uncrop,
+                void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -245,6 +245,7 @@ mpm_status set_block(mpm_ctx ctx, int B)
                           hipMemcpyHostToDevice, ctx->stream));
     // the grid layout changed: every (m, p) must be zero and every v finite
     HIPCHK(launch_clear_f(ctx->d_grid, 7 * ctx->n_nodes, ctx->stream));
+    if (ctx->L.touched) HIPCHK(hipMemsetAsync(ctx->L.touched, 0, ctx->T_cap, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->since_sort = 1 << 30;
     clear_graphs(ctx);
@@ -318,6 +319,7 @@ SortArgs sort_args(mpm_ctx ctx)
     a.count = ctx->d_count;
     a.pstart = ctx->d_pstart;
     a.perm = ctx->d_perm;
+    a.perm2 = (int *)ctx->d_keys;   // the keys are dead once the scatter has run
     a.tsum = ctx->d_tsum;
     a.dil = ctx->d_dil;
     a.L = ctx->L;
@@ -498,7 +500,7 @@ void release(mpm_ctx ctx)
     void *bufs[] = {ctx->d_scenes, ctx->d_psc, ctx->d_P[0], ctx->d_P[1], ctx->d_grid, ctx->d_cols, ctx->d_colnow,
                     ctx->d_col_scene, ctx->d_scene_bin_off, ctx->d_keys, ctx->d_count, ctx->d_pstart, ctx->d_perm,
                     ctx->d_tsum, ctx->d_dil, ctx->L.items, ctx->L.gitems, ctx->L.n_items, ctx->L.n_gitems,
-                    ctx->L.scene_item_begin, ctx->L.scene_gitem_begin, ctx->L.bflag, ctx->L.ovf, ctx->L.n_ovf, ctx->L.ibound,
+                    ctx->L.scene_item_begin, ctx->L.scene_gitem_begin, ctx->L.bflag, ctx->L.ovf, ctx->L.n_ovf, ctx->L.ibound, ctx->L.touched,
                     ctx->d_flags, ctx->d_queue, ctx->d_scene_done, ctx->d_cap, ctx->d_cap_off, ctx->d_io,
                     ctx->d_active, ctx->d_sur_gend, ctx->d_sur_acc, ctx->d_sur_nfb};
     for (void *p : bufs)
@@ -576,6 +578,7 @@ mpm_status create_impl(mpm_ctx ctx, const mpm_scene_desc *scenes, int n_scenes)
     HIPCHK(dalloc(&ctx->L.scene_item_begin, n_scenes + 1));
     HIPCHK(dalloc(&ctx->L.scene_gitem_begin, n_scenes + 1));
     HIPCHK(dalloc(&ctx->L.bflag, T4));
+    HIPCHK(dalloc(&ctx->L.touched, T4));
     HIPCHK(dalloc(&ctx->L.ovf, T4));
     HIPCHK(dalloc(&ctx->L.n_ovf, 1));
     ctx->L.ovf_cap = T4;
@@ -604,6 +607,7 @@ mpm_status create_impl(mpm_ctx ctx, const mpm_scene_desc *scenes, int n_scenes)
     }
     HIPCHK(hipMemsetAsync(ctx->d_count, 0, sizeof(int) * T4, ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->L.bflag, 0, sizeof(int) * T4, ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->L.touched, 0, T4, ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->L.n_ovf, 0, sizeof(int), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->L.n_items, 0, sizeof(int), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->L.n_gitems, 0, sizeof(int), ctx->stream));

@@ -226,11 +226,62 @@ __global__ __launch_bounds__(WG) void k_scatter(SortArgs a)
     }
 }
 
+// Order inside a work item so that the lanes of a P2G wave scatter into
+// distinct LDS banks.  A particle's bank class is the tile address of its
+// base node mod 64; every stencil offset adds the same constant to all
+// lanes, so lanes with distinct classes hit distinct banks.  Particles are
+// ranked inside their class and laid out by (rank, class): the first 64
+// slots hold rank 0 of every class present, the next ones rank 1, and so on.
+// Slot of (rank r, class c) = sum_c' min(count[c'], r) + #{c' < c : count[c'] > r}.
+constexpr int BANK_CLASSES = 64;
+
+template <int B>
+__global__ __launch_bounds__(WG) void k_bank_order(SortArgs a)
+{
+    constexpr int T = B + 4;
+    __shared__ int cnt[BANK_CLASSES];
+    __shared__ unsigned short rank[8192];
+    __shared__ unsigned char cls[8192];
+    const int n_items = *a.L.n_items;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const Item item = a.L.items[it];
+        if (threadIdx.x < BANK_CLASSES) cnt[threadIdx.x] = 0;
+        __syncthreads();
+        const SceneDev &S = a.scenes[item.scene];
+        const int nb = S.nb;
+        const int org[3] = {(item.block / (nb * nb)) * B - 1, ((item.block / nb) % nb) * B - 1, (item.block % nb) * B - 1};
+        for (int li = threadIdx.x; li < item.count; li += WG) {
+            const int j = a.perm[item.start + li];
+            int tb[3], cl = 0;
+            float f;
+            for (int d = 0; d < 3; d++) {
+                int b;
+                particle_base(S, a.P[(long long)(X0 + d) * a.pstride + j], b, f, cl);
+                tb[d] = min(max(b - org[d], 0), T - 1);
+            }
+            const int c = ((tb[0] * T + tb[1]) * T + tb[2]) % BANK_CLASSES;
+            cls[li] = (unsigned char)c;
+            rank[li] = (unsigned short)atomicAdd(&cnt[c], 1);
+        }
+        __syncthreads();
+        for (int li = threadIdx.x; li < item.count; li += WG) {
+            const int c = cls[li], r = rank[li];
+            int pos = 0;
+            for (int q = 0; q < BANK_CLASSES; q++) {
+                const int k = cnt[q];
+                pos += min(k, r) + ((q < c && k > r) ? 1 : 0);
+            }
+            a.perm2[item.start + pos] = a.perm[item.start + li];
+        }
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(WG) void k_gather(SortArgs a)
 {
     int p = blockIdx.x * WG + threadIdx.x;
     if (p >= a.N) return;
-    int j = a.perm[p];
+    int j = a.perm2[p];
 #pragma unroll
     for (int c = 0; c < NCOMP; c++) a.Pn[(long long)c * a.pstride + p] = a.P[(long long)c * a.pstride + j];
 }
@@ -271,6 +322,8 @@ hipError_t launch_sort(const SortArgs &a, hipStream_t st)
     k_scan_emit<<<ntiles, WG, 0, st>>>(a);
     if (a.N > 0) {
         k_scatter<<<gN, WG, 0, st>>>(a);
+        if (a.B == 4) k_bank_order<4><<<2048, WG, 0, st>>>(a);
+        else k_bank_order<8><<<2048, WG, 0, st>>>(a);
         k_gather<<<gN, WG, 0, st>>>(a);
         k_item_bounds<<<2048, WG, 0, st>>>(a);
     }
@@ -328,7 +381,9 @@ __device__ void p2g_global(const StepArgs &a, int s, const SceneDev &S, const fl
             for (int cz = 0; cz < 2; cz++) {
                 int bx = (b[0] + 2 * cx) / B, by = (b[1] + 2 * cy) / B, bz = (b[2] + 2 * cz) / B;
                 if ((cx && bx == b[0] / B) || (cy && by == b[1] / B) || (cz && bz == b[2] / B)) continue;
-                queue_block(a, s, S, (bx * S.nb + by) * S.nb + bz);
+                const int lb = (bx * S.nb + by) * S.nb + bz;
+                a.L.touched[S.bin_off + lb] = 1;
+                queue_block(a, s, S, lb);
             }
 }
 
@@ -432,8 +487,10 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
         int tx = n / (T * T), ty = (n / T) % T, tz = n % T;
         int gi = org[0] + tx, gj = org[1] + ty, gk = org[2] + tz;
         if (gi < 0 || gj < 0 || gk < 0 || gi >= S.res || gj >= S.res || gk >= S.res) continue;
+        const int lb = ((gi / B) * S.nb + (gj / B)) * S.nb + (gk / B);
+        a.L.touched[S.bin_off + lb] = 1;
         if (tx == 0 || ty == 0 || tz == 0)   // node of a lower neighbour block: make sure it is updated
-            queue_block(a, s, S, ((gi / B) * S.nb + (gj / B)) * S.nb + (gk / B));
+            queue_block(a, s, S, lb);
         long long idx = node_index(S, B, gi, gj, gk);
         atomicAdd(a.gm + idx, (float)m0 * im);
         atomicAdd(a.gpx + idx, (float)p0 * ip);
@@ -461,6 +518,8 @@ template <int B>
 __device__ void grid_block(const StepArgs &a, int s, int lb, int lane)
 {
     const SceneDev &S = a.scenes[s];
+    unsigned char *tf = a.L.touched + S.bin_off + lb;
+    if (!*tf) return;          // no P2G wrote into this block: every (m, p) in it is zero
     const int nb = S.nb;
     const int bx = lb / (nb * nb), by = (lb / nb) % nb, bz = lb % nb;
     const ColliderNow *cn = (const ColliderNow *)a.colnow + S.col_off;
@@ -510,6 +569,7 @@ __device__ void grid_block(const StepArgs &a, int s, int lb, int lane)
         a.gpy[idx] = 0.0f;
         a.gpz[idx] = 0.0f;
     }
+    if (lane == 0) *tf = 0;
 }
 
 template <int B>

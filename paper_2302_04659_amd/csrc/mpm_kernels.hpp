@@ -46,6 +46,7 @@ struct SortArgs {
     int *count;               // [T] (zero on entry, zero again after scatter)
     int *pstart;              // [T]
     int *perm;                // [N]
+    int *perm2;               // [N] perm with every item in bank order (k_gather reads this)
     int3 *tsum;               // per scan tile
     unsigned char *dil;       // [T] 1 = grid block of the dilated particle set (by linear block)
     Lists L;

@@ -120,4 +120,24 @@ int mpm_nn_adam(float *p, const float *g, float *m, float *v, long long n, float
     return st_of(nn::adam(p, g, m, v, n, lr, beta1, beta2, eps, t, (hipStream_t)stream));
 }
 
+int mpm_nn_bbox(const float *field, int cf, int n, int R, int *bbox, void *stream)
+{
+    if (!field || !bbox || cf <= 0 || n <= 0 || R <= 0) return -1;
+    return st_of(nn::bbox(field, cf, n, R, bbox, (hipStream_t)stream));
+}
+
+int mpm_nn_crop_origin(const int *bbox, int n, int R, int D, int H, int W, int *origin, void *stream)
+{
+    if (!bbox || !origin || n <= 0 || D <= 0 || H <= 0 || W <= 0 || D > R || H > R || W > R) return -1;
+    return st_of(nn::crop_origin(bbox, n, R, D, H, W, origin, (hipStream_t)stream));
+}
+
+int mpm_nn_crop(const float *src, int c, int n, int R, const int *origin, int D, int H, int W, float *dst, int uncrop,
+                void *stream)
+{
+    if (!src || !dst || !origin || c <= 0 || n <= 0 || D <= 0 || H <= 0 || W <= 0 || D > R || H > R || W > R) return -1;
+    if (uncrop != 0 && uncrop != 1) return -1;
+    return st_of(nn::crop(src, c, n, R, origin, D, H, W, dst, uncrop, (hipStream_t)stream));
+}
+
 }  // extern "C"

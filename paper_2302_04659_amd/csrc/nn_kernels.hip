@@ -145,6 +145,112 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
         }
 }
 
+// ---------------------------------------------------------------- LDS-tiled convolution (3^3 and up)
+// A workgroup computes a 4 x 4 x 16 (z, y, x) tile of output voxels for all
+// output channels; wave w owns the z-slice w (4 row fragments of 16 x).  For
+// every 16-channel chunk of the input, the tile's input halo is staged once
+// in LDS (zero where the padding or the tensor edge is) and all 27 taps read
+// their A fragments from it; weights come from the packed B fragments.
+constexpr int TLZ = 4, TLY = 4, TLX = 16;
+constexpr int HLZ = TLZ + 2, HLY = TLY + 2, HLX = TLX + 2;   // 3^3 halo (the up halo is smaller)
+
+template <int NF, int KIND>
+__global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
+{
+    __shared__ uint2 halo[HLZ * HLY * HLX * 4];              // [voxel][4 x (4 bf16)]
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tiles_x = (a.ow + TLX - 1) / TLX, tiles_y = (a.oh + TLY - 1) / TLY, tiles_z = (a.od + TLZ - 1) / TLZ;
+    int b = blockIdx.x;
+    const int bx = b % tiles_x;
+    b /= tiles_x;
+    const int by = b % tiles_y;
+    b /= tiles_y;
+    const int bz = b % tiles_z;
+    const int bn = b / tiles_z;
+    const int z0 = bz * TLZ, y0 = by * TLY, x0 = bx * TLX;
+    // input-space origin and extent of the halo
+    int hz0, hy0, hx0, hz, hy, hx;
+    if (KIND == KIND_C3) {
+        hz0 = z0 - 1; hy0 = y0 - 1; hx0 = x0 - 1;
+        hz = HLZ; hy = HLY; hx = HLX;
+    } else {   // nearest x2 upsampled input: fine u = o + t - 1 reads coarse u >> 1
+        hz0 = (z0 >> 1) - 1; hy0 = (y0 >> 1) - 1; hx0 = (x0 >> 1) - 1;
+        hz = TLZ / 2 + 2; hy = TLY / 2 + 2; hx = TLX / 2 + 2;
+    }
+    const int nh = hz * hy * hx;
+    f4 acc[4][NF];
+#pragma unroll
+    for (int f = 0; f < 4; f++)
+#pragma unroll
+        for (int n = 0; n < NF; n++) acc[f][n] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int kc = a.cin / 16;
+    const int q = lane >> 4, i = lane & 15;
+    for (int c = 0; c < kc; c++) {
+        // stage the halo of input channels [16 c, 16 c + 16)
+        for (int e = threadIdx.x; e < nh * 4; e += 256) {
+            const int v = e >> 2, qq = e & 3;
+            const int lx = v % hx, ly = (v / hx) % hy, lz = v / (hx * hy);
+            const int gz = hz0 + lz, gy = hy0 + ly, gx = hx0 + lx;
+            uint2 val = make_uint2(0u, 0u);
+            if (gz >= 0 && gy >= 0 && gx >= 0 && gz < a.id && gy < a.ih && gx < a.iw)
+                val = *(const uint2 *)(a.x + ((((long long)bn * a.id + gz) * a.ih + gy) * a.iw + gx) * a.cx + a.x_off +
+                                       16 * c + 4 * qq);
+            halo[e] = val;
+        }
+        __syncthreads();
+        const uint16_t *wc = a.w + (size_t)c * NF * 256 + 4 * lane;
+        for (int t = 0; t < 27; t++) {
+            const int ta = t / 9, tb = (t / 3) % 3, tc = t % 3;
+            s4 Af[4];
+#pragma unroll
+            for (int f = 0; f < 4; f++) {
+                int lz, ly, lx;
+                if (KIND == KIND_C3) {
+                    lz = wv + ta; ly = f + tb; lx = i + tc;
+                } else {
+                    lz = ((z0 + wv + ta - 1) >> 1) - hz0;
+                    ly = ((y0 + f + tb - 1) >> 1) - hy0;
+                    lx = ((x0 + i + tc - 1) >> 1) - hx0;
+                }
+                const uint2 raw = halo[((lz * hy + ly) * hx + lx) * 4 + q];
+                Af[f] = s4{(short)(raw.x & 0xffff), (short)(raw.x >> 16), (short)(raw.y & 0xffff), (short)(raw.y >> 16)};
+            }
+            const uint16_t *wt = wc + (size_t)t * kc * NF * 256;
+#pragma unroll
+            for (int n = 0; n < NF; n++) {
+                const uint2 raw = *(const uint2 *)(wt + (size_t)n * 256);
+                const s4 Bv = s4{(short)(raw.x & 0xffff), (short)(raw.x >> 16), (short)(raw.y & 0xffff), (short)(raw.y >> 16)};
+#pragma unroll
+                for (int f = 0; f < 4; f++) acc[f][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Af[f], Bv, acc[f][n], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // epilogue: fragment f = output row y0 + f, D[i][j] -> x = x0 + 4 (lane/16) + r, channel 16 n + lane % 16
+    const int oz = z0 + wv;
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+        const int oy = y0 + f;
+        if (oz >= a.od || oy >= a.oh) continue;
+#pragma unroll
+        for (int n = 0; n < NF; n++) {
+            const int co = 16 * n + (lane & 15);
+            if (co >= a.cout) continue;
+            const float bias = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int ox = x0 + 4 * (lane >> 4) + r;
+                if (ox >= a.ow) continue;
+                const long long v = (((long long)bn * a.od + oz) * a.oh + oy) * a.ow + ox;
+                float val = acc[f][n][r] + bias;
+                if (a.relu) val = fmaxf(val, 0.0f);
+                if (a.y) a.y[v * a.cy + a.y_off + co] = f2bf(val);
+                if (a.y32) a.y32[v * a.cy32 + co] = val;
+            }
+        }
+    }
+}
+
 // Pack FP32 master weights W[tap][ci][co] (ci < cin, co < cout) into the
 // B-fragment order the conv kernel reads, as BF16; `transpose` packs the
 // weights of the adjoint (dgrad) convolution: taps mirrored, ci <-> co.
@@ -413,6 +519,90 @@ __global__ void k_adam(float *p, const float *g, float *m, float *v, long long n
     }
 }
 
+// ---------------------------------------------------------------- crops of dense per-scene grids
+// Bounding box of the nodes whose channel 0 is positive, one workgroup per
+// grid: bbox[g] = (lo_x, lo_y, lo_z, hi_x, hi_y, hi_z), hi exclusive; an
+// empty grid gives (0, 0, 0, 0, 0, 0).
+__global__ __launch_bounds__(256) void k_bbox(const float *field, int cf, int R, int *bbox)
+{
+    __shared__ int red[6][256];
+    const long long R3 = (long long)R * R * R;
+    const float *f = field + (long long)blockIdx.x * R3 * cf;
+    int lo[3] = {R, R, R}, hi[3] = {-1, -1, -1};
+    for (long long c = threadIdx.x; c < R3; c += 256) {
+        if (!(f[c * cf] > 0.0f)) continue;
+        const int ii[3] = {(int)(c / ((long long)R * R)), (int)((c / R) % R), (int)(c % R)};
+        for (int d = 0; d < 3; d++) {
+            lo[d] = min(lo[d], ii[d]);
+            hi[d] = max(hi[d], ii[d]);
+        }
+    }
+    for (int d = 0; d < 3; d++) {
+        red[d][threadIdx.x] = lo[d];
+        red[3 + d][threadIdx.x] = hi[d];
+    }
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int d = 0; d < 3; d++) {
+                red[d][threadIdx.x] = min(red[d][threadIdx.x], red[d][threadIdx.x + o]);
+                red[3 + d][threadIdx.x] = max(red[3 + d][threadIdx.x], red[3 + d][threadIdx.x + o]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const bool empty = red[3][0] < 0;
+        for (int d = 0; d < 3; d++) {
+            bbox[6 * blockIdx.x + d] = empty ? 0 : red[d][0];
+            bbox[6 * blockIdx.x + 3 + d] = empty ? 0 : red[3 + d][0] + 1;
+        }
+    }
+}
+
+// Crop origin per grid: the box of size (D, H, W) centred on bbox, moved
+// inside [0, R).
+__global__ void k_crop_origin(const int *bbox, int n, int R, int D, int H, int W, int *origin)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const int size[3] = {D, H, W};
+    for (int d = 0; d < 3; d++) {
+        const int lo = bbox[6 * g + d], hi = bbox[6 * g + 3 + d];
+        int o = (lo + hi - size[d]) / 2;
+        o = max(0, min(o, R - size[d]));
+        origin[3 * g + d] = o;
+    }
+}
+
+// dst[g][z][y][x][:c] = src[g][oz + z][oy + y][ox + x][:c]  (crop), or the
+// reverse with zeros outside the crop (uncrop: dst is the full grid).
+__global__ void k_crop(const float *src, int c, int n, int R, const int *origin, int D, int H, int W, float *dst,
+                       int uncrop)
+{
+    const long long R3 = (long long)R * R * R;
+    const long long per = uncrop ? R3 : (long long)D * H * W;
+    const long long total = per * n * c;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+        const int ch = (int)(e % c);
+        const long long v = e / c;
+        const int g = (int)(v / per);
+        const long long l = v - (long long)g * per;
+        const int* o = origin + 3 * g;
+        if (!uncrop) {
+            const int z = (int)(l / ((long long)H * W)), y = (int)((l / W) % H), x = (int)(l % W);
+            const long long sv = (((long long)g * R + o[0] + z) * R + o[1] + y) * R + o[2] + x;
+            dst[e] = src[sv * c + ch];
+        } else {
+            const int i = (int)(l / ((long long)R * R)), j = (int)((l / R) % R), k = (int)(l % R);
+            const int z = i - o[0], y = j - o[1], x = k - o[2];
+            float val = 0.0f;
+            if (z >= 0 && y >= 0 && x >= 0 && z < D && y < H && x < W)
+                val = src[((((long long)g * D + z) * H + y) * W + x) * c + ch];
+            dst[e] = val;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 static unsigned grid_for(long long n, int per = 256)
 {
@@ -420,8 +610,26 @@ static unsigned grid_for(long long n, int per = 256)
     return (unsigned)(b < 16384 ? (b < 1 ? 1 : b) : 16384);
 }
 
+template <int KIND>
+static hipError_t conv_lds(const ConvArgs &a, hipStream_t st)
+{
+    const long long tiles = (long long)a.n * ((a.od + TLZ - 1) / TLZ) * ((a.oh + TLY - 1) / TLY) * ((a.ow + TLX - 1) / TLX);
+    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+    const unsigned g = (unsigned)tiles;
+    switch ((a.cout + 15) / 16) {
+    case 1: k_conv_lds<1, KIND><<<g, 256, 0, st>>>(a); break;
+    case 2: k_conv_lds<2, KIND><<<g, 256, 0, st>>>(a); break;
+    case 4: k_conv_lds<4, KIND><<<g, 256, 0, st>>>(a); break;
+    case 8: k_conv_lds<8, KIND><<<g, 256, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t conv(const ConvArgs &a, hipStream_t st)
 {
+    if (a.kind == KIND_C3) return conv_lds<KIND_C3>(a, st);
+    if (a.kind == KIND_UP) return conv_lds<KIND_UP>(a, st);
     const long long nvox = (long long)a.n * a.od * a.oh * a.ow;
     const unsigned g = (unsigned)((nvox + 255) / 256);
     switch ((a.cout + 15) / 16) {
@@ -501,6 +709,26 @@ hipError_t masked_mse(const float *pred, int cp, const float *target, const floa
 {
     k_mask_count<<<1, 256, 0, st>>>(mask, nvox, loss_parts + nparts);
     k_masked_mse<<<nparts, 256, 0, st>>>(pred, cp, target, mask, nvox, c, loss_parts + nparts, g, cg, loss_parts);
+    return hipGetLastError();
+}
+
+hipError_t bbox(const float *field, int cf, int n, int R, int *box, hipStream_t st)
+{
+    k_bbox<<<n, 256, 0, st>>>(field, cf, R, box);
+    return hipGetLastError();
+}
+
+hipError_t crop_origin(const int *box, int n, int R, int D, int H, int W, int *origin, hipStream_t st)
+{
+    k_crop_origin<<<(n + 63) / 64, 64, 0, st>>>(box, n, R, D, H, W, origin);
+    return hipGetLastError();
+}
+
+hipError_t crop(const float *src, int c, int n, int R, const int *origin, int D, int H, int W, float *dst, int uncrop,
+                hipStream_t st)
+{
+    const long long per = uncrop ? (long long)R * R * R : (long long)D * H * W;
+    k_crop<<<grid_for(per * n * c), 256, 0, st>>>(src, c, n, R, origin, D, H, W, dst, uncrop);
     return hipGetLastError();
 }
 

@@ -51,6 +51,10 @@ hipError_t to_bf16(const float *x, int cs, long long nvox, int c, uint16_t *y, i
                    hipStream_t st);
 hipError_t masked_mse(const float *pred, int cp, const float *target, const float *mask, long long nvox, int c,
                       uint16_t *g, int cg, float *loss_parts, int nparts, hipStream_t st);
+hipError_t bbox(const float *field, int cf, int n, int R, int *box, hipStream_t st);
+hipError_t crop_origin(const int *box, int n, int R, int D, int H, int W, int *origin, hipStream_t st);
+hipError_t crop(const float *src, int c, int n, int R, const int *origin, int D, int H, int W, float *dst, int uncrop,
+                hipStream_t st);
 hipError_t adam(float *p, const float *g, float *m, float *v, long long n, float lr, float b1, float b2, float eps, int t,
                 hipStream_t st);
 

@@ -25,6 +25,7 @@ import numpy as np
 
 from . import mpm as _mpm
 from .unet import UNet
+from .unet import nn_lib as _unet_lib
 
 CIN, COUT = 8, 4
 SUBSTEPS = 25
@@ -55,18 +56,36 @@ def _stream_of(sim):
     return ts
 
 
+def crop_shape(bbox: np.ndarray, margin: int, R: int):
+    """Common crop size of a batch: the largest material extent plus a margin
+    on each side, rounded up to a multiple of 8 and at most R."""
+    ext = (bbox[:, 3:] - bbox[:, :3]).max(axis=0) + 2 * margin
+    return tuple(int(min(R, max(8, -(-e // 8) * 8))) for e in ext)
+
+
+def _crop_all(L, stream, src, c, n, R, origin, shape, dst, uncrop=0):
+    D, H, W = shape
+    r = L.mpm_nn_crop(src.data_ptr(), c, n, R, origin.data_ptr(), D, H, W, dst.data_ptr(), uncrop, stream)
+    if r != 0:
+        raise RuntimeError(f"mpm_nn_crop failed ({r})")
+
+
 class GridSurrogate:
     """Runs control steps of a Sim through a trained UNet.  Everything is
     queued on the Sim's stream."""
 
-    def __init__(self, sim: "_mpm.Sim", net: UNet, threshold: float = 1e-3, chunk: int = 16):
+    def __init__(self, sim: "_mpm.Sim", net: UNet, threshold: float = 1e-3, chunk: int = 16, margin: int = 4,
+                 crop: bool = True):
         torch = _torch()
         self.sim, self.net, self.threshold, self.chunk = sim, net, float(threshold), int(chunk)
+        self.margin, self.crop = int(margin), bool(crop)
         self.ts = _stream_of(sim)
         R = sim.scenes[0].res
         S = sim.n_scenes
         dev = net.device
         self.R, self.S = R, S
+        self.crop_shape = (R, R, R)
+        self._cbuf = None
         torch.cuda.synchronize()      # weights and buffers made on other streams are ready
         with torch.cuda.stream(self.ts):
             self.feat = torch.zeros((S, R, R, R, CIN), dtype=torch.float32, device=dev)
@@ -74,15 +93,41 @@ class GridSurrogate:
             self.pred = torch.zeros((S, R, R, R, COUT), dtype=torch.float32, device=dev)
             self.residual = torch.zeros(S, dtype=torch.float32, device=dev)
             self.n_fallback = torch.zeros(1, dtype=torch.int32, device=dev)
+            self.box = torch.zeros((S, 6), dtype=torch.int32, device=dev)
+            self.origin = torch.zeros((S, 3), dtype=torch.int32, device=dev)
 
     def predict(self):
-        """Features of the current state and the network's prediction (device)."""
+        """Features of the current state and the network's prediction (device).
+        With crop = True the network runs on a box around each scene's
+        material (one host read of the boxes per call) and predicts zero
+        outside it."""
         torch = _torch()
+        L = self.net.L
         with torch.cuda.stream(self.ts):
+            s = self.ts.cuda_stream
             self.sim.sur_features(self.feat, self.grid0)
+            if not self.crop:
+                for i in range(0, self.S, self.chunk):
+                    j = min(self.S, i + self.chunk)
+                    self.net.forward(self.feat[i:j], out=self.pred[i:j])
+                return
+            if L.mpm_nn_bbox(self.feat.data_ptr(), CIN, self.S, self.R, self.box.data_ptr(), s) != 0:
+                raise RuntimeError("mpm_nn_bbox failed")
+            shape = crop_shape(self.box.cpu().numpy(), self.margin, self.R)
+            D, H, W = shape
+            if L.mpm_nn_crop_origin(self.box.data_ptr(), self.S, self.R, D, H, W, self.origin.data_ptr(), s) != 0:
+                raise RuntimeError("mpm_nn_crop_origin failed")
+            if self._cbuf is None or self._cbuf[0] != shape:
+                self._cbuf = (shape,
+                              torch.zeros((self.S, D, H, W, CIN), dtype=torch.float32, device=self.net.device),
+                              torch.zeros((self.S, D, H, W, COUT), dtype=torch.float32, device=self.net.device))
+            _, fc, pc = self._cbuf
+            self.crop_shape = shape
+            _crop_all(L, s, self.feat, CIN, self.S, self.R, self.origin, shape, fc)
             for i in range(0, self.S, self.chunk):
                 j = min(self.S, i + self.chunk)
-                self.net.forward(self.feat[i:j], out=self.pred[i:j])
+                self.net.forward(fc[i:j], out=pc[i:j])
+            _crop_all(L, s, pc, COUT, self.S, self.R, self.origin, shape, self.pred, uncrop=1)
 
     def block(self, fallback: bool = True, sync: bool = False):
         """One control step of every scene (surrogate, plain MPM where the
@@ -107,7 +152,7 @@ class RolloutData:
     """Start grids and features of consecutive control steps of plain MPM
     rollouts, and the targets between them (all on the device)."""
 
-    def __init__(self, scene_list: Sequence, n_blocks: int):
+    def __init__(self, scene_list: Sequence, n_blocks: int, crop: bool = True, margin: int = 4):
         torch = _torch()
         sim = make_sim(scene_list)
         S, R = sim.n_scenes, scene_list[0].res
@@ -134,6 +179,35 @@ class RolloutData:
         if st < 0:
             raise RuntimeError(f"rollout failed ({st})")
         sim.close()
+        self.shape = (R, R, R)
+        if crop:
+            self._crop(margin)
+
+    def _crop(self, margin: int):
+        """Keep a box around each sample's material (start or end of the
+        step): the network trains on the same kind of crop it runs on."""
+        torch = _torch()
+        L = _unet_lib()
+        n, R = self.n_blocks * self.S, self.R
+        s = torch.cuda.current_stream().cuda_stream
+        box = torch.zeros((n, 6), dtype=torch.int32, device="cuda")
+        origin = torch.zeros((n, 3), dtype=torch.int32, device="cuda")
+        if L.mpm_nn_bbox(self.mask.data_ptr(), 1, n, R, box.data_ptr(), s) != 0:
+            raise RuntimeError("mpm_nn_bbox failed")
+        shape = crop_shape(box.cpu().numpy(), margin, R)
+        D, H, W = shape
+        if L.mpm_nn_crop_origin(box.data_ptr(), n, R, D, H, W, origin.data_ptr(), s) != 0:
+            raise RuntimeError("mpm_nn_crop_origin failed")
+        out = []
+        for src, c in ((self.feat, CIN), (self.target, COUT), (self.mask, 1)):
+            dst = torch.zeros((n, D, H, W, c), dtype=torch.float32, device="cuda")
+            _crop_all(L, s, src, c, n, R, origin, shape, dst)
+            out.append(dst)
+        torch.cuda.synchronize()
+        self.feat = out[0].view(self.n_blocks, self.S, D, H, W, CIN)
+        self.target = out[1].view(self.n_blocks, self.S, D, H, W, COUT)
+        self.mask = out[2].view(self.n_blocks, self.S, D, H, W)
+        self.shape = shape
 
     @property
     def n_samples(self):
@@ -151,11 +225,11 @@ def train(net: UNet, data: RolloutData, steps: int, batch: int = 8, lr: float = 
           log_every: int = 50, holdout: Optional[RolloutData] = None) -> List[Dict]:
     """Adam on the masked MSE of the targets; returns a loss log."""
     torch = _torch()
-    R = data.R
+    sh = tuple(data.shape)
     rng = np.random.default_rng(seed)
-    xb = torch.zeros((batch, R, R, R, CIN), dtype=torch.float32, device="cuda")
-    tb = torch.zeros((batch, R, R, R, COUT), dtype=torch.float32, device="cuda")
-    mb = torch.zeros((batch, R, R, R), dtype=torch.float32, device="cuda")
+    xb = torch.zeros((batch,) + sh + (CIN,), dtype=torch.float32, device="cuda")
+    tb = torch.zeros((batch,) + sh + (COUT,), dtype=torch.float32, device="cuda")
+    mb = torch.zeros((batch,) + sh, dtype=torch.float32, device="cuda")
     log = []
     t0 = time.perf_counter()
     for it in range(1, steps + 1):
@@ -174,10 +248,10 @@ def train(net: UNet, data: RolloutData, steps: int, batch: int = 8, lr: float = 
 def evaluate_loss(net: UNet, data: RolloutData, batch: int = 8) -> float:
     """Masked MSE over every sample of `data` (forward only)."""
     torch = _torch()
-    R = data.R
-    xb = torch.zeros((batch, R, R, R, CIN), dtype=torch.float32, device="cuda")
-    tb = torch.zeros((batch, R, R, R, COUT), dtype=torch.float32, device="cuda")
-    mb = torch.zeros((batch, R, R, R), dtype=torch.float32, device="cuda")
+    sh = tuple(data.shape)
+    xb = torch.zeros((batch,) + sh + (CIN,), dtype=torch.float32, device="cuda")
+    tb = torch.zeros((batch,) + sh + (COUT,), dtype=torch.float32, device="cuda")
+    mb = torch.zeros((batch,) + sh, dtype=torch.float32, device="cuda")
     tot, n = 0.0, 0
     for i in range(0, data.n_samples - batch + 1, batch):
         data.batch(range(i, i + batch), xb, tb, mb)

@@ -71,6 +71,9 @@ def nn_lib():
         L.mpm_nn_to_bf16.argtypes = [vp, i, ll, i, vp, i, i, i, vp]
         L.mpm_nn_masked_mse.argtypes = [vp, i, vp, vp, ll, i, vp, i, vp, i, vp]
         L.mpm_nn_adam.argtypes = [vp, vp, vp, vp, ll, f, f, f, f, i, vp]
+        L.mpm_nn_bbox.argtypes = [vp, i, i, i, vp, vp]
+        L.mpm_nn_crop_origin.argtypes = [vp, i, i, i, i, i, vp, vp]
+        L.mpm_nn_crop.argtypes = [vp, i, i, i, vp, i, i, i, vp, i, vp]
         L._nn_ready = True
     return L
 

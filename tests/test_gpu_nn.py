@@ -432,3 +432,42 @@ def test_network_forward_backward_vs_oracle(nn):
             if e_q > 0.5 * e_ox + 2e-3 or e_x > 1.5 * e_ox + 5e-3:
                 bad.append(key)
     assert not bad, bad
+
+
+def test_bbox_crop_uncrop(nn):
+    """Boxes of the positive nodes, crop origins and crop / uncrop copies are
+    exact against their definitions (integer and copy work: bit-exact)."""
+    import torch
+    announce("nn bbox / crop / uncrop")
+    rng = np.random.default_rng(12)
+    n, R, c = 3, 16, 2
+    field = np.zeros((n, R, R, R, c), np.float32)
+    field[0, 3:9, 5:7, 2:14, 0] = rng.random((6, 2, 12)) + 0.1
+    field[1, 10, 0, 15, 0] = 1.0                      # a single node in a corner
+    field[..., 1] = rng.normal(size=(n, R, R, R))     # channel 1 is payload only
+    L, s = nn.nn_lib(), _stream()
+    f_d = _f32_dev(field)
+    box = torch.zeros((n, 6), dtype=torch.int32, device="cuda")
+    assert L.mpm_nn_bbox(f_d.data_ptr(), c, n, R, box.data_ptr(), s) == 0
+    D, H, W = 8, 8, 12
+    org = torch.zeros((n, 3), dtype=torch.int32, device="cuda")
+    assert L.mpm_nn_crop_origin(box.data_ptr(), n, R, D, H, W, org.data_ptr(), s) == 0
+    crop = torch.zeros((n, D, H, W, c), dtype=torch.float32, device="cuda")
+    assert L.mpm_nn_crop(f_d.data_ptr(), c, n, R, org.data_ptr(), D, H, W, crop.data_ptr(), 0, s) == 0
+    back = torch.full((n, R, R, R, c), 7.0, dtype=torch.float32, device="cuda")
+    assert L.mpm_nn_crop(crop.data_ptr(), c, n, R, org.data_ptr(), D, H, W, back.data_ptr(), 1, s) == 0
+    torch.cuda.synchronize()
+    bh, oh = box.cpu().numpy(), org.cpu().numpy()
+    ch, kh = crop.cpu().numpy(), back.cpu().numpy()
+    for g in range(n):
+        pos = np.argwhere(field[g, ..., 0] > 0)
+        exp = np.zeros(6, int) if len(pos) == 0 else np.concatenate([pos.min(0), pos.max(0) + 1])
+        assert np.array_equal(bh[g], exp)
+        size = np.array([D, H, W])
+        o = np.clip((exp[:3] + exp[3:] - size) // 2, 0, R - size)
+        assert np.array_equal(oh[g], o)
+        sl = tuple(slice(o[d], o[d] + size[d]) for d in range(3))
+        assert np.array_equal(ch[g], field[g][sl])
+        full = np.zeros((R, R, R, c), np.float32)
+        full[sl] = field[g][sl]
+        assert np.array_equal(kh[g], full)
