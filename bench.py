@@ -265,6 +265,8 @@ def bench_surrogate(args):
     n_blocks = 4
     # plain batched MPM (graph replay of 25-substep blocks)
     plain = mpm.Sim(ev)
+    plain.autotune(10)            # both sides run the tuned substep configuration
+    tuned = {o: plain.get_option(o) for o in (mpm.OPT_BLOCK, mpm.OPT_CHUNK, mpm.OPT_SORT_EVERY)}
     plain.set_option(mpm.OPT_GRAPH, 1)
     plain.set_colliders_ctrl(0)
     plain.step(25)
@@ -279,6 +281,8 @@ def bench_surrogate(args):
 
     def run_surrogate(threshold, fallback=True):
         sim = surrogate.make_sim(ev)
+        for o, v in tuned.items():
+            sim.set_option(o, v)
         sim.set_option(mpm.OPT_GRAPH, 1)
         gs = surrogate.GridSurrogate(sim, net, threshold=threshold, chunk=16)
         sim.set_colliders_ctrl(0)
@@ -332,7 +336,8 @@ def bench_surrogate(args):
                                f"trained {args.train_steps} steps on 16 cfg2 rollouts x 8 control steps; timed on "
                                f"{len(ev)} held-out cfg2 scenes (65,536 particles, 64^3 each), residual gate 1e-3",
                    "scenes": len(ev), "particles": int(sum(sc.n for sc in ev)), "crop": list(crop),
-                   "train_crop": list(train_shape)},
+                   "train_crop": list(train_shape), "block": tuned[mpm.OPT_BLOCK], "chunk": tuned[mpm.OPT_CHUNK],
+                   "sort_every": tuned[mpm.OPT_SORT_EVERY]},
         "plain_ms_per_control_step": t_plain * 1e3,
         "surrogate_ms_per_control_step": t_sur * 1e3,
         "fallback_fraction": fb_frac,

@@ -53,7 +53,9 @@ int mpm_nn_wgrad(int kind, const uint16_t *x, int n, int id, int ih, int iw, int
                  const uint16_t *g, int cg, int g_off, int cout, long long chunk, float *partial, float *gw,
                  int accumulate, void *stream);
 
-/* gb[co] (+)= sum over voxels of g[voxel][g_off + co]. */
+/* gb[co] (+)= sum over voxels of g[voxel][g_off + co] (cout <= 128; the
+ * partial sums are added with float atomics, so the summation order -- and
+ * the last bit -- may differ between calls). */
 int mpm_nn_bias_grad(const uint16_t *g, long long voxels, int cg, int g_off, int cout, float *gb, int accumulate,
                      void *stream);
 

@@ -71,7 +71,7 @@ int mpm_nn_wgrad(int kind, const uint16_t *x, int n, int id, int ih, int iw, int
 int mpm_nn_bias_grad(const uint16_t *g, long long voxels, int cg, int g_off, int cout, float *gb, int accumulate,
                      void *stream)
 {
-    if (!g || !gb || voxels <= 0 || cout <= 0 || g_off + cout > cg) return -1;
+    if (!g || !gb || voxels <= 0 || cout <= 0 || cout > 128 || g_off + cout > cg) return -1;
     return st_of(nn::bias_grad(g, voxels, cg, g_off, cout, gb, accumulate, (hipStream_t)stream));
 }
 

@@ -371,20 +371,35 @@ __global__ void k_reduce_partials(const float *partial, int nchunk, long long pe
     }
 }
 
-// bias gradient: gb[co] = sum over voxels of dY[v][co] (one workgroup per 256 channels-slots)
-__global__ void k_bias_grad(const uint16_t *g, long long nvox, int cg, int g_off, int cout, float *gb, int accumulate)
+// bias gradient: gb[co] (+)= sum over voxels of dY[v][co].  Each workgroup
+// sums a chunk of voxels for every channel (consecutive threads read
+// consecutive channels of a voxel), reduces in LDS and adds its partial sums
+// with one float atomic per channel; gb is cleared first unless accumulating.
+constexpr int BIAS_CHUNK = 8192;
+
+__global__ void k_fill_f(float *p, int n, float v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t *g, long long nvox, int cg, int g_off, int cout,
+                                                   float *gb)
 {
     __shared__ float red[256];
-    const int co = blockIdx.x;
-    float s = 0.0f;
-    for (long long v = threadIdx.x; v < nvox; v += blockDim.x) s += bf2f(g[v * cg + g_off + co]);
-    red[threadIdx.x] = s;
+    const int vl = 256 / cout;                       // voxel lanes (cout <= 128)
+    const int co = threadIdx.x % cout, lv = threadIdx.x / cout;
+    const long long v0 = (long long)blockIdx.x * BIAS_CHUNK, v1 = min(nvox, v0 + BIAS_CHUNK);
+    float sum = 0.0f;
+    if (lv < vl)
+        for (long long v = v0 + lv; v < v1; v += vl) sum += bf2f(g[v * cg + g_off + co]);
+    red[threadIdx.x] = lv < vl ? sum : 0.0f;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
+    if (threadIdx.x < cout) {
+        float t = 0.0f;
+        for (int k = 0; k < vl; k++) t += red[k * cout + threadIdx.x];
+        atomicAdd(gb + threadIdx.x, t);
     }
-    if (threadIdx.x == 0) gb[co] = (accumulate ? gb[co] : 0.0f) + red[0];
 }
 
 // ---------------------------------------------------------------- elementwise and resampling
@@ -458,20 +473,28 @@ __global__ void k_to_bf16(const float *x, int cs, long long nvox, int c, uint16_
     }
 }
 
-// Number of masked voxels (mask != 0), counted in integers by one workgroup
-// and stored as a float (exact below 2^24 voxels).
-__global__ void k_mask_count(const float *mask, long long nvox, float *count)
+// Number of masked voxels (mask != 0): integer partial counts per workgroup
+// added into the count slot (held as an int while counting), then turned
+// into a float (exact below 2^24 voxels).
+__global__ void k_mask_count(const float *mask, long long nvox, int *count)
 {
     __shared__ int red[256];
     int c = 0;
-    for (long long v = threadIdx.x; v < nvox; v += blockDim.x) c += mask[v] != 0.0f;
+    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < nvox; v += (long long)gridDim.x * blockDim.x)
+        c += mask[v] != 0.0f;
     red[threadIdx.x] = c;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *count = (float)red[0];
+    if (threadIdx.x == 0 && red[0]) atomicAdd(count, red[0]);
+}
+
+__global__ void k_int_slot(int *slot, int to_float)
+{
+    if (to_float) *(float *)slot = (float)*slot;
+    else *slot = 0;
 }
 
 // Masked mean-squared error and its gradient (BF16):
@@ -481,7 +504,7 @@ __global__ void k_masked_mse(const float *pred, int cp, const float *target, con
                              const float *count, uint16_t *g, int cg, float *loss_parts)
 {
     __shared__ float red[256];
-    const float cnt = *count * (float)c;
+    const float cnt = (float)*(const int *)count * (float)c;
     const float inv_count = cnt > 0.0f ? 1.0f / cnt : 0.0f;
     float s = 0.0f;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nvox * cg; e += (long long)gridDim.x * blockDim.x) {
@@ -672,7 +695,10 @@ hipError_t wgrad(const WgradArgs &a, hipStream_t st)
 hipError_t bias_grad(const uint16_t *g, long long nvox, int cg, int g_off, int cout, float *gb, int accumulate,
                      hipStream_t st)
 {
-    k_bias_grad<<<cout, 256, 0, st>>>(g, nvox, cg, g_off, cout, gb, accumulate);
+    if (cout > 128) return hipErrorInvalidValue;
+    if (!accumulate) k_fill_f<<<(cout + 63) / 64, 64, 0, st>>>(gb, cout, 0.0f);
+    const long long nb = (nvox + BIAS_CHUNK - 1) / BIAS_CHUNK;
+    k_bias_grad<<<(unsigned)nb, 256, 0, st>>>(g, nvox, cg, g_off, cout, gb);
     return hipGetLastError();
 }
 
@@ -707,8 +733,11 @@ hipError_t to_bf16(const float *x, int cs, long long nvox, int c, uint16_t *y, i
 hipError_t masked_mse(const float *pred, int cp, const float *target, const float *mask, long long nvox, int c,
                       uint16_t *g, int cg, float *loss_parts, int nparts, hipStream_t st)
 {
-    k_mask_count<<<1, 256, 0, st>>>(mask, nvox, loss_parts + nparts);
+    int *slot = (int *)(loss_parts + nparts);
+    k_int_slot<<<1, 1, 0, st>>>(slot, 0);
+    k_mask_count<<<grid_for(nvox), 256, 0, st>>>(mask, nvox, slot);
     k_masked_mse<<<nparts, 256, 0, st>>>(pred, cp, target, mask, nvox, c, loss_parts + nparts, g, cg, loss_parts);
+    k_int_slot<<<1, 1, 0, st>>>(slot, 1);
     return hipGetLastError();
 }
 
