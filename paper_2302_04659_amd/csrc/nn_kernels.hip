@@ -362,6 +362,129 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
     }
 }
 
+// LDS-tiled weight gradient (3^3 and up kinds).  Workgroup (group, cf, tg):
+// the output tiles [group * tpg, (group + 1) * tpg), input channels
+// [16 cf, 16 cf + 16) and taps [8 tg, 8 tg + 8).  Per tile it stages the
+// input halo channel-major (xh[ci][halo voxel]) and the output-gradient tile
+// voxel-packed (gt[co][4-voxel pack]); wave w owns taps 8 tg + w and
+// 8 tg + w + 4 and accumulates, over the tile's voxels (K = 16 voxels = one
+// x row per MFMA), D[ci][co] += sum_v X[v + tap][ci] dY[v][co].  The partial
+// of the group goes to P[group][tap][ci][co].
+template <int NF, int KIND>
+__global__ __launch_bounds__(256) void k_wgrad_lds(WgradArgs a, int tpg, int ntiles)
+{
+    constexpr int TZ = NF == 8 ? 2 : 4;            // tile depth (LDS budget of the gradient tile)
+    constexpr int TV = TZ * TLY * TLX;             // tile voxels
+    constexpr int HZ = TZ + 2;
+    __shared__ unsigned short xh[16 * HZ * HLY * HLX];
+    __shared__ uint2 gt[NF * 16 * (TV / 4)];
+    unsigned short *gts = (unsigned short *)gt;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int cf = blockIdx.y, tg = blockIdx.z;
+    const int tiles_x = (a.ow + TLX - 1) / TLX, tiles_y = (a.oh + TLY - 1) / TLY, tiles_z = (a.od + TZ - 1) / TZ;
+    int hz, hy, hx;
+    if (KIND == KIND_C3) { hz = HZ; hy = HLY; hx = HLX; }
+    else { hz = TZ / 2 + 2; hy = TLY / 2 + 2; hx = TLX / 2 + 2; }
+    const int nh = hz * hy * hx;
+    const int t0 = 8 * tg + wv, t1 = t0 + 4;
+    const int tmax = min(27, 8 * tg + 8);
+    f4 acc[2][NF];
+#pragma unroll
+    for (int u = 0; u < 2; u++)
+#pragma unroll
+        for (int n = 0; n < NF; n++) acc[u][n] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int q = lane >> 4, i = lane & 15;
+    const int tile_end = min(ntiles, (int)(blockIdx.x + 1) * tpg);
+    for (int tile = blockIdx.x * tpg; tile < tile_end; tile++) {
+        int b = tile;
+        const int bx = b % tiles_x;
+        b /= tiles_x;
+        const int by = b % tiles_y;
+        b /= tiles_y;
+        const int bz = b % tiles_z;
+        const int bn = b / tiles_z;
+        const int z0 = bz * TZ, y0 = by * TLY, x0 = bx * TLX;
+        int hz0, hy0, hx0;
+        if (KIND == KIND_C3) { hz0 = z0 - 1; hy0 = y0 - 1; hx0 = x0 - 1; }
+        else { hz0 = (z0 >> 1) - 1; hy0 = (y0 >> 1) - 1; hx0 = (x0 >> 1) - 1; }
+        // input halo, channels [16 cf, 16 cf + 16), stored channel-major
+        for (int e = threadIdx.x; e < nh * 4; e += 256) {
+            const int v = e >> 2, qq = e & 3;
+            const int lx = v % hx, ly = (v / hx) % hy, lz = v / (hx * hy);
+            const int gz = hz0 + lz, gy = hy0 + ly, gx = hx0 + lx;
+            uint2 val = make_uint2(0u, 0u);
+            if (gz >= 0 && gy >= 0 && gx >= 0 && gz < a.id && gy < a.ih && gx < a.iw)
+                val = *(const uint2 *)(a.x + ((((long long)bn * a.id + gz) * a.ih + gy) * a.iw + gx) * a.cx + a.x_off +
+                                       16 * cf + 4 * qq);
+            const int c0 = 4 * qq;
+            xh[(c0 + 0) * nh + v] = (unsigned short)(val.x & 0xffff);
+            xh[(c0 + 1) * nh + v] = (unsigned short)(val.x >> 16);
+            xh[(c0 + 2) * nh + v] = (unsigned short)(val.y & 0xffff);
+            xh[(c0 + 3) * nh + v] = (unsigned short)(val.y >> 16);
+        }
+        // output-gradient tile, [co][voxel]
+        for (int e = threadIdx.x; e < TV * NF * 4; e += 256) {
+            const int v = e / (NF * 4), qq = e % (NF * 4);
+            const int tx = v % TLX, ty = (v / TLX) % TLY, tz = v / (TLX * TLY);
+            const int oz = z0 + tz, oy = y0 + ty, ox = x0 + tx;
+            const int c0 = 4 * qq;
+            unsigned short w4[4] = {0, 0, 0, 0};
+            if (oz < a.od && oy < a.oh && ox < a.ow) {
+                const long long gv = (((long long)bn * a.od + oz) * a.oh + oy) * a.ow + ox;
+                const uint16_t *gp = a.g + gv * a.cg + a.g_off + c0;
+                for (int k = 0; k < 4; k++) w4[k] = (c0 + k < a.cout) ? gp[k] : (unsigned short)0;
+            }
+            for (int k = 0; k < 4; k++) gts[(c0 + k) * TV + v] = w4[k];
+        }
+        __syncthreads();
+        for (int row = 0; row < TZ * TLY; row++) {
+            const int tz = row / TLY, ty = row % TLY;
+            s4 Bv[NF];
+#pragma unroll
+            for (int n = 0; n < NF; n++) {
+                const uint2 raw = gt[(16 * n + i) * (TV / 4) + (row * TLX + 4 * q) / 4];
+                Bv[n] = s4{(short)(raw.x & 0xffff), (short)(raw.x >> 16), (short)(raw.y & 0xffff), (short)(raw.y >> 16)};
+            }
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                const int t = u ? t1 : t0;
+                if (t >= tmax) continue;
+                const int ta = t / 9, tb = (t / 3) % 3, tc = t % 3;
+                s4 Av;
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int tx = 4 * q + r;
+                    int lz, ly, lx;
+                    if (KIND == KIND_C3) { lz = tz + ta; ly = ty + tb; lx = tx + tc; }
+                    else {
+                        lz = ((z0 + tz + ta - 1) >> 1) - hz0;
+                        ly = ((y0 + ty + tb - 1) >> 1) - hy0;
+                        lx = ((x0 + tx + tc - 1) >> 1) - hx0;
+                    }
+                    Av[r] = (short)xh[i * nh + (lz * hy + ly) * hx + lx];
+                }
+#pragma unroll
+                for (int n = 0; n < NF; n++) acc[u][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Av, Bv[n], acc[u][n], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // D[i][j]: ci = 16 cf + 4 (lane / 16) + r, co = 16 n + lane % 16
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+        const int t = u ? t1 : t0;
+        if (t >= tmax) continue;
+        float *P = a.partial + ((long long)blockIdx.x * 27 + t) * a.cin * a.cout;
+#pragma unroll
+        for (int n = 0; n < NF; n++) {
+            const int co = 16 * n + (lane & 15);
+            if (co >= a.cout) continue;
+#pragma unroll
+            for (int r = 0; r < 4; r++) P[(long long)(16 * cf + 4 * (lane >> 4) + r) * a.cout + co] = acc[u][n][r];
+        }
+    }
+}
+
 __global__ void k_reduce_partials(const float *partial, int nchunk, long long per, float *out, int accumulate)
 {
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < per; e += (long long)gridDim.x * blockDim.x) {
@@ -673,8 +796,34 @@ hipError_t pack(const float *w, int ntap, int cin, int cout, int cin_p, int cout
     return hipGetLastError();
 }
 
+template <int KIND>
+static hipError_t wgrad_lds(const WgradArgs &a, hipStream_t st)
+{
+    const int nf = (a.cout + 15) / 16;
+    const int TZ = nf == 8 ? 2 : 4;
+    const long long nvox = (long long)a.n * a.od * a.oh * a.ow;
+    const long long ntiles = (long long)a.n * ((a.od + TZ - 1) / TZ) * ((a.oh + TLY - 1) / TLY) * ((a.ow + TLX - 1) / TLX);
+    const long long groups_max = (nvox + a.chunk - 1) / a.chunk;          // the partial buffer holds this many
+    const long long tpg = (ntiles + groups_max - 1) / groups_max;
+    const long long groups = (ntiles + tpg - 1) / tpg;
+    if (ntiles > 0x7fffffff || groups > 65535) return hipErrorInvalidValue;
+    const dim3 g((unsigned)groups, (unsigned)(a.cin / 16), 4);
+    switch (nf) {
+    case 1: k_wgrad_lds<1, KIND><<<g, 256, 0, st>>>(a, (int)tpg, (int)ntiles); break;
+    case 2: k_wgrad_lds<2, KIND><<<g, 256, 0, st>>>(a, (int)tpg, (int)ntiles); break;
+    case 4: k_wgrad_lds<4, KIND><<<g, 256, 0, st>>>(a, (int)tpg, (int)ntiles); break;
+    case 8: k_wgrad_lds<8, KIND><<<g, 256, 0, st>>>(a, (int)tpg, (int)ntiles); break;
+    default: return hipErrorInvalidValue;
+    }
+    const long long per = 27LL * a.cin * a.cout;
+    k_reduce_partials<<<grid_for(per), 256, 0, st>>>(a.partial, (int)groups, per, a.gw, a.accumulate);
+    return hipGetLastError();
+}
+
 hipError_t wgrad(const WgradArgs &a, hipStream_t st)
 {
+    if (a.kind == KIND_C3) return wgrad_lds<KIND_C3>(a, st);
+    if (a.kind == KIND_UP) return wgrad_lds<KIND_UP>(a, st);
     const int ks = a.kind == KIND_C3 || a.kind == KIND_UP ? 3 : (a.kind == KIND_DOWN ? 2 : 1);
     const int ntap = ks * ks * ks;
     const long long nvox = (long long)a.n * a.od * a.oh * a.ow;

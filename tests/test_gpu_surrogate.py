@@ -196,14 +196,15 @@ def test_advance_reproduces_linear_field(env, u):
     sim.close()
 
 
-def test_residual_gate_falls_back_per_scene(env, orc):
+@pytest.mark.parametrize("graph", [0, 1])
+def test_residual_gate_falls_back_per_scene(env, orc, graph):
     """Scene 1 gets a wild prediction and falls back (plain substeps, oracle
     bar); scenes 0 and 2 stay on the surrogate, bit-identical to a second
     context given the same start grid and prediction with the fallback
     switched off (the particle advance is deterministic)."""
     torch, mpm = env
     batch = _batch()
-    announce("surrogate residual gate", len(batch))
+    announce("surrogate residual gate", len(batch), "graph", graph)
     S, R = len(batch), batch[0].res
     ts = _new_stream(torch)
     with torch.cuda.stream(ts):
@@ -214,6 +215,7 @@ def test_residual_gate_falls_back_per_scene(env, orc):
     outs = []
     for fallback in (True, False):
         sim = mpm.Sim(batch, stream=ts.cuda_stream)
+        sim.set_option(mpm.OPT_GRAPH, graph)      # the fallback substeps replay a captured graph
         sim.set_colliders_ctrl(0)
         with torch.cuda.stream(ts):
             residual = torch.zeros(S, dtype=torch.float32, device="cuda")
