@@ -74,10 +74,13 @@ class GridSurrogate:
     """Runs control steps of a Sim through a trained UNet.  Everything is
     queued on the Sim's stream."""
 
-    def __init__(self, sim: "_mpm.Sim", net: UNet, threshold: float = 1e-3, chunk: int = 16, margin: int = 4,
+    def __init__(self, sim: "_mpm.Sim", net: UNet, threshold: float = 1e-3, chunk: int = 0, margin: int = 4,
                  crop: bool = True):
         torch = _torch()
-        self.sim, self.net, self.threshold, self.chunk = sim, net, float(threshold), int(chunk)
+        # scenes per network launch (0: all at once -- the coarse levels of a crop are small, and only
+        # a large batch fills the GPU; activations take ~1 KB per crop voxel)
+        self.sim, self.net, self.threshold = sim, net, float(threshold)
+        self.chunk = int(chunk) if chunk > 0 else sim.n_scenes
         self.margin, self.crop = int(margin), bool(crop)
         self.ts = _stream_of(sim)
         R = sim.scenes[0].res
