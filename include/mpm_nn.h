@@ -69,8 +69,9 @@ int mpm_nn_up_bwd(const uint16_t *fine, int cf, int f_off, uint16_t *coarse, int
                   int w, int c, void *stream);
 
 /* Input gradient of the 2^3 stride-2 convolution with FP32 weights w
- * [8][cin][cout]; (n, d, h, wd) are the fine (input) sizes; accumulate = 1
- * adds to gx (a skip connection's gradient already there). */
+ * [8][cin][cout] (16-byte aligned for the MFMA path), which are rounded to
+ * BF16 as in every other adjoint; (n, d, h, wd) are the fine (input) sizes;
+ * accumulate = 1 adds to gx (a skip connection's gradient already there). */
 int mpm_nn_down_dgrad(const uint16_t *g, int cg, int g_off, const float *w, int cin, int cout, uint16_t *gx, int cx,
                       int x_off, int n, int d, int h, int wd, int accumulate, void *stream);
 

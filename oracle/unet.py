@@ -184,11 +184,12 @@ def forward(params, x, cin, cout, width=1, q=None):
 def backward(params, cache, gout, cin, cout, width=1, q=None):
     """Gradients of every parameter for the output gradient `gout`.
 
-    With q (see forward): every input gradient is rounded where a BF16
-    implementation stores it -- after each convolution adjoint (computed
-    with the rounded weights), after the upsampling adjoint, and where a
-    skip gradient is summed in; the stride-2 adjoint uses the exact weights
-    and is rounded only in that sum.  Parameter gradients stay exact."""
+    With q (see forward): every convolution adjoint is computed with the
+    rounded weights, and every input gradient is rounded where a BF16
+    implementation stores it -- after each convolution adjoint, after the
+    upsampling adjoint, and where a skip gradient is summed in (the
+    stride-2 adjoint writes straight into that sum and is rounded only
+    there).  Parameter gradients stay exact."""
     q_ = q if q is not None else (lambda a: a)
     grads = {}
     shapes = layer_shapes(cin, cout, width)
@@ -206,7 +207,7 @@ def backward(params, cache, gout, cin, cout, width=1, q=None):
             gin, gw, gb = conv3_backward(inp, q_(w), g)
             gin = q_(gin)
         elif kind == "down":
-            gin, gw, gb = down_backward(inp, w, g)
+            gin, gw, gb = down_backward(inp, q_(w), g)
         else:
             gin, gw, gb = conv1_backward(inp, q_(w), g)
             gin = q_(gin)

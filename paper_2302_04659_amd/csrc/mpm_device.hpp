@@ -67,6 +67,40 @@ __device__ __forceinline__ void particle_base(const SceneDev &S, float x, int &b
     f = xi - (float)c;
 }
 
+// Scene constants a particle loop uses, read once into scalar registers.
+// Without the copy, every particle store (which, as far as the compiler
+// knows, may alias the scene table) forces a reload and a wait on all
+// outstanding memory operations before the next use.
+struct SceneK {
+    int res;
+    float dx, inv_dx, dt, mass, kstress;
+};
+
+__device__ __forceinline__ float uniform_f(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+
+__device__ __forceinline__ SceneK scene_k(const SceneDev &S)
+{
+    SceneK k;
+    k.res = __builtin_amdgcn_readfirstlane(S.res);
+    k.dx = uniform_f(S.dx);
+    k.inv_dx = uniform_f(S.inv_dx);
+    k.dt = uniform_f(S.dt);
+    k.mass = uniform_f(S.mass);
+    k.kstress = uniform_f(S.kstress);
+    return k;
+}
+
+__device__ __forceinline__ void particle_base(const SceneK &K, float x, int &b, float &f, int &clamped)
+{
+    float xi = x * K.inv_dx;
+    float fb = floorf(xi - 0.5f);
+    int bi = (int)fb;
+    int c = bi < 0 ? 0 : (bi > K.res - 3 ? K.res - 3 : bi);
+    clamped |= (c != bi) || !(fb == fb);
+    b = c;
+    f = xi - (float)c;
+}
+
 __device__ __forceinline__ Material material_of(const SceneDev &S)
 {
     Material m;

@@ -21,6 +21,8 @@
 #include "mpm_kernels.hpp"
 #include "mpm_types.hpp"
 
+static_assert(MPM_MAX_COLLIDERS == mpm::MAX_COLLIDERS_PER_SCENE, "grid kernel LDS collider slots");
+
 using namespace mpm;
 
 namespace {

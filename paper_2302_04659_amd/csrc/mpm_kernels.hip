@@ -207,7 +207,9 @@ constexpr long long BIN_SCRAMBLE = 104729;   // prime
 
 __global__ __launch_bounds__(WG) void k_scatter(SortArgs a)
 {
-    const int j = blockIdx.x * WG + threadIdx.x;
+    // each XCD takes a contiguous share of the particles, so the bins one
+    // XCD writes are not also pulled into the L2 of the others
+    const int j = xcd_remap(blockIdx.x, gridDim.x) * WG + threadIdx.x;
     const bool valid = j < a.N;
     const unsigned key = valid ? a.keys[j] : 0xFFFFFFFFu;
     const KeyRun r = key_run(key);
@@ -279,11 +281,20 @@ __global__ __launch_bounds__(WG) void k_bank_order(SortArgs a)
 
 __global__ __launch_bounds__(WG) void k_gather(SortArgs a)
 {
-    int p = blockIdx.x * WG + threadIdx.x;
+    // contiguous share per XCD: the sources of a bin (scattered over that
+    // bin's old range) are fetched into one L2 rather than into all eight
+    int p = xcd_remap(blockIdx.x, gridDim.x) * WG + threadIdx.x;
     if (p >= a.N) return;
     int j = a.perm2[p];
+    // all loads before any store: the compiler cannot tell that the two
+    // buffers do not overlap, and would otherwise wait for each store
+    const float *__restrict__ src = a.P;
+    float *__restrict__ dst = a.Pn;
+    float v[NCOMP];
 #pragma unroll
-    for (int c = 0; c < NCOMP; c++) a.Pn[(long long)c * a.pstride + p] = a.P[(long long)c * a.pstride + j];
+    for (int c = 0; c < NCOMP; c++) v[c] = src[(long long)c * a.pstride + j];
+#pragma unroll
+    for (int c = 0; c < NCOMP; c++) dst[(long long)c * a.pstride + p] = v[c];
 }
 
 // Scale bound of every new work item (the P2G fixed-point scale), from the
@@ -321,10 +332,11 @@ hipError_t launch_sort(const SortArgs &a, hipStream_t st)
     k_scan_top<<<1, WG, 0, st>>>(a, ntiles);
     k_scan_emit<<<ntiles, WG, 0, st>>>(a);
     if (a.N > 0) {
-        k_scatter<<<gN, WG, 0, st>>>(a);
+        const int gN8 = (gN + 7) & ~7;    // xcd_remap needs a multiple of 8 workgroups
+        k_scatter<<<gN8, WG, 0, st>>>(a);
         if (a.B == 4) k_bank_order<4><<<2048, WG, 0, st>>>(a);
         else k_bank_order<8><<<2048, WG, 0, st>>>(a);
-        k_gather<<<gN, WG, 0, st>>>(a);
+        k_gather<<<gN8, WG, 0, st>>>(a);
         k_item_bounds<<<2048, WG, 0, st>>>(a);
     }
     return hipGetLastError();
@@ -418,14 +430,15 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
 
     // Power-of-two fixed-point scales keeping every node sum below 2^30:
     // |contribution| <= w * bound, w <= 0.421875, at most item.count particles.
+    const SceneK K = scene_k(S);
     const float lim = 1073741824.0f / (0.421875f * (float)item.count);
-    int em = ilogbf(lim / S.mass);
+    int em = ilogbf(lim / K.mass);
     em = min(max(em, -120), 120);
     int ep = bmax > 0.0f ? ilogbf(lim / bmax) : 120;
     ep = min(max(ep, -120), 120);
     const float Sm = ldexpf(1.0f, em), Sp = ldexpf(1.0f, ep);
-    const float kk = Sp / (Sm * S.mass);       // momentum scale relative to the mass-scaled weight
-    const float msc = Sm * S.mass;
+    const float kk = Sp / (Sm * K.mass);       // momentum scale relative to the mass-scaled weight
+    const float msc = Sm * K.mass;
 
     for (int base = 0; base < item.count; base += WG) {
         const int li = base + t;
@@ -436,7 +449,7 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
         int cl = 0, in = 1;
 #pragma unroll
         for (int d = 0; d < 3; d++) {
-            particle_base(S, x[d], bp[d], f[d], cl);
+            particle_base(K, x[d], bp[d], f[d], cl);
             int tb = bp[d] - org[d];
             in &= (tb >= 0) & (tb <= B + 1);
         }
@@ -456,8 +469,8 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
 #pragma unroll
         for (int c = 0; c < 3; c++) {
 #pragma unroll
-            for (int e = 0; e < 3; e++) Ad[c][e] = kk * A[3 * c + e] * S.dx;
-            r0[c] = kk * S.mass * v[c] - (Ad[c][0] * f[0] + Ad[c][1] * f[1] + Ad[c][2] * f[2]);
+            for (int e = 0; e < 3; e++) Ad[c][e] = kk * A[3 * c + e] * K.dx;
+            r0[c] = kk * K.mass * v[c] - (Ad[c][0] * f[0] + Ad[c][1] * f[1] + Ad[c][2] * f[2]);
         }
         int *tb = tile + ((bp[0] - org[0]) * T + (bp[1] - org[1])) * T + (bp[2] - org[2]);
 #pragma unroll
@@ -515,21 +528,38 @@ __global__ __launch_bounds__(WG) void k_p2g(StepArgs a)
 
 // ---------------------------------------------------------------- grid update
 template <int B>
-__device__ void grid_block(const StepArgs &a, int s, int lb, int lane)
+// cl: this wave's LDS copy of the scene's colliders (at most
+// MAX_COLLIDERS_PER_SCENE).
+// The node loop stores to the grid; reading the colliders and the scene
+// constants from LDS and registers keeps the compiler from reloading them
+// from global memory (and waiting for the stores) on every node.
+__device__ void grid_block(const StepArgs &a, int s, int lb, int lane, ColliderNow *cl)
 {
     const SceneDev &S = a.scenes[s];
     unsigned char *tf = a.L.touched + S.bin_off + lb;
     if (!*tf) return;          // no P2G wrote into this block: every (m, p) in it is zero
     const int nb = S.nb;
     const int bx = lb / (nb * nb), by = (lb / nb) % nb, bz = lb % nb;
-    const ColliderNow *cn = (const ColliderNow *)a.colnow + S.col_off;
+    const int n_col = __builtin_amdgcn_readfirstlane(S.n_col);
+    const int bound = __builtin_amdgcn_readfirstlane(S.bound);
+    const SceneK K = scene_k(S);
+    const float gdt[3] = {K.dt * uniform_f(S.g[0]), K.dt * uniform_f(S.g[1]), K.dt * uniform_f(S.g[2])};
+    const long long goff = S.grid_off;
+    {
+        const float *src = (const float *)((const ColliderNow *)a.colnow + S.col_off);
+        float *dst = (float *)cl;
+        for (int q = lane; q < n_col * (int)(sizeof(ColliderNow) / 4); q += 64) dst[q] = src[q];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     for (int l = lane; l < B * B * B; l += 64) {
-        long long idx = S.grid_off + (long long)lb * (B * B * B) + l;
+        long long idx = goff + (long long)lb * (B * B * B) + l;
         float m = a.gm[idx], px = a.gpx[idx], py = a.gpy[idx], pz = a.gpz[idx];
         if (m == 0.0f && px == 0.0f && py == 0.0f && pz == 0.0f) continue;
         int ii[3] = {bx * B + l / (B * B), by * B + (l / B) % B, bz * B + l % B};
         if (a.cap) {
-            long long c = a.cap_off[s] + ((long long)ii[0] * S.res + ii[1]) * S.res + ii[2];
+            long long c = a.cap_off[s] + ((long long)ii[0] * K.res + ii[1]) * K.res + ii[2];
             a.cap[4 * c] = m;
             a.cap[4 * c + 1] = px;
             a.cap[4 * c + 2] = py;
@@ -541,15 +571,15 @@ __device__ void grid_block(const StepArgs &a, int s, int lb, int lane)
             v[1] = py / m;
             v[2] = pz / m;
         }
-        for (int d = 0; d < 3; d++) v[d] += S.dt * S.g[d];
-        float xi[3] = {ii[0] * S.dx, ii[1] * S.dx, ii[2] * S.dx};
-        for (int c = 0; c < S.n_col; c++) collide_node(cn[c], xi, v);
+        for (int d = 0; d < 3; d++) v[d] += gdt[d];
+        float xi[3] = {ii[0] * K.dx, ii[1] * K.dx, ii[2] * K.dx};
+        for (int c = 0; c < n_col; c++) collide_node(cl[c], xi, v);
         for (int d = 0; d < 3; d++) {
-            if (ii[d] < S.bound && v[d] < 0.0f) v[d] = 0.0f;
-            if (ii[d] >= S.res - S.bound && v[d] > 0.0f) v[d] = 0.0f;
+            if (ii[d] < bound && v[d] < 0.0f) v[d] = 0.0f;
+            if (ii[d] >= K.res - bound && v[d] > 0.0f) v[d] = 0.0f;
         }
         if (a.dense) {   // (m, p / m) of the P2G, before gravity, colliders and walls
-            const long long c = a.cap_off[s] + ((long long)ii[0] * S.res + ii[1]) * S.res + ii[2];
+            const long long c = a.cap_off[s] + ((long long)ii[0] * K.res + ii[1]) * K.res + ii[2];
             const float im = m > 0.0f ? 1.0f / m : 0.0f;
             *(float4 *)(a.dense + 4 * c) = make_float4(m, px * im, py * im, pz * im);
             if (a.feat) {
@@ -578,11 +608,12 @@ __global__ __launch_bounds__(WG) void k_grid(StepArgs a)
     const int lane = threadIdx.x & 63;
     const int nw = gridDim.x * (WG / 64);
     const int w0 = xcd_remap(blockIdx.x, gridDim.x) * (WG / 64) + (threadIdx.x >> 6);
+    __shared__ ColliderNow cls[WG / 64][MAX_COLLIDERS_PER_SCENE];
     const int ng = *a.L.n_gitems;
     const int no = min(*a.L.n_ovf, a.L.ovf_cap);
     for (int w = w0; w < ng + no; w += nw) {
         int2 e = w < ng ? a.L.gitems[w] : a.L.ovf[w - ng];
-        grid_block<B>(a, e.x, e.y, lane);
+        grid_block<B>(a, e.x, e.y, lane, cls[threadIdx.x >> 6]);
         if (w >= ng && lane == 0) a.L.bflag[a.scenes[e.x].bin_off + e.y] = 0;
     }
 }
@@ -613,6 +644,7 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt)
     }
     __syncthreads();
     const Material mat = material_of(S);
+    const SceneK K = scene_k(S);
     const long long ps = a.pstride;
     int bad_any = 0, cl_any = 0;
     float bnd = 0.0f;
@@ -627,7 +659,7 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt)
         float f[3];
 #pragma unroll
         for (int d = 0; d < 3; d++) {
-            particle_base(S, x[d], b[d], f[d], cl);
+            particle_base(K, x[d], b[d], f[d], cl);
             int tb = b[d] - org[d];
             in &= (tb >= 0) & (tb <= B + 1);
         }
@@ -684,14 +716,14 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt)
                     }
         }
         // C = (4/dx^2) sum w v (x_i - x_p)^T = (4/dx) (So - vp f^T)
-        const float Dd = 4.0f * S.inv_dx;
+        const float Dd = 4.0f * K.inv_dx;
         float C[9];
 #pragma unroll
         for (int c = 0; c < 3; c++)
 #pragma unroll
             for (int e = 0; e < 3; e++) C[3 * c + e] = Dd * fmaf(-vp[c], f[e], So[c][e]);
 #pragma unroll
-        for (int d = 0; d < 3; d++) x[d] = fmaf(S.dt, vp[d], x[d]);
+        for (int d = 0; d < 3; d++) x[d] = fmaf(K.dt, vp[d], x[d]);
         // F <- (I + dt C) F  ->  G <- G + dt C + dt C G
         float Gt[9];
 #pragma unroll
@@ -701,7 +733,7 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt)
                 float acc = C[3 * i + k];
 #pragma unroll
                 for (int e = 0; e < 3; e++) acc = fmaf(C[3 * i + e], G[3 * e + k], acc);
-                Gt[3 * i + k] = fmaf(S.dt, acc, G[3 * i + k]);
+                Gt[3 * i + k] = fmaf(K.dt, acc, G[3 * i + k]);
             }
         float tau[9], Gn[9];
         int bad = 0;
@@ -722,11 +754,11 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt)
         float An[9];
 #pragma unroll
         for (int e = 0; e < 9; e++) {
-            An[e] = fmaf(S.mass, C[e], -S.kstress * tau[e]);
+            An[e] = fmaf(K.mass, C[e], -K.kstress * tau[e]);
             pstore(a.P, ps, A00 + e, jo, An[e]);
             pstore(a.P, ps, G00 + e, jo, Gn[e]);
         }
-        bnd = fmaxf(bnd, scatter_bound(S.mass, S.dx, vp, An));
+        bnd = fmaxf(bnd, scatter_bound(K.mass, K.dx, vp, An));
     }
     bnd = wave_max(bnd);
     if ((t & 63) == 0 && bnd > 0.0f) atomicMax((int *)(a.L.ibound + it), __float_as_int(bnd));
@@ -804,6 +836,7 @@ __global__ __launch_bounds__(WG) void k_substep_persistent(StepArgs a)
     constexpr int T = B + 4, T3 = T * T * T;
     __shared__ int smem[4 * T3];
     __shared__ int s_q;
+    __shared__ ColliderNow cls[WG / 64][MAX_COLLIDERS_PER_SCENE];
     const int n_items = *a.L.n_items;
     const int n_g = *a.L.n_gitems;
     const int n_grid = n_g + a.n_scenes;
@@ -838,13 +871,13 @@ __global__ __launch_bounds__(WG) void k_substep_persistent(StepArgs a)
                 }
                 wait_counter(&p2g_done[s], a.L.scene_item_begin[s + 1] - a.L.scene_item_begin[s], a.flags + s);
                 if (lb >= 0) {
-                    grid_block<B>(a, s, lb, lane);
+                    grid_block<B>(a, s, lb, lane, cls[wv]);
                 } else {
                     const int no = min(*a.L.n_ovf, a.L.ovf_cap);
                     for (int k = 0; k < no; k++) {
                         int2 e = a.L.ovf[k];
                         if (e.x != s) continue;
-                        grid_block<B>(a, s, e.y, lane);
+                        grid_block<B>(a, s, e.y, lane, cls[wv]);
                         if (lane == 0) a.L.bflag[a.scenes[s].bin_off + e.y] = 0;
                     }
                 }

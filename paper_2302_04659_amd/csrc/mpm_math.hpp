@@ -163,13 +163,17 @@ MPM_HD void jacobi_rot(float &app, float &aqq, float &apq, float &arp, float &ar
     aqq = s * s * a_pp + 2.0f * c * s * a_pq + c * c * a_qq;
     apq = (c * c - s * s) * a_pq + c * s * (a_pp - a_qq);
 #else
+    // t = tan of the rotation angle, the root of t^2 + 2 zeta t - 1 = 0 of
+    // smaller magnitude, zeta = (aqq - app) / (2 apq), written with d = aqq - app
+    // as t = sgn(d) 2 apq / (|d| + sqrt(d^2 + 4 apq^2)): one square root and
+    // one reciprocal.
     float t = 0.0f;
     if (apq != 0.0f) {
-        float zeta = (aqq - app) * frcp(2.0f * apq);
-        float az = fabsf(zeta);
-        float tt = frcp(az + fsqrt(fmaf(az, az, 1.0f)));
-        t = zeta >= 0.0f ? tt : -tt;
-        if (az > 1e18f) t = 0.0f;     // rotation smaller than rounding
+        const float d = aqq - app;
+        const float ad = fabsf(d);
+        const float den = ad + fsqrt(fmaf(d, d, 4.0f * apq * apq));
+        t = den > 0.0f ? 2.0f * apq * frcp(den) : copysignf(1.0f, apq);   // den = 0: d = 0 and apq^2 underflows
+        if (d < 0.0f) t = -t;
     }
     float c = frsqrt(fmaf(t, t, 1.0f));
     float s = t * c;

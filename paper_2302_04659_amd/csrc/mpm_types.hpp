@@ -19,6 +19,8 @@ enum Comp : int {
 
 enum Flag : int { FLAG_CLAMPED = 1, FLAG_NONFINITE = 2, FLAG_SPIN = 4, FLAG_OVERFLOW_FULL = 8 };
 
+constexpr int MAX_COLLIDERS_PER_SCENE = 4;   // equals MPM_MAX_COLLIDERS of the public header
+
 struct SceneDev {
     int p_begin, p_end;       // particle slots
     int res, nb;              // nodes per axis, blocks per axis

@@ -251,23 +251,153 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
     }
 }
 
+// The same tiling on v_mfma_f32_16x16x32_bf16 for a multiple of 32 input
+// channels.  K slot 4 h + r of lane group g (= lane / 16) carries channel
+// 16 h + 4 g + r of the 32-channel chunk, for A (halo) and B (packed weights)
+// alike.  The halo holds, per voxel, four 16-byte pairs (channels 4 g .. 4 g + 3
+// and 16 + 4 g .. 16 + 4 g + 3), pair g stored at slot g ^ ((v >> 2) & 3) so
+// that the 16-byte reads of 8 neighbouring x voxels hit distinct banks.  For
+// each (z tap, x tap) a wave reads the six halo rows its four output rows see
+// through the three y taps once.
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+
+template <int NF, int KIND>
+__global__ __launch_bounds__(256, 2) void k_conv_lds32(ConvArgs a)
+{
+    __shared__ uint4 halo[HLZ * HLY * HLX * 4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tiles_x = (a.ow + TLX - 1) / TLX, tiles_y = (a.oh + TLY - 1) / TLY, tiles_z = (a.od + TLZ - 1) / TLZ;
+    int b = blockIdx.x;
+    const int bx = b % tiles_x;
+    b /= tiles_x;
+    const int by = b % tiles_y;
+    b /= tiles_y;
+    const int bz = b % tiles_z;
+    const int bn = b / tiles_z;
+    const int z0 = bz * TLZ, y0 = by * TLY, x0 = bx * TLX;
+    int hz0, hy0, hx0, hz, hy, hx;
+    if (KIND == KIND_C3) {
+        hz0 = z0 - 1; hy0 = y0 - 1; hx0 = x0 - 1;
+        hz = HLZ; hy = HLY; hx = HLX;
+    } else {
+        hz0 = (z0 >> 1) - 1; hy0 = (y0 >> 1) - 1; hx0 = (x0 >> 1) - 1;
+        hz = TLZ / 2 + 2; hy = TLY / 2 + 2; hx = TLX / 2 + 2;
+    }
+    const int nh = hz * hy * hx;
+    f4 acc[4][NF];
+#pragma unroll
+    for (int f = 0; f < 4; f++)
+#pragma unroll
+        for (int n = 0; n < NF; n++) acc[f][n] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int kc = a.cin / 32;
+    const int g = lane >> 4, i = lane & 15;
+    uint2 *h2 = (uint2 *)halo;
+    for (int c = 0; c < kc; c++) {
+        // stage channels [32 c, 32 c + 32): thread element e -> voxel e / 8, 4-channel group e % 8
+        for (int e = threadIdx.x; e < nh * 8; e += 256) {
+            const int v = e >> 3, gg = e & 3, hh = (e >> 2) & 1;
+            const int lx = v % hx, ly = (v / hx) % hy, lz = v / (hx * hy);
+            const int gz = hz0 + lz, gy = hy0 + ly, gx = hx0 + lx;
+            uint2 val = make_uint2(0u, 0u);
+            if (gz >= 0 && gy >= 0 && gx >= 0 && gz < a.id && gy < a.ih && gx < a.iw)
+                val = *(const uint2 *)(a.x + ((((long long)bn * a.id + gz) * a.ih + gy) * a.iw + gx) * a.cx + a.x_off +
+                                       32 * c + 16 * hh + 4 * gg);
+            h2[v * 8 + 2 * (gg ^ ((v >> 2) & 3)) + hh] = val;
+        }
+        __syncthreads();
+        const uint16_t *wc = a.w + (size_t)c * NF * 512 + 8 * lane;
+#pragma unroll 1
+        for (int ta = 0; ta < 3; ta++) {
+            int lz;
+            if (KIND == KIND_C3) lz = wv + ta;
+            else lz = ((z0 + wv + ta - 1) >> 1) - hz0;
+#pragma unroll 1
+            for (int tc = 0; tc < 3; tc++) {
+                int lx;
+                if (KIND == KIND_C3) lx = i + tc;
+                else lx = ((x0 + i + tc - 1) >> 1) - hx0;
+                b8 Ar[6];
+#pragma unroll
+                for (int r = 0; r < 6; r++) {
+                    int ly;
+                    if (KIND == KIND_C3) ly = r;
+                    else ly = ((y0 + r - 1) >> 1) - hy0;
+                    const int v = (lz * hy + ly) * hx + lx;
+                    Ar[r] = __builtin_bit_cast(b8, halo[v * 4 + (g ^ ((v >> 2) & 3))]);
+                }
+#pragma unroll
+                for (int tb = 0; tb < 3; tb++) {
+                    const int t = (ta * 3 + tb) * 3 + tc;
+                    const uint16_t *wt = wc + (size_t)t * kc * NF * 512;
+#pragma unroll
+                    for (int n = 0; n < NF; n++) {
+                        const b8 Bv = __builtin_bit_cast(b8, *(const uint4 *)(wt + (size_t)n * 512));
+#pragma unroll
+                        for (int f = 0; f < 4; f++)
+                            acc[f][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar[f + tb], Bv, acc[f][n], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const int oz = z0 + wv;
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+        const int oy = y0 + f;
+        if (oz >= a.od || oy >= a.oh) continue;
+#pragma unroll
+        for (int n = 0; n < NF; n++) {
+            const int co = 16 * n + (lane & 15);
+            if (co >= a.cout) continue;
+            const float bias = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int ox = x0 + 4 * (lane >> 4) + r;
+                if (ox >= a.ow) continue;
+                const long long v = (((long long)bn * a.od + oz) * a.oh + oy) * a.ow + ox;
+                float val = acc[f][n][r] + bias;
+                if (a.relu) val = fmaxf(val, 0.0f);
+                if (a.y) a.y[v * a.cy + a.y_off + co] = f2bf(val);
+                if (a.y32) a.y32[v * a.cy32 + co] = val;
+            }
+        }
+    }
+}
+
 // Pack FP32 master weights W[tap][ci][co] (ci < cin, co < cout) into the
 // B-fragment order the conv kernel reads, as BF16; `transpose` packs the
 // weights of the adjoint (dgrad) convolution: taps mirrored, ci <-> co.
-__global__ void k_pack(const float *w, int ntap, int cin, int cout, int cin_p, int cout_p, int transpose,
+//   k32 = 0: element (((t * KC + c) * NF + n) * 64 + lane) * 4 + r holds
+//            B[k][j], k = 16 c + 4 (lane / 16) + r (16x16x16 fragments);
+//   k32 = 1: element (((t * KC2 + c) * NF + n) * 64 + lane) * 8 + 4 h + r holds
+//            k = 32 c + 16 h + 4 (lane / 16) + r (16x16x32 fragments).
+__global__ void k_pack(const float *w, int ntap, int cin, int cout, int cin_p, int cout_p, int transpose, int k32,
                        uint16_t *out)
 {
-    // output element index = (((t * KC + c) * NF + n) * 64 + lane) * 4 + r
     const int KC = cin_p / 16, NF = cout_p / 16;
     const long long total = (long long)ntap * KC * NF * 256;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
-        const int r = (int)(e & 3), lane = (int)((e >> 2) & 63);
-        long long q = e >> 8;
-        const int n = (int)(q % NF);
-        q /= NF;
-        const int c = (int)(q % KC);
-        const int t = (int)(q / KC);
-        const int k = 16 * c + 4 * (lane >> 4) + r;     // input channel of this conv
+        int k, lane, n, t;
+        if (!k32) {
+            const int r = (int)(e & 3);
+            lane = (int)((e >> 2) & 63);
+            long long q = e >> 8;
+            n = (int)(q % NF);
+            q /= NF;
+            const int c = (int)(q % KC);
+            t = (int)(q / KC);
+            k = 16 * c + 4 * (lane >> 4) + r;             // input channel of this conv
+        } else {
+            const int r = (int)(e & 3), h = (int)((e >> 2) & 1);
+            lane = (int)((e >> 3) & 63);
+            long long q = e >> 9;
+            n = (int)(q % NF);
+            q /= NF;
+            const int c = (int)(q % (KC / 2));
+            t = (int)(q / (KC / 2));
+            k = 32 * c + 16 * h + 4 * (lane >> 4) + r;
+        }
         const int j = 16 * n + (lane & 15);              // output channel of this conv
         float v = 0.0f;
         if (!transpose) {
@@ -525,6 +655,51 @@ __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t *g, long long 
     }
 }
 
+// The same sum with 4 channels per thread (8-byte loads) and four voxels in
+// flight per thread; needs cout, cg and g_off multiples of 4.
+__global__ __launch_bounds__(256) void k_bias_grad4(const uint16_t *g, long long nvox, int cg, int g_off, int cout,
+                                                    float *gb)
+{
+    __shared__ float red[256 * 4];
+    const int cq = cout / 4;                         // threads per voxel
+    const int vl = 256 / cq;                         // voxel lanes
+    const int q = threadIdx.x % cq, lv = threadIdx.x / cq;
+    const long long v0 = (long long)blockIdx.x * BIAS_CHUNK, v1 = min(nvox, v0 + BIAS_CHUNK);
+    float sum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (lv < vl) {
+        const uint16_t *gp = g + g_off + 4 * q;
+        long long v = v0 + lv;
+        for (; v + 3 * vl < v1; v += 4 * vl) {
+            uint2 r[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) r[u] = *(const uint2 *)(gp + (v + u * vl) * cg);
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                sum[0] += __uint_as_float(r[u].x << 16);
+                sum[1] += __uint_as_float(r[u].x & 0xffff0000u);
+                sum[2] += __uint_as_float(r[u].y << 16);
+                sum[3] += __uint_as_float(r[u].y & 0xffff0000u);
+            }
+        }
+        for (; v < v1; v += vl) {
+            const uint2 r = *(const uint2 *)(gp + v * cg);
+            sum[0] += __uint_as_float(r.x << 16);
+            sum[1] += __uint_as_float(r.x & 0xffff0000u);
+            sum[2] += __uint_as_float(r.y << 16);
+            sum[3] += __uint_as_float(r.y & 0xffff0000u);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) red[k * 256 + threadIdx.x] = lv < vl ? sum[k] : 0.0f;
+    __syncthreads();
+    if (threadIdx.x < cout) {
+        const int co = threadIdx.x, qq = co / 4, k = co % 4;
+        float t = 0.0f;
+        for (int l = 0; l < vl; l++) t += red[k * 256 + l * cq + qq];
+        atomicAdd(gb + co, t);
+    }
+}
+
 // ---------------------------------------------------------------- elementwise and resampling
 // g <- g * (y > 0) over a channel slice (ReLU backward; y is the layer output)
 __global__ void k_relu_bwd(uint16_t *g, int cg, int g_off, const uint16_t *y, int cy, int y_off, long long nvox, int c)
@@ -561,7 +736,8 @@ __global__ void k_up_bwd(const uint16_t *fine, int cf, int f_off, uint16_t *coar
     }
 }
 
-// dX of the 2^3 stride-2 convolution: dX[u] = dY[u / 2] W[u % 2]^T (FP32 math)
+// dX of the 2^3 stride-2 convolution: dX[u] = dY[u / 2] W[u % 2]^T (weights
+// rounded to BF16 like those of every other adjoint, FP32 accumulation)
 __global__ void k_down_dgrad(const uint16_t *g, int cg, int g_off, const float *w, int cin, int cout, uint16_t *gx,
                              int cx, int x_off, int n, int d, int h, int wd, int accumulate)
 {
@@ -580,9 +756,77 @@ __global__ void k_down_dgrad(const uint16_t *g, int cg, int g_off, const float *
         long long cv = (((long long)nn * (d / 2) + z / 2) * (h / 2) + y / 2) * (wd / 2) + x / 2;
         const float *wt = w + ((long long)t * cin + ci) * cout;
         float s = 0.0f;
-        for (int co = 0; co < cout; co++) s += bf2f(g[cv * cg + g_off + co]) * wt[co];
+        for (int co = 0; co < cout; co++) s += bf2f(g[cv * cg + g_off + co]) * bf2f(f2bf(wt[co]));
         if (accumulate) s += bf2f(gx[v * cx + x_off + ci]);
         gx[v * cx + x_off + ci] = f2bf(s);
+    }
+}
+
+// The same adjoint on MFMA: for each of the 8 taps t it is a GEMM
+//   D[coarse voxel V][ci] = sum_co dY[V][co] W[t][ci][co]
+// whose result lands on the fine voxel 2 V + t.  A wave owns 64 coarse voxels
+// (4 row fragments) and all cin = 16 NF input channels; the FP32 weights are
+// rounded to BF16 as they are read into the B fragments.
+template <int NF>
+__global__ __launch_bounds__(256) void k_down_dgrad_mfma(const uint16_t *g, int cg, int g_off, const float *w, int cin,
+                                                         int cout, uint16_t *gx, int cx, int x_off, int n, int d, int h,
+                                                         int wd, int accumulate)
+{
+    const int lane = threadIdx.x & 63, i = lane & 15, gq = lane >> 4;
+    const int D2 = d / 2, H2 = h / 2, W2 = wd / 2;
+    const int nvc = n * D2 * H2 * W2;
+    const int V0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
+    if (V0 >= nvc) return;
+    // fine index of tap 0 for the coarse voxels of this lane's D rows (f, r)
+    int fb[4][4];
+#pragma unroll
+    for (int f = 0; f < 4; f++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int V = V0 + 16 * f + 4 * gq + r;
+            if (V >= nvc) { fb[f][r] = -1; continue; }
+            const int x = V % W2, y = (V / W2) % H2, z = (V / (W2 * H2)) % D2, nn = V / (W2 * H2 * D2);
+            fb[f][r] = ((nn * d + 2 * z) * h + 2 * y) * wd + 2 * x;
+        }
+    const int kc = cout / 16;
+    for (int t = 0; t < 8; t++) {
+        const int ta = t >> 2, tb = (t >> 1) & 1, tc = t & 1;
+        f4 acc[4][NF];
+#pragma unroll
+        for (int f = 0; f < 4; f++)
+#pragma unroll
+            for (int nf = 0; nf < NF; nf++) acc[f][nf] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int c = 0; c < kc; c++) {
+            s4 A[4];
+#pragma unroll
+            for (int f = 0; f < 4; f++) {
+                const int V = V0 + 16 * f + i;
+                uint2 raw = make_uint2(0u, 0u);
+                if (V < nvc) raw = *(const uint2 *)(g + (long long)V * cg + g_off + 16 * c + 4 * gq);
+                A[f] = s4{(short)(raw.x & 0xffff), (short)(raw.x >> 16), (short)(raw.y & 0xffff), (short)(raw.y >> 16)};
+            }
+#pragma unroll
+            for (int nf = 0; nf < NF; nf++) {
+                const float4 wv = *(const float4 *)(w + ((long long)t * cin + 16 * nf + i) * cout + 16 * c + 4 * gq);
+                const s4 Bv = s4{(short)f2bf(wv.x), (short)f2bf(wv.y), (short)f2bf(wv.z), (short)f2bf(wv.w)};
+#pragma unroll
+                for (int f = 0; f < 4; f++) acc[f][nf] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[f], Bv, acc[f][nf], 0, 0, 0);
+            }
+        }
+        const int toff = (ta * h + tb) * wd + tc;
+#pragma unroll
+        for (int f = 0; f < 4; f++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                if (fb[f][r] < 0) continue;
+                uint16_t *gp = gx + (long long)(fb[f][r] + toff) * cx + x_off + i;
+#pragma unroll
+                for (int nf = 0; nf < NF; nf++) {
+                    float val = acc[f][nf][r];
+                    if (accumulate) val += bf2f(gp[16 * nf]);
+                    gp[16 * nf] = f2bf(val);
+                }
+            }
     }
 }
 
@@ -762,6 +1006,16 @@ static hipError_t conv_lds(const ConvArgs &a, hipStream_t st)
     const long long tiles = (long long)a.n * ((a.od + TLZ - 1) / TLZ) * ((a.oh + TLY - 1) / TLY) * ((a.ow + TLX - 1) / TLX);
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
     const unsigned g = (unsigned)tiles;
+    if (a.cin % 32 == 0) {
+        switch ((a.cout + 15) / 16) {
+        case 1: k_conv_lds32<1, KIND><<<g, 256, 0, st>>>(a); break;
+        case 2: k_conv_lds32<2, KIND><<<g, 256, 0, st>>>(a); break;
+        case 4: k_conv_lds32<4, KIND><<<g, 256, 0, st>>>(a); break;
+        case 8: k_conv_lds32<8, KIND><<<g, 256, 0, st>>>(a); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch ((a.cout + 15) / 16) {
     case 1: k_conv_lds<1, KIND><<<g, 256, 0, st>>>(a); break;
     case 2: k_conv_lds<2, KIND><<<g, 256, 0, st>>>(a); break;
@@ -792,7 +1046,9 @@ hipError_t pack(const float *w, int ntap, int cin, int cout, int cin_p, int cout
                 hipStream_t st)
 {
     const long long total = (long long)ntap * (cin_p / 16) * (cout_p / 16) * 256;
-    k_pack<<<grid_for(total), 256, 0, st>>>(w, ntap, cin, cout, cin_p, cout_p, transpose, out);
+    // 3^3 kernels with a multiple of 32 input channels run on 16x16x32 fragments
+    const int k32 = ntap == 27 && cin_p % 32 == 0;
+    k_pack<<<grid_for(total), 256, 0, st>>>(w, ntap, cin, cout, cin_p, cout_p, transpose, k32, out);
     return hipGetLastError();
 }
 
@@ -847,7 +1103,10 @@ hipError_t bias_grad(const uint16_t *g, long long nvox, int cg, int g_off, int c
     if (cout > 128) return hipErrorInvalidValue;
     if (!accumulate) k_fill_f<<<(cout + 63) / 64, 64, 0, st>>>(gb, cout, 0.0f);
     const long long nb = (nvox + BIAS_CHUNK - 1) / BIAS_CHUNK;
-    k_bias_grad<<<(unsigned)nb, 256, 0, st>>>(g, nvox, cg, g_off, cout, gb);
+    if (cout % 4 == 0 && cg % 4 == 0 && g_off % 4 == 0 && ((uintptr_t)g & 7) == 0)
+        k_bias_grad4<<<(unsigned)nb, 256, 0, st>>>(g, nvox, cg, g_off, cout, gb);
+    else
+        k_bias_grad<<<(unsigned)nb, 256, 0, st>>>(g, nvox, cg, g_off, cout, gb);
     return hipGetLastError();
 }
 
@@ -868,8 +1127,23 @@ hipError_t up_bwd(const uint16_t *fine, int cf, int f_off, uint16_t *coarse, int
 hipError_t down_dgrad(const uint16_t *g, int cg, int g_off, const float *w, int cin, int cout, uint16_t *gx, int cx,
                       int x_off, int n, int d, int h, int wd, int accumulate, hipStream_t st)
 {
-    k_down_dgrad<<<grid_for((long long)n * d * h * wd * cin), 256, 0, st>>>(g, cg, g_off, w, cin, cout, gx, cx, x_off, n,
-                                                                              d, h, wd, accumulate);
+    const long long nfine = (long long)n * d * h * wd;
+    if (cin % 16 == 0 && cout % 16 == 0 && cin <= 128 && cg % 4 == 0 && g_off % 4 == 0 && nfine < 0x7fffffffLL &&
+        ((uintptr_t)g & 7) == 0 && ((uintptr_t)w & 15) == 0) {
+        const long long nvc = nfine / 8;
+        const unsigned blocks = (unsigned)((nvc + 255) / 256);
+        switch (cin / 16) {
+        case 1: k_down_dgrad_mfma<1><<<blocks, 256, 0, st>>>(g, cg, g_off, w, cin, cout, gx, cx, x_off, n, d, h, wd, accumulate); break;
+        case 2: k_down_dgrad_mfma<2><<<blocks, 256, 0, st>>>(g, cg, g_off, w, cin, cout, gx, cx, x_off, n, d, h, wd, accumulate); break;
+        case 4: k_down_dgrad_mfma<4><<<blocks, 256, 0, st>>>(g, cg, g_off, w, cin, cout, gx, cx, x_off, n, d, h, wd, accumulate); break;
+        case 8: k_down_dgrad_mfma<8><<<blocks, 256, 0, st>>>(g, cg, g_off, w, cin, cout, gx, cx, x_off, n, d, h, wd, accumulate); break;
+        default:
+            k_down_dgrad<<<grid_for(nfine * cin), 256, 0, st>>>(g, cg, g_off, w, cin, cout, gx, cx, x_off, n, d, h, wd,
+                                                                accumulate);
+        }
+        return hipGetLastError();
+    }
+    k_down_dgrad<<<grid_for(nfine * cin), 256, 0, st>>>(g, cg, g_off, w, cin, cout, gx, cx, x_off, n, d, h, wd, accumulate);
     return hipGetLastError();
 }
 

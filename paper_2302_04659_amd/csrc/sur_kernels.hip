@@ -122,9 +122,10 @@ __device__ void sur_advance_item(const StepArgs &a, int it, const Item &item, fl
     }
     __syncthreads();
     const Material mat = material_of(S);
+    const SceneK K = scene_k(S);
     const long long ps = a.pstride;
-    const float Tb = (float)n_sub * S.dt;
-    const float Dd = 4.0f * S.inv_dx;
+    const float Tb = (float)n_sub * K.dt;
+    const float Dd = 4.0f * K.inv_dx;
     int bad_any = 0, cl_any = 0;
     float bnd = 0.0f;
     for (int li = t; li < item.count; li += WG) {
@@ -135,7 +136,7 @@ __device__ void sur_advance_item(const StepArgs &a, int it, const Item &item, fl
         int b[3], cl = 0, in = 1;
         float f[3];
         for (int d = 0; d < 3; d++) {
-            particle_base(S, x[d], b[d], f[d], cl);
+            particle_base(K, x[d], b[d], f[d], cl);
             const int tb = b[d] - org[d];
             in &= (tb >= 0) & (tb <= B + 1);
         }
@@ -158,7 +159,7 @@ __device__ void sur_advance_item(const StepArgs &a, int it, const Item &item, fl
                         }
                     } else {
                         float vs[3], dv[3];
-                        sur_node(grid0, pred, cp, base + ((long long)(b[0] + ox) * S.res + b[1] + oy) * S.res + b[2] + oz,
+                        sur_node(grid0, pred, cp, base + ((long long)(b[0] + ox) * K.res + b[1] + oy) * K.res + b[2] + oz,
                                  vs, dv);
                         for (int d = 0; d < 3; d++) {
                             um[d] = fmaf(0.5f, dv[d], vs[d]);
@@ -206,11 +207,11 @@ __device__ void sur_advance_item(const StepArgs &a, int it, const Item &item, fl
         }
         float An[9];
         for (int e = 0; e < 9; e++) {
-            An[e] = fmaf(S.mass, Ce[e], -S.kstress * tau[e]);
+            An[e] = fmaf(K.mass, Ce[e], -K.kstress * tau[e]);
             pstore(a.P, ps, A00 + e, jo, An[e]);
             pstore(a.P, ps, G00 + e, jo, Gn[e]);
         }
-        bnd = fmaxf(bnd, scatter_bound(S.mass, S.dx, ve, An));
+        bnd = fmaxf(bnd, scatter_bound(K.mass, K.dx, ve, An));
     }
     bnd = wave_max(bnd);
     if ((t & 63) == 0 && bnd > 0.0f) atomicMax((int *)(a.L.ibound + it), __float_as_int(bnd));

@@ -280,7 +280,7 @@ def test_down_input_gradient(nn, accumulate):
     W = rng.normal(0, 0.1, size=(2, 2, 2, cin, cout)).astype(np.float32).astype(np.float64)
     G = ou.bf16_round(rng.normal(size=(n, 3, 2, 5, cout)))
     prev = ou.bf16_round(rng.normal(size=(n,) + sp + (cin,))) if accumulate else np.zeros((n,) + sp + (cin,))
-    ref, _, _ = ou.down_backward(np.zeros((n,) + sp + (cin,)), W, G)
+    ref, _, _ = ou.down_backward(np.zeros((n,) + sp + (cin,)), ou.bf16_round(W), G)   # weights enter as BF16
     bound, _, _ = ou.down_backward(np.zeros((n,) + sp + (cin,)), np.abs(W), np.abs(G))
     ref = ref + prev
     cx, x_off = cin + 16, 16
