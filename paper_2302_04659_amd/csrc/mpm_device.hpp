@@ -19,6 +19,15 @@ __device__ __forceinline__ int xcd_remap(int b, int G)
     return (b & 7) * (G >> 3) + (b >> 3);
 }
 
+// Workgroups that share n units of work: the whole launch when the work
+// suffices, else the smallest multiple of 8 covering it, so that every XCD
+// (the dispatcher deals workgroups to the 8 XCDs in turn) still gets a share.
+// The launch size must be a multiple of 8.
+__device__ __forceinline__ int active_wgs(int n)
+{
+    return min((int)gridDim.x, (n + 7) & ~7);
+}
+
 __device__ __forceinline__ int cvt_rpi(float x)
 {
     int r;

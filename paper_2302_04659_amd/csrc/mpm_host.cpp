@@ -372,7 +372,13 @@ mpm_status do_sort(mpm_ctx ctx)
     return MPM_OK;
 }
 
-int substep_wgs(mpm_ctx ctx) { return ctx->cus * 8; }
+// Workgroups per launch.  The particle kernels stride statically over work
+// items of uneven size; launching many more workgroups than fit at once lets
+// the hardware dispatcher hand the remaining items to whichever CU frees up
+// first (measured on cfg3: P2G and G2P best at 32 per CU, the grid update,
+// whose unit is one wave per block, at 16).
+int substep_wgs(mpm_ctx ctx) { return ctx->cus * 32; }
+int grid_wgs(mpm_ctx ctx) { return ctx->cus * 16; }
 
 // Queue n substeps (sort when due, P2G, grid, G2P) and the collider advance.
 mpm_status queue_plain(mpm_ctx ctx, int n)
@@ -396,7 +402,7 @@ mpm_status queue_plain(mpm_ctx ctx, int n)
         }
         {
             KTimer kt(ctx, MPM_K_GRID);
-            HIPCHK(launch_grid(a, substep_wgs(ctx), ctx->stream));
+            HIPCHK(launch_grid(a, grid_wgs(ctx), ctx->stream));
         }
         {
             KTimer kt(ctx, MPM_K_G2P);
@@ -1024,7 +1030,7 @@ mpm_status mpm_sur_features(mpm_ctx ctx, float *feat, int cf, float *grid0)
     a.cf = cf;
     a.keep_bound = 1;   // the state does not change: its scatter bounds stay valid
     HIPCHK(launch_p2g(a, ctx->CH, substep_wgs(ctx), ctx->stream));
-    HIPCHK(launch_grid(a, substep_wgs(ctx), ctx->stream));
+    HIPCHK(launch_grid(a, grid_wgs(ctx), ctx->stream));
     HIPCHK(launch_fill_i(ctx->L.n_ovf, 1, 0, ctx->stream));   // the overflow list has been consumed
     return MPM_OK;
 }
@@ -1061,7 +1067,7 @@ mpm_status mpm_sur_block(mpm_ctx ctx, const float *pred, int cp, const float *gr
     r.dense = ctx->d_sur_gend;
     r.keep_bound = 1;   // bounds now cover both the start and the advanced state
     HIPCHK(launch_p2g(r, ctx->CH, substep_wgs(ctx), ctx->stream));
-    HIPCHK(launch_grid(r, substep_wgs(ctx), ctx->stream));
+    HIPCHK(launch_grid(r, grid_wgs(ctx), ctx->stream));
     HIPCHK(launch_fill_i(ctx->L.n_ovf, 1, 0, ctx->stream));
     HIPCHK(launch_clear_f(ctx->d_sur_acc, 4 * ctx->n_scenes, ctx->stream));
     HIPCHK(launch_sur_residual(a, R, grid0, pred, cp, ctx->d_sur_gend, ctx->d_sur_acc, ctx->stream));

@@ -519,7 +519,9 @@ __global__ __launch_bounds__(WG) void k_p2g(StepArgs a)
     constexpr int T = B + 4, T3 = T * T * T;
     __shared__ int tile[4 * T3];
     const int n_items = *a.L.n_items;
-    for (int it = xcd_remap(blockIdx.x, gridDim.x); it < n_items; it += gridDim.x) {
+    const int G = active_wgs(n_items);
+    if ((int)blockIdx.x >= G) return;
+    for (int it = xcd_remap(blockIdx.x, G); it < n_items; it += G) {
         Item item = a.L.items[it];
         if (!a.active[item.scene]) continue;
         p2g_item<B>(a, it, item, tile);
@@ -606,11 +608,13 @@ template <int B>
 __global__ __launch_bounds__(WG) void k_grid(StepArgs a)
 {
     const int lane = threadIdx.x & 63;
-    const int nw = gridDim.x * (WG / 64);
-    const int w0 = xcd_remap(blockIdx.x, gridDim.x) * (WG / 64) + (threadIdx.x >> 6);
     __shared__ ColliderNow cls[WG / 64][MAX_COLLIDERS_PER_SCENE];
     const int ng = *a.L.n_gitems;
     const int no = min(*a.L.n_ovf, a.L.ovf_cap);
+    const int G = active_wgs((ng + no + WG / 64 - 1) / (WG / 64));
+    if ((int)blockIdx.x >= G) return;
+    const int nw = G * (WG / 64);
+    const int w0 = xcd_remap(blockIdx.x, G) * (WG / 64) + (threadIdx.x >> 6);
     for (int w = w0; w < ng + no; w += nw) {
         int2 e = w < ng ? a.L.gitems[w] : a.L.ovf[w - ng];
         grid_block<B>(a, e.x, e.y, lane, cls[threadIdx.x >> 6]);
@@ -774,7 +778,9 @@ __global__ __launch_bounds__(WG, 4) void k_g2p(StepArgs a)
     __shared__ float vt[3 * T3];
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(a.L.n_ovf, 0);   // grid update has consumed the list
     const int n_items = *a.L.n_items;
-    for (int it = xcd_remap(blockIdx.x, gridDim.x); it < n_items; it += gridDim.x) {
+    const int G = active_wgs(n_items);
+    if ((int)blockIdx.x >= G) return;
+    for (int it = xcd_remap(blockIdx.x, G); it < n_items; it += G) {
         Item item = a.L.items[it];
         if (!a.active[item.scene]) continue;
         g2p_item<B>(a, it, item, vt);

@@ -226,7 +226,9 @@ __global__ __launch_bounds__(WG) void k_sur_advance(StepArgs a, const float *gri
     constexpr int T = B + 4, T3 = T * T * T;
     __shared__ float vt[6 * T3];
     const int n_items = *a.L.n_items;
-    for (int it = xcd_remap(blockIdx.x, gridDim.x); it < n_items; it += gridDim.x) {
+    const int G = active_wgs(n_items);
+    if ((int)blockIdx.x >= G) return;
+    for (int it = xcd_remap(blockIdx.x, G); it < n_items; it += G) {
         const Item item = a.L.items[it];
         sur_advance_item<B>(a, it, item, vt, grid0, pred, cp, n_sub);
     }
