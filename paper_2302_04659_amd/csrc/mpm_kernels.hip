@@ -207,9 +207,7 @@ constexpr long long BIN_SCRAMBLE = 104729;   // prime
 
 __global__ __launch_bounds__(WG) void k_scatter(SortArgs a)
 {
-    // each XCD takes a contiguous share of the particles, so the bins one
-    // XCD writes are not also pulled into the L2 of the others
-    const int j = xcd_remap(blockIdx.x, gridDim.x) * WG + threadIdx.x;
+    const int j = blockIdx.x * WG + threadIdx.x;
     const bool valid = j < a.N;
     const unsigned key = valid ? a.keys[j] : 0xFFFFFFFFu;
     const KeyRun r = key_run(key);
@@ -332,8 +330,8 @@ hipError_t launch_sort(const SortArgs &a, hipStream_t st)
     k_scan_top<<<1, WG, 0, st>>>(a, ntiles);
     k_scan_emit<<<ntiles, WG, 0, st>>>(a);
     if (a.N > 0) {
-        const int gN8 = (gN + 7) & ~7;    // xcd_remap needs a multiple of 8 workgroups
-        k_scatter<<<gN8, WG, 0, st>>>(a);
+        const int gN8 = (gN + 7) & ~7;    // xcd_remap (gather) needs a multiple of 8 workgroups
+        k_scatter<<<gN, WG, 0, st>>>(a);
         if (a.B == 4) k_bank_order<4><<<2048, WG, 0, st>>>(a);
         else k_bank_order<8><<<2048, WG, 0, st>>>(a);
         k_gather<<<gN8, WG, 0, st>>>(a);
