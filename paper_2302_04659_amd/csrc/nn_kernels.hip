@@ -258,12 +258,21 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
 // and 16 + 4 g .. 16 + 4 g + 3), pair g stored at slot g ^ ((v >> 2) & 3) so
 // that the 16-byte reads of 8 neighbouring x voxels hit distinct banks.  For
 // each (z tap, x tap) a wave reads the six halo rows its four output rows see
-// through the three y taps once.
+// through the three y taps once.  Staging reads 16 bytes (8 channels) per
+// load; a BF16 output slice goes out through LDS as 16-byte rows (needs the
+// channel stride and offset of x and y to be multiples of 8).
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 
-template <int NF, int KIND>
+template <int NF, int KIND, bool X16>
 __global__ __launch_bounds__(256, 2) void k_conv_lds32(ConvArgs a)
 {
+    constexpr int HZ = KIND == KIND_C3 ? HLZ : TLZ / 2 + 2;
+    constexpr int HY = KIND == KIND_C3 ? HLY : TLY / 2 + 2;
+    constexpr int HX = KIND == KIND_C3 ? HLX : TLX / 2 + 2;
+    constexpr int NH = HZ * HY * HX;
+    constexpr int CO = 16 * NF;
+    constexpr int OROW = CO + 8;                               // output row in LDS (bf16), padded against conflicts
+    static_assert(256 * OROW * 2 <= HLZ * HLY * HLX * 64 || NF == 8, "output tile must fit the halo buffer");
     __shared__ uint4 halo[HLZ * HLY * HLX * 4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int tiles_x = (a.ow + TLX - 1) / TLX, tiles_y = (a.oh + TLY - 1) / TLY, tiles_z = (a.od + TLZ - 1) / TLZ;
@@ -275,15 +284,12 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds32(ConvArgs a)
     const int bz = b % tiles_z;
     const int bn = b / tiles_z;
     const int z0 = bz * TLZ, y0 = by * TLY, x0 = bx * TLX;
-    int hz0, hy0, hx0, hz, hy, hx;
+    int hz0, hy0, hx0;
     if (KIND == KIND_C3) {
         hz0 = z0 - 1; hy0 = y0 - 1; hx0 = x0 - 1;
-        hz = HLZ; hy = HLY; hx = HLX;
     } else {
         hz0 = (z0 >> 1) - 1; hy0 = (y0 >> 1) - 1; hx0 = (x0 >> 1) - 1;
-        hz = TLZ / 2 + 2; hy = TLY / 2 + 2; hx = TLX / 2 + 2;
     }
-    const int nh = hz * hy * hx;
     f4 acc[4][NF];
 #pragma unroll
     for (int f = 0; f < 4; f++)
@@ -292,17 +298,28 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds32(ConvArgs a)
     const int kc = a.cin / 32;
     const int g = lane >> 4, i = lane & 15;
     uint2 *h2 = (uint2 *)halo;
+    // staging (X16): thread t loads channels 8 (t & 3) .. + 7 of voxels (t >> 2) + 64 k;
+    // otherwise 4 channels per load, thread t: group t & 7 of voxels (t >> 3) + 32 k
+    const int q = X16 ? (threadIdx.x & 3) : (threadIdx.x & 7);
+    const int gs = X16 ? 2 * (q & 1) : (q & 3), hs = X16 ? (q >> 1) : (q >> 2);
+    const uint16_t *xb = a.x + (long long)bn * a.id * a.ih * a.iw * a.cx + a.x_off + (X16 ? 8 * q : 16 * hs + 4 * gs);
     for (int c = 0; c < kc; c++) {
-        // stage channels [32 c, 32 c + 32): thread element e -> voxel e / 8, 4-channel group e % 8
-        for (int e = threadIdx.x; e < nh * 8; e += 256) {
-            const int v = e >> 3, gg = e & 3, hh = (e >> 2) & 1;
-            const int lx = v % hx, ly = (v / hx) % hy, lz = v / (hx * hy);
+        for (int v = threadIdx.x >> (X16 ? 2 : 3); v < NH; v += (X16 ? 64 : 32)) {
+            const int lx = v % HX, ly = (v / HX) % HY, lz = v / (HX * HY);
             const int gz = hz0 + lz, gy = hy0 + ly, gx = hx0 + lx;
-            uint2 val = make_uint2(0u, 0u);
-            if (gz >= 0 && gy >= 0 && gx >= 0 && gz < a.id && gy < a.ih && gx < a.iw)
-                val = *(const uint2 *)(a.x + ((((long long)bn * a.id + gz) * a.ih + gy) * a.iw + gx) * a.cx + a.x_off +
-                                       32 * c + 16 * hh + 4 * gg);
-            h2[v * 8 + 2 * (gg ^ ((v >> 2) & 3)) + hh] = val;
+            const bool in = gz >= 0 && gy >= 0 && gx >= 0 && gz < a.id && gy < a.ih && gx < a.iw;
+            const long long off = (((long long)gz * a.ih + gy) * a.iw + gx) * a.cx + 32 * c;
+            const int sw = (v >> 2) & 3;
+            if (X16) {
+                uint4 val = make_uint4(0u, 0u, 0u, 0u);
+                if (in) val = *(const uint4 *)(xb + off);
+                h2[v * 8 + 2 * (gs ^ sw) + hs] = make_uint2(val.x, val.y);
+                h2[v * 8 + 2 * ((gs + 1) ^ sw) + hs] = make_uint2(val.z, val.w);
+            } else {
+                uint2 val = make_uint2(0u, 0u);
+                if (in) val = *(const uint2 *)(xb + off);
+                h2[v * 8 + 2 * (gs ^ sw) + hs] = val;
+            }
         }
         __syncthreads();
         const uint16_t *wc = a.w + (size_t)c * NF * 512 + 8 * lane;
@@ -322,7 +339,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds32(ConvArgs a)
                     int ly;
                     if (KIND == KIND_C3) ly = r;
                     else ly = ((y0 + r - 1) >> 1) - hy0;
-                    const int v = (lz * hy + ly) * hx + lx;
+                    const int v = (lz * HY + ly) * HX + lx;
                     Ar[r] = __builtin_bit_cast(b8, halo[v * 4 + (g ^ ((v >> 2) & 3))]);
                 }
 #pragma unroll
@@ -342,6 +359,43 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds32(ConvArgs a)
         __syncthreads();
     }
     const int oz = z0 + wv;
+    const bool fast = a.y && !a.y32 && a.cout == CO && (a.cy % 8) == 0 && (a.y_off % 8) == 0 &&
+                      ((uintptr_t)a.y & 15) == 0;
+    if (fast) {
+        // D[i][j] -> LDS row (wave, f, x = 4 (lane / 16) + r), channel 16 n + lane % 16; then 16-byte rows out
+        uint16_t *ot = (uint16_t *)halo;
+        constexpr int NP = NF == 8 ? 2 : 1;                   // channel passes (128 channels: two of 64)
+        constexpr int CP = CO / NP;
+        constexpr int PROW = CP + 8;
+#pragma unroll
+        for (int pass = 0; pass < NP; pass++) {
+#pragma unroll
+            for (int f = 0; f < 4; f++)
+#pragma unroll
+                for (int nn = 0; nn < NF / NP; nn++) {
+                    const int n = pass * (NF / NP) + nn;
+                    const float bias = a.bias ? a.bias[16 * n + i] : 0.0f;
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        float val = acc[f][n][r] + bias;
+                        if (a.relu) val = fmaxf(val, 0.0f);
+                        ot[((wv * 4 + f) * 16 + 4 * g + r) * PROW + 16 * nn + i] = f2bf(val);
+                    }
+                }
+            __syncthreads();
+            for (int e = threadIdx.x; e < 256 * (CP / 8); e += 256) {
+                const int vl = e / (CP / 8), part = e % (CP / 8);
+                const int tz = vl >> 6, ty = (vl >> 4) & 3, tx = vl & 15;
+                const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
+                if (gz < a.od && gy < a.oh && gx < a.ow) {
+                    const long long gv = (((long long)bn * a.od + gz) * a.oh + gy) * a.ow + gx;
+                    *(uint4 *)(a.y + gv * a.cy + a.y_off + pass * CP + 8 * part) = *(const uint4 *)(ot + vl * PROW + 8 * part);
+                }
+            }
+            if (pass + 1 < NP) __syncthreads();
+        }
+        return;
+    }
 #pragma unroll
     for (int f = 0; f < 4; f++) {
         const int oy = y0 + f;
@@ -1006,12 +1060,13 @@ static hipError_t conv_lds(const ConvArgs &a, hipStream_t st)
     const long long tiles = (long long)a.n * ((a.od + TLZ - 1) / TLZ) * ((a.oh + TLY - 1) / TLY) * ((a.ow + TLX - 1) / TLX);
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
     const unsigned g = (unsigned)tiles;
-    if (a.cin % 32 == 0) {
+    if (a.cin % 32 == 0) {   // the weights were packed as 16x16x32 fragments (same condition in pack)
+        const bool x16 = a.cx % 8 == 0 && a.x_off % 8 == 0 && ((uintptr_t)a.x & 15) == 0;
         switch ((a.cout + 15) / 16) {
-        case 1: k_conv_lds32<1, KIND><<<g, 256, 0, st>>>(a); break;
-        case 2: k_conv_lds32<2, KIND><<<g, 256, 0, st>>>(a); break;
-        case 4: k_conv_lds32<4, KIND><<<g, 256, 0, st>>>(a); break;
-        case 8: k_conv_lds32<8, KIND><<<g, 256, 0, st>>>(a); break;
+        case 1: if (x16) k_conv_lds32<1, KIND, true><<<g, 256, 0, st>>>(a); else k_conv_lds32<1, KIND, false><<<g, 256, 0, st>>>(a); break;
+        case 2: if (x16) k_conv_lds32<2, KIND, true><<<g, 256, 0, st>>>(a); else k_conv_lds32<2, KIND, false><<<g, 256, 0, st>>>(a); break;
+        case 4: if (x16) k_conv_lds32<4, KIND, true><<<g, 256, 0, st>>>(a); else k_conv_lds32<4, KIND, false><<<g, 256, 0, st>>>(a); break;
+        case 8: if (x16) k_conv_lds32<8, KIND, true><<<g, 256, 0, st>>>(a); else k_conv_lds32<8, KIND, false><<<g, 256, 0, st>>>(a); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();

@@ -81,6 +81,8 @@ CONV_CASES = [
     ("c3", 2, (5, 6, 7), 48, 16, 32, 32),
     ("c3", 1, (4, 3, 9), 16, 0, 16, 64),
     ("c3", 1, (6, 5, 4), 128, 0, 128, 128),
+    ("c3", 1, (5, 4, 18), 40, 4, 32, 32),        # 8-byte staging (slice offset not a multiple of 8)
+    ("c3", 1, (4, 5, 21), 64, 0, 64, 64),        # two x tiles, ragged
     ("up", 1, (3, 5, 3), 64, 0, 64, 32),
     ("up", 2, (2, 3, 2), 128, 0, 128, 64),
     ("down", 2, (6, 4, 10), 64, 32, 32, 64),
@@ -90,12 +92,14 @@ CONV_CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", CONV_CASES, ids=[f"{c[0]}-{c[5]}x{c[6]}" for c in CONV_CASES])
+@pytest.mark.parametrize("case", CONV_CASES, ids=[f"{c[0]}-{c[5]}x{c[6]}-{c[4]}" for c in CONV_CASES])
 @pytest.mark.parametrize("relu", [0, 1])
-def test_conv_forward(nn, case, relu):
+@pytest.mark.parametrize("out32", [1, 0])
+def test_conv_forward(nn, case, relu, out32):
+    """out32 = 0: BF16 output only (the LDS-transposed store path of the 3^3 kernels)."""
     import torch
     kind, n, sp, cx, x_off, cin, cout = case
-    announce("nn conv", kind, n, sp, cin, cout, "relu", relu)
+    announce("nn conv", kind, n, sp, cin, cout, "relu", relu, "out32", out32)
     rng = np.random.default_rng(2 * CONV_CASES.index(case) + relu)
     k = KS[kind]
     X = rng.normal(size=(n,) + sp + (cx,))
@@ -119,12 +123,14 @@ def test_conv_forward(nn, case, relu):
     y = torch.full((n,) + osp + (cy,), sentinel, dtype=torch.int16, device="cuda")
     y32 = torch.zeros((n,) + osp + (cout,), dtype=torch.float32, device="cuda")
     r = L.mpm_nn_conv(nn.KIND[kind], x_d.data_ptr(), n, sp[0], sp[1], sp[2], cx, x_off, cin, fw.data_ptr(),
-                      b_d.data_ptr(), relu, y.data_ptr(), cy, y_off, cout, y32.data_ptr(), cout, s)
+                      b_d.data_ptr(), relu, y.data_ptr(), cy, y_off, cout, y32.data_ptr() if out32 else None,
+                      cout if out32 else 0, s)
     assert r == 0
     torch.cuda.synchronize()
-    got32 = y32.cpu().numpy().astype(np.float64)
-    err = np.abs(got32 - ref)
-    assert np.all(err <= 1e-5 * bound + 1e-30), f"max err/bound {np.max(err / (bound + 1e-30)):.3e}"
+    if out32:
+        got32 = y32.cpu().numpy().astype(np.float64)
+        err = np.abs(got32 - ref)
+        assert np.all(err <= 1e-5 * bound + 1e-30), f"max err/bound {np.max(err / (bound + 1e-30)):.3e}"
     yb = _from_bf16(y)
     got = yb[..., y_off:y_off + cout]
     assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * bound + 1e-30)
