@@ -304,7 +304,7 @@ def bench_surrogate(args):
 
     sim, gs, t_sur, fb_frac, res, st = run_surrogate(1e-3)
     # the network alone on the last crop, timed with events on its stream
-    _, fc, pc = gs._cbuf
+    _, fc, _, pc = gs._cbuf
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(gs.ts):
         ev0.record()

@@ -203,20 +203,34 @@ mpm_status mpm_set_scene_mask(mpm_ctx ctx, const int *active);
  * Units: velocities in 0.2 m/s, masses in rho dx^3 of the scene, predicted
  * mass changes in rho dx^3 / 32. */
 
+/* Box: the surrogate arrays of the next calls cover, per scene s, either the
+ * whole grid (origin = NULL; the box is R^3) or the box of D x H x W nodes
+ * starting at node (origin[3 s], origin[3 s + 1], origin[3 s + 2]) (origin
+ * a device array of 3 n_scenes ints; 1 <= D, H, W <= R; the caller keeps
+ * the box inside the grid).  Array [n_scenes][box][c] below means
+ * [n_scenes][D][H][W][c], node (i, j, k) at box index (i - o0, j - o1, k - o2).
+ *
+ * Per scene, the nodes the current particles' P2G stencils reach: box
+ * [6 n_scenes] (device) = (lo i, lo j, lo k, hi i, hi j, hi k), inclusive;
+ * all zero for a scene without particles.  A box around it with a margin
+ * holds every node the features and the re-splat of a control step touch. */
+mpm_status mpm_sur_bbox(mpm_ctx ctx, int *box);
+
 /* Network input and start grid of the current state at the current
  * collider poses: a P2G and grid update (the state is not changed).
- * feat  [n_scenes][R][R][R][cf] (cf >= 8): 0 m, 1-3 p (P2G output), 4
+ * feat  [n_scenes][box][cf] (cf >= 8): 0 m, 1-3 p (P2G output), 4
  *       distance to the nearest collider in cells clipped to [-3, 3], 5-7
  *       that collider's velocity where it is closer than 3 cells (else 0),
  *       8.. zero;
- * grid0 [n_scenes][R][R][R][4]: (m, v = p / m) of that P2G, before gravity,
+ * grid0 [n_scenes][box][4]: (m, v = p / m) of that P2G, before gravity,
  *       colliders and walls (v = 0 where m = 0).  Node (i, j, k) is at
- *       (i dx, j dx, k dx). */
-mpm_status mpm_sur_features(mpm_ctx ctx, float *feat, int cf, float *grid0);
+ *       (i dx, j dx, k dx).  Material outside the box is left out. */
+mpm_status mpm_sur_features(mpm_ctx ctx, float *feat, int cf, float *grid0, const int *origin, int D, int H, int W);
 
-/* One control step from a grid prediction.  pred [n_scenes][R][R][R][cp]
+/* One control step from a grid prediction.  pred [n_scenes][box][cp]
  * (cp >= 4, multiple of 4): 0-2 velocity change, 3 mass change over the
- * step, at the nodes of grid0 (from mpm_sur_features on this state).
+ * step, at the nodes of grid0 (from mpm_sur_features on this state, same
+ * box; the prediction is zero outside the box).
  * Particles advance with T = 25 dt: x += T v_mid, F <- (I + T C_mid) F
  * then the return map, v and C from v_end = v_start + dv (v_mid the mean of
  * start and end), and a P2G of the advanced particles (m_r, v_r = p_r / m_r)
@@ -224,7 +238,8 @@ mpm_status mpm_sur_features(mpm_ctx ctx, float *feat, int cf, float *grid0);
  * after:
  *   r = max(|m_r - m_pred|_1 / sum m, |m_r v_r - m_pred v_end|_1 /
  *           max(|m v_start|_1, sum m |g| T)),
- * per scene.  Scenes with r > threshold (or non-finite state) are put back
+ * per scene (re-splat mass outside the box counts in full in the first
+ * term).  Scenes with r > threshold (or non-finite state) are put back
  * to their state at the start of the step and run the 25 plain substeps
  * instead (flag MPM_SUR_NO_FALLBACK keeps every scene on the surrogate and
  * only reports r).  residual [n_scenes] (nullable) receives r; n_fallback
@@ -232,11 +247,12 @@ mpm_status mpm_sur_features(mpm_ctx ctx, float *feat, int cf, float *grid0);
  * waits for the decision and skips the plain substeps when no scene fell
  * back.  Colliders advance by 25 substeps either way. */
 enum { MPM_SUR_NO_FALLBACK = 1, MPM_SUR_SYNC = 2 };
-mpm_status mpm_sur_block(mpm_ctx ctx, const float *pred, int cp, const float *grid0, float threshold, int flags,
-                         float *residual, int *n_fallback);
+mpm_status mpm_sur_block(mpm_ctx ctx, const float *pred, int cp, const float *grid0, const int *origin, int D, int H,
+                         int W, float threshold, int flags, float *residual, int *n_fallback);
 
 /* Training targets between the start grids g0, g1 of two consecutive
- * control steps (both from mpm_sur_features): target [n][R^3][ct] (ct >= 4)
+ * control steps (both from mpm_sur_features on the whole grid): target
+ * [n][R^3][ct] (ct >= 4)
  * = ((v1 - v0) in 0.2 m/s, (m1 - m0) in rho dx^3 / 32), mask [n][R^3] = 1
  * where m0 > 0 or m1 > 0, else 0. */
 mpm_status mpm_sur_targets(mpm_ctx ctx, const float *g0, const float *g1, float *target, int ct, float *mask);

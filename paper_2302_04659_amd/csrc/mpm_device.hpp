@@ -55,6 +55,18 @@ __device__ __forceinline__ long long node_index(const SceneDev &S, int B, int i,
     return S.grid_off + (long long)lb * (B * B * B) + l;
 }
 
+// Index of grid node (i, j, k) of scene s in the surrogate's per-scene
+// arrays: the whole grid (offset cap_off[s]) or the scene's box; -1 outside
+// the box.
+__device__ __forceinline__ long long sur_index(const StepArgs &a, int s, int res, int i, int j, int k)
+{
+    if (!a.sur_org) return a.cap_off[s] + ((long long)i * res + j) * res + k;
+    const int *o = a.sur_org + 3 * s;
+    const int z = i - o[0], y = j - o[1], x = k - o[2];
+    if (z < 0 || y < 0 || x < 0 || z >= a.sur_box[0] || y >= a.sur_box[1] || x >= a.sur_box[2]) return -1;
+    return (((long long)s * a.sur_box[0] + z) * a.sur_box[1] + y) * a.sur_box[2] + x;
+}
+
 __device__ __forceinline__ int scene_of_bin(const int *off, int n_scenes, int b)
 {
     int lo = 0, hi = n_scenes;          // off[lo] <= b < off[hi]

@@ -91,7 +91,7 @@ struct mpm_ctx_s {
     // per-scene step mask (1 = step), dense per-scene grid offsets
     int *d_active = nullptr;
     // grid surrogate: re-splat grid and residual sums
-    float *d_sur_gend = nullptr, *d_sur_acc = nullptr;
+    float *d_sur_gend = nullptr, *d_sur_acc = nullptr, *d_sur_out = nullptr;
     int *d_sur_nfb = nullptr;
 
     // debug capture of the P2G grid
@@ -510,7 +510,7 @@ void release(mpm_ctx ctx)
                     ctx->d_tsum, ctx->d_dil, ctx->L.items, ctx->L.gitems, ctx->L.n_items, ctx->L.n_gitems,
                     ctx->L.scene_item_begin, ctx->L.scene_gitem_begin, ctx->L.bflag, ctx->L.ovf, ctx->L.n_ovf, ctx->L.ibound, ctx->L.touched,
                     ctx->d_flags, ctx->d_queue, ctx->d_scene_done, ctx->d_cap, ctx->d_cap_off, ctx->d_io,
-                    ctx->d_active, ctx->d_sur_gend, ctx->d_sur_acc, ctx->d_sur_nfb};
+                    ctx->d_active, ctx->d_sur_gend, ctx->d_sur_acc, ctx->d_sur_out, ctx->d_sur_nfb};
     for (void *p : bufs)
         if (p) hipFree(p);
     for (int i = 0; i < STAGE_RING; i++) {
@@ -1008,9 +1008,32 @@ int common_res(mpm_ctx ctx)
     return r;
 }
 
+// The surrogate arrays of a call: per-scene boxes (origin on the device) or the whole grid.
+mpm_status sur_box(mpm_ctx ctx, StepArgs &a, int R, const int *origin, int D, int H, int W)
+{
+    if (!origin) return MPM_OK;
+    ARGCHK(D > 0 && H > 0 && W > 0 && D <= R && H <= R && W <= R, "box size must be in 1 .. res");
+    a.sur_org = origin;
+    a.sur_box[0] = D;
+    a.sur_box[1] = H;
+    a.sur_box[2] = W;
+    return MPM_OK;
+}
+
 }  // namespace
 
-mpm_status mpm_sur_features(mpm_ctx ctx, float *feat, int cf, float *grid0)
+mpm_status mpm_sur_bbox(mpm_ctx ctx, int *box)
+{
+    ARGCHK(ctx, "null context");
+    ARGCHK(box, "box must not be NULL");
+    const int R = common_res(ctx);
+    ARGCHK(R > 0, "the surrogate needs one grid resolution for all scenes");
+    hipSetDevice(ctx->dev);
+    HIPCHK(launch_sur_bbox(step_args(ctx, 0), R, box, ctx->stream));
+    return MPM_OK;
+}
+
+mpm_status mpm_sur_features(mpm_ctx ctx, float *feat, int cf, float *grid0, const int *origin, int D, int H, int W)
 {
     ARGCHK(ctx, "null context");
     ARGCHK(feat && grid0, "feat and grid0 must not be NULL");
@@ -1023,8 +1046,10 @@ mpm_status mpm_sur_features(mpm_ctx ctx, float *feat, int cf, float *grid0)
         if (st != MPM_OK) return st;
     }
     StepArgs a = step_args(ctx, 0);
+    mpm_status st = sur_box(ctx, a, R, origin, D, H, W);
+    if (st != MPM_OK) return st;
     HIPCHK(launch_colliders_now(a, (int)ctx->h_cols.size(), ctx->d_col_scene, ctx->stream));
-    HIPCHK(launch_sur_dense(a, R, feat, cf, grid0, ctx->stream));
+    HIPCHK(launch_sur_init(a, R, feat, cf, grid0, ctx->stream));
     a.dense = grid0;
     a.feat = feat;
     a.cf = cf;
@@ -1035,8 +1060,8 @@ mpm_status mpm_sur_features(mpm_ctx ctx, float *feat, int cf, float *grid0)
     return MPM_OK;
 }
 
-mpm_status mpm_sur_block(mpm_ctx ctx, const float *pred, int cp, const float *grid0, float threshold, int flags,
-                         float *residual, int *n_fallback)
+mpm_status mpm_sur_block(mpm_ctx ctx, const float *pred, int cp, const float *grid0, const int *origin, int D, int H,
+                         int W, float threshold, int flags, float *residual, int *n_fallback)
 {
     ARGCHK(ctx, "null context");
     ARGCHK(pred && grid0, "pred and grid0 must not be NULL");
@@ -1045,10 +1070,15 @@ mpm_status mpm_sur_block(mpm_ctx ctx, const float *pred, int cp, const float *gr
     ARGCHK((flags & ~(MPM_SUR_NO_FALLBACK | MPM_SUR_SYNC)) == 0, "unknown flag");
     const int R = common_res(ctx);
     ARGCHK(R > 0, "the surrogate needs one grid resolution for all scenes");
-    ARGCHK(((long long)R * R * R) % 4096 == 0, "grid resolution too small for the surrogate (res^3 % 4096)");
     hipSetDevice(ctx->dev);
+    {
+        StepArgs chk = step_args(ctx, 0);
+        mpm_status st = sur_box(ctx, chk, R, origin, D, H, W);
+        if (st != MPM_OK) return st;
+    }
     if (!ctx->d_sur_gend) HIPCHK(dalloc(&ctx->d_sur_gend, (size_t)4 * ctx->cap_nodes));
     if (!ctx->d_sur_acc) HIPCHK(dalloc(&ctx->d_sur_acc, (size_t)4 * ctx->n_scenes));
+    if (!ctx->d_sur_out) HIPCHK(dalloc(&ctx->d_sur_out, (size_t)ctx->n_scenes));
     if (!ctx->d_sur_nfb) HIPCHK(dalloc(&ctx->d_sur_nfb, 1));
     const int nsub = GRAPH_BLOCK;
     const int fallback = !(flags & MPM_SUR_NO_FALLBACK);
@@ -1056,15 +1086,22 @@ mpm_status mpm_sur_block(mpm_ctx ctx, const float *pred, int cp, const float *gr
         mpm_status st = do_sort(ctx);
         if (st != MPM_OK) return st;
     }
-    // snapshot into the sort's other buffer (dead until the next sort)
-    HIPCHK(hipMemcpyAsync(ctx->d_P[1 - ctx->cur], ctx->d_P[ctx->cur], sizeof(float) * NCOMP * ctx->pstride,
-                          hipMemcpyDeviceToDevice, ctx->stream));
+    // snapshot into the sort's other buffer (dead until the next sort); only a fallback reads it
+    if (fallback)
+        HIPCHK(hipMemcpyAsync(ctx->d_P[1 - ctx->cur], ctx->d_P[ctx->cur], sizeof(float) * NCOMP * ctx->pstride,
+                              hipMemcpyDeviceToDevice, ctx->stream));
     StepArgs a = step_args(ctx, 0);
+    sur_box(ctx, a, R, origin, D, H, W);
     HIPCHK(launch_sur_advance(a, grid0, pred, cp, nsub, substep_wgs(ctx), ctx->stream));
-    // re-splat the advanced particles
+    // re-splat the advanced particles (on the same box; mass landing outside it is counted)
     StepArgs r = step_args(ctx, nsub);
-    HIPCHK(launch_clear_f(ctx->d_sur_gend, 4 * ctx->cap_nodes, ctx->stream));
+    sur_box(ctx, r, R, origin, D, H, W);
+    const long long box_nodes = origin ? (long long)ctx->n_scenes * D * H * W : ctx->cap_nodes;
+    HIPCHK(launch_clear_f(ctx->d_sur_gend, 4 * box_nodes, ctx->stream));
+    HIPCHK(launch_clear_f(ctx->d_sur_out, ctx->n_scenes, ctx->stream));
     r.dense = ctx->d_sur_gend;
+    r.out_mass = ctx->d_sur_out;
+    a.out_mass = ctx->d_sur_out;   // read by the residual
     r.keep_bound = 1;   // bounds now cover both the start and the advanced state
     HIPCHK(launch_p2g(r, ctx->CH, substep_wgs(ctx), ctx->stream));
     HIPCHK(launch_grid(r, grid_wgs(ctx), ctx->stream));

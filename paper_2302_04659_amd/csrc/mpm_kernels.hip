@@ -578,8 +578,9 @@ __device__ void grid_block(const StepArgs &a, int s, int lb, int lane, ColliderN
             if (ii[d] < bound && v[d] < 0.0f) v[d] = 0.0f;
             if (ii[d] >= K.res - bound && v[d] > 0.0f) v[d] = 0.0f;
         }
-        if (a.dense) {   // (m, p / m) of the P2G, before gravity, colliders and walls
-            const long long c = a.cap_off[s] + ((long long)ii[0] * K.res + ii[1]) * K.res + ii[2];
+        const long long c = a.dense ? sur_index(a, s, K.res, ii[0], ii[1], ii[2]) : -1;
+        if (a.dense && c < 0 && a.out_mass && m > 0.0f) atomicAdd(a.out_mass + s, m);   // outside the box
+        if (c >= 0) {   // (m, p / m) of the P2G, before gravity, colliders and walls
             const float im = m > 0.0f ? 1.0f / m : 0.0f;
             *(float4 *)(a.dense + 4 * c) = make_float4(m, px * im, py * im, pz * im);
             if (a.feat) {

@@ -25,10 +25,13 @@ struct StepArgs {
     int *scene_done;          // persistent mode: [n_scenes] P2G items done, [n_scenes] grid entries done
     int n_wg;                 // persistent mode: number of workgroups launched
     const int *active;        // per scene: 0 = leave this scene's particles as they are (P2G / G2P skip it)
-    float *dense;             // optional grid-update output, dense per scene [res^3][4] = (m, v), or null
-    float *feat;              // optional surrogate input channels 0-3 (m, p normalised) [res^3][cf], or null
+    float *dense;             // optional grid-update output per scene on the surrogate box [box][4] = (m, v), or null
+    float *feat;              // optional surrogate input channels 0-3 (m, p normalised) [box][cf], or null
     int cf;
     int keep_bound;           // 1: a P2G with no G2P after it (leave the per-item scatter bounds as they are)
+    const int *sur_org;       // surrogate box of scene s: origin sur_org[3 s ..] (device), size sur_box;
+    int sur_box[3];           //   null = the whole grid (res^3 per scene, offset cap_off[s])
+    float *out_mass;          // per scene: P2G mass the grid update found outside the box (added), or null
 };
 
 
@@ -74,7 +77,8 @@ hipError_t launch_fill_i(int *p, long long n, int v, hipStream_t st);
 
 // Grid surrogate support (all scenes share one resolution `res`).
 hipError_t launch_colliders_now(const StepArgs &a, int n_cols, const int *col_scene, hipStream_t st);
-hipError_t launch_sur_dense(const StepArgs &a, int res, float *feat, int cf, float *grid0, hipStream_t st);
+hipError_t launch_sur_init(const StepArgs &a, int res, float *feat, int cf, float *grid0, hipStream_t st);
+hipError_t launch_sur_bbox(const StepArgs &a, int res, int *box, hipStream_t st);
 hipError_t launch_sur_advance(const StepArgs &a, const float *grid0, const float *pred, int cp, int n_sub, int n_wg,
                               hipStream_t st);
 hipError_t launch_sur_residual(const StepArgs &a, int res, const float *grid0, const float *pred, int cp,

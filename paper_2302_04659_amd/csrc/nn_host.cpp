@@ -36,7 +36,10 @@ int mpm_nn_conv(int kind, const uint16_t *x, int n, int id, int ih, int iw, int 
                 float *y32, int cy32, void *stream)
 {
     if (!kind_ok(kind) || !x || !wpack || (!y && !y32) || n <= 0 || id <= 0 || ih <= 0 || iw <= 0) return -1;
-    if (!c16(cin) || cout <= 0 || cout > 128 || x_off < 0 || x_off + cin > cx || (x_off % 4) || (cx % 4)) return -1;
+    if (!(c16(cin) || (kind == 0 && cin == 8)) || cout <= 0 || cout > 128 || x_off < 0 || x_off + cin > cx ||
+        (x_off % 4) || (cx % 4))
+        return -1;
+    if (cin == 8 && ((x_off % 8) || (cx % 8))) return -1;
     if (y && (y_off < 0 || y_off + cout > cy)) return -1;
     if (y32 && cy32 < cout) return -1;
     if (kind == 2 && (id % 2 || ih % 2 || iw % 2)) return -1;

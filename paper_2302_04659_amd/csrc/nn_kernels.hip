@@ -251,6 +251,77 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
     }
 }
 
+// Epilogue of the LDS-tiled kernels: bias, ReLU and the outputs of a 4 x 4 x 16
+// tile (wave wv owns z-slice wv, fragment f row f, lane (i, g) voxels 4 g + r
+// of channel 16 n + i).  A BF16-only output slice (cout = 16 NF, 16-byte
+// aligned rows) goes through `ot` (LDS, >= 256 x (16 min(NF, 4) + 8) BF16,
+// free after the last barrier) and out as 16-byte rows.
+template <int NF>
+__device__ __forceinline__ void conv_store(const ConvArgs &a, f4 (&acc)[4][NF], int bn, int z0, int y0, int x0, int wv,
+                                           int lane, uint16_t *ot)
+{
+    constexpr int CO = 16 * NF;
+    const int g = lane >> 4, i = lane & 15;
+    const int oz = z0 + wv;
+    const bool fast = a.y && !a.y32 && a.cout == CO && (a.cy % 8) == 0 && (a.y_off % 8) == 0 &&
+                      ((uintptr_t)a.y & 15) == 0;
+    if (fast) {
+        // D[i][j] -> LDS row (wave, f, x = 4 (lane / 16) + r), channel 16 n + lane % 16; then 16-byte rows out
+        constexpr int NP = NF == 8 ? 2 : 1;                   // channel passes (128 channels: two of 64)
+        constexpr int CP = CO / NP;
+        constexpr int PROW = CP + 8;
+#pragma unroll
+        for (int pass = 0; pass < NP; pass++) {
+#pragma unroll
+            for (int f = 0; f < 4; f++)
+#pragma unroll
+                for (int nn = 0; nn < NF / NP; nn++) {
+                    const int n = pass * (NF / NP) + nn;
+                    const float bias = a.bias ? a.bias[16 * n + i] : 0.0f;
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        float val = acc[f][n][r] + bias;
+                        if (a.relu) val = fmaxf(val, 0.0f);
+                        ot[((wv * 4 + f) * 16 + 4 * g + r) * PROW + 16 * nn + i] = f2bf(val);
+                    }
+                }
+            __syncthreads();
+            for (int e = threadIdx.x; e < 256 * (CP / 8); e += 256) {
+                const int vl = e / (CP / 8), part = e % (CP / 8);
+                const int tz = vl >> 6, ty = (vl >> 4) & 3, tx = vl & 15;
+                const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
+                if (gz < a.od && gy < a.oh && gx < a.ow) {
+                    const long long gv = (((long long)bn * a.od + gz) * a.oh + gy) * a.ow + gx;
+                    *(uint4 *)(a.y + gv * a.cy + a.y_off + pass * CP + 8 * part) = *(const uint4 *)(ot + vl * PROW + 8 * part);
+                }
+            }
+            if (pass + 1 < NP) __syncthreads();
+        }
+        return;
+    }
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+        const int oy = y0 + f;
+        if (oz >= a.od || oy >= a.oh) continue;
+#pragma unroll
+        for (int n = 0; n < NF; n++) {
+            const int co = 16 * n + (lane & 15);
+            if (co >= a.cout) continue;
+            const float bias = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int ox = x0 + 4 * (lane >> 4) + r;
+                if (ox >= a.ow) continue;
+                const long long v = (((long long)bn * a.od + oz) * a.oh + oy) * a.ow + ox;
+                float val = acc[f][n][r] + bias;
+                if (a.relu) val = fmaxf(val, 0.0f);
+                if (a.y) a.y[v * a.cy + a.y_off + co] = f2bf(val);
+                if (a.y32) a.y32[v * a.cy32 + co] = val;
+            }
+        }
+    }
+}
+
 // The same tiling on v_mfma_f32_16x16x32_bf16 for a multiple of 32 input
 // channels.  K slot 4 h + r of lane group g (= lane / 16) carries channel
 // 16 h + 4 g + r of the 32-channel chunk, for A (halo) and B (packed weights)
@@ -270,9 +341,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds32(ConvArgs a)
     constexpr int HY = KIND == KIND_C3 ? HLY : TLY / 2 + 2;
     constexpr int HX = KIND == KIND_C3 ? HLX : TLX / 2 + 2;
     constexpr int NH = HZ * HY * HX;
-    constexpr int CO = 16 * NF;
-    constexpr int OROW = CO + 8;                               // output row in LDS (bf16), padded against conflicts
-    static_assert(256 * OROW * 2 <= HLZ * HLY * HLX * 64 || NF == 8, "output tile must fit the halo buffer");
+    static_assert(256 * (16 * (NF < 4 ? NF : 4) + 8) * 2 <= HLZ * HLY * HLX * 64, "output tile must fit the halo buffer");
     __shared__ uint4 halo[HLZ * HLY * HLX * 4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int tiles_x = (a.ow + TLX - 1) / TLX, tiles_y = (a.oh + TLY - 1) / TLY, tiles_z = (a.od + TLZ - 1) / TLZ;
@@ -358,65 +427,64 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds32(ConvArgs a)
         }
         __syncthreads();
     }
-    const int oz = z0 + wv;
-    const bool fast = a.y && !a.y32 && a.cout == CO && (a.cy % 8) == 0 && (a.y_off % 8) == 0 &&
-                      ((uintptr_t)a.y & 15) == 0;
-    if (fast) {
-        // D[i][j] -> LDS row (wave, f, x = 4 (lane / 16) + r), channel 16 n + lane % 16; then 16-byte rows out
-        uint16_t *ot = (uint16_t *)halo;
-        constexpr int NP = NF == 8 ? 2 : 1;                   // channel passes (128 channels: two of 64)
-        constexpr int CP = CO / NP;
-        constexpr int PROW = CP + 8;
-#pragma unroll
-        for (int pass = 0; pass < NP; pass++) {
-#pragma unroll
-            for (int f = 0; f < 4; f++)
-#pragma unroll
-                for (int nn = 0; nn < NF / NP; nn++) {
-                    const int n = pass * (NF / NP) + nn;
-                    const float bias = a.bias ? a.bias[16 * n + i] : 0.0f;
-#pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        float val = acc[f][n][r] + bias;
-                        if (a.relu) val = fmaxf(val, 0.0f);
-                        ot[((wv * 4 + f) * 16 + 4 * g + r) * PROW + 16 * nn + i] = f2bf(val);
-                    }
-                }
-            __syncthreads();
-            for (int e = threadIdx.x; e < 256 * (CP / 8); e += 256) {
-                const int vl = e / (CP / 8), part = e % (CP / 8);
-                const int tz = vl >> 6, ty = (vl >> 4) & 3, tx = vl & 15;
-                const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
-                if (gz < a.od && gy < a.oh && gx < a.ow) {
-                    const long long gv = (((long long)bn * a.od + gz) * a.oh + gy) * a.ow + gx;
-                    *(uint4 *)(a.y + gv * a.cy + a.y_off + pass * CP + 8 * part) = *(const uint4 *)(ot + vl * PROW + 8 * part);
-                }
-            }
-            if (pass + 1 < NP) __syncthreads();
-        }
-        return;
+    conv_store<NF>(a, acc, bn, z0, y0, x0, wv, lane, (uint16_t *)halo);
+}
+
+// First layer: 3^3 convolution over 8 input channels with the taps folded
+// into K.  K step c (32 wide) covers taps 4 c .. 4 c + 3: lane group g takes
+// tap 4 c + g and its 8 elements are the 8 channels of that tap's input voxel
+// (one 16-byte LDS read); 7 steps cover the 27 taps (the 28th has zero
+// weights and reads tap 26's voxel).  The halo holds 8 channels per voxel.
+constexpr int FIRST_STEPS = 7;
+
+template <int NF>
+__global__ __launch_bounds__(256, 2) void k_conv_first(ConvArgs a)
+{
+    constexpr int NH = HLZ * HLY * HLX;
+    constexpr int OBUF = (256 * (16 * (NF < 4 ? NF : 4) + 8) * 2 + 15) / 16;   // epilogue rows, in uint4
+    __shared__ uint4 lds[NH > OBUF ? NH : OBUF];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tiles_x = (a.ow + TLX - 1) / TLX, tiles_y = (a.oh + TLY - 1) / TLY, tiles_z = (a.od + TLZ - 1) / TLZ;
+    int b = blockIdx.x;
+    const int bx = b % tiles_x;
+    b /= tiles_x;
+    const int by = b % tiles_y;
+    b /= tiles_y;
+    const int bz = b % tiles_z;
+    const int bn = b / tiles_z;
+    const int z0 = bz * TLZ, y0 = by * TLY, x0 = bx * TLX;
+    const uint16_t *xb = a.x + (long long)bn * a.id * a.ih * a.iw * a.cx + a.x_off;
+    for (int v = threadIdx.x; v < NH; v += 256) {
+        const int lx = v % HLX, ly = (v / HLX) % HLY, lz = v / (HLX * HLY);
+        const int gz = z0 - 1 + lz, gy = y0 - 1 + ly, gx = x0 - 1 + lx;
+        uint4 val = make_uint4(0u, 0u, 0u, 0u);
+        if (gz >= 0 && gy >= 0 && gx >= 0 && gz < a.id && gy < a.ih && gx < a.iw)
+            val = *(const uint4 *)(xb + (((long long)gz * a.ih + gy) * a.iw + gx) * a.cx);
+        lds[v] = val;
     }
+    __syncthreads();
+    f4 acc[4][NF];
 #pragma unroll
-    for (int f = 0; f < 4; f++) {
-        const int oy = y0 + f;
-        if (oz >= a.od || oy >= a.oh) continue;
+    for (int f = 0; f < 4; f++)
+#pragma unroll
+        for (int n = 0; n < NF; n++) acc[f][n] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int g = lane >> 4, i = lane & 15;
+#pragma unroll
+    for (int c = 0; c < FIRST_STEPS; c++) {
+        const int t = min(4 * c + g, 26);
+        const int ta = t / 9, tb = (t / 3) % 3, tc = t % 3;
+        b8 A[4];
+#pragma unroll
+        for (int f = 0; f < 4; f++) A[f] = __builtin_bit_cast(b8, lds[((wv + ta) * HLY + f + tb) * HLX + i + tc]);
 #pragma unroll
         for (int n = 0; n < NF; n++) {
-            const int co = 16 * n + (lane & 15);
-            if (co >= a.cout) continue;
-            const float bias = a.bias ? a.bias[co] : 0.0f;
+            const b8 Bv = __builtin_bit_cast(b8, *(const uint4 *)(a.w + ((size_t)(c * NF + n) * 64 + lane) * 8));
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int ox = x0 + 4 * (lane >> 4) + r;
-                if (ox >= a.ow) continue;
-                const long long v = (((long long)bn * a.od + oz) * a.oh + oy) * a.ow + ox;
-                float val = acc[f][n][r] + bias;
-                if (a.relu) val = fmaxf(val, 0.0f);
-                if (a.y) a.y[v * a.cy + a.y_off + co] = f2bf(val);
-                if (a.y32) a.y32[v * a.cy32 + co] = val;
-            }
+            for (int f = 0; f < 4; f++) acc[f][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[f], Bv, acc[f][n], 0, 0, 0);
         }
     }
+    __syncthreads();   // the epilogue reuses the halo's LDS
+    conv_store<NF>(a, acc, bn, z0, y0, x0, wv, lane, (uint16_t *)lds);
 }
 
 // Pack FP32 master weights W[tap][ci][co] (ci < cin, co < cout) into the
@@ -426,13 +494,26 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds32(ConvArgs a)
 //            B[k][j], k = 16 c + 4 (lane / 16) + r (16x16x16 fragments);
 //   k32 = 1: element (((t * KC2 + c) * NF + n) * 64 + lane) * 8 + 4 h + r holds
 //            k = 32 c + 16 h + 4 (lane / 16) + r (16x16x32 fragments).
+//   k32 = 2: the first-layer order (8 input channels, taps folded into K):
+//            element ((c * NF + n) * 64 + lane) * 8 + j holds tap 4 c + lane / 16
+//            (zero for tap 27), channel j.
 __global__ void k_pack(const float *w, int ntap, int cin, int cout, int cin_p, int cout_p, int transpose, int k32,
                        uint16_t *out)
 {
     const int KC = cin_p / 16, NF = cout_p / 16;
-    const long long total = (long long)ntap * KC * NF * 256;
+    const long long total = k32 == 2 ? (long long)FIRST_STEPS * NF * 512 : (long long)ntap * KC * NF * 256;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
         int k, lane, n, t;
+        if (k32 == 2) {
+            const int j = (int)(e & 7);
+            lane = (int)((e >> 3) & 63);
+            const long long q = e >> 9;
+            n = (int)(q % NF);
+            t = 4 * (int)(q / NF) + (lane >> 4);
+            const int co = 16 * n + (lane & 15);
+            out[e] = f2bf(t < 27 && j < cin && co < cout ? w[((long long)t * cin + j) * cout + co] : 0.0f);
+            continue;
+        }
         if (!k32) {
             const int r = (int)(e & 3);
             lane = (int)((e >> 2) & 63);
@@ -1083,6 +1164,19 @@ static hipError_t conv_lds(const ConvArgs &a, hipStream_t st)
 
 hipError_t conv(const ConvArgs &a, hipStream_t st)
 {
+    if (a.kind == KIND_C3 && a.cin == 8) {
+        if (a.cx % 8 || a.x_off % 8 || ((uintptr_t)a.x & 15)) return hipErrorInvalidValue;
+        const long long tiles = (long long)a.n * ((a.od + TLZ - 1) / TLZ) * ((a.oh + TLY - 1) / TLY) * ((a.ow + TLX - 1) / TLX);
+        if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+        switch ((a.cout + 15) / 16) {
+        case 1: k_conv_first<1><<<(unsigned)tiles, 256, 0, st>>>(a); break;
+        case 2: k_conv_first<2><<<(unsigned)tiles, 256, 0, st>>>(a); break;
+        case 4: k_conv_first<4><<<(unsigned)tiles, 256, 0, st>>>(a); break;
+        case 8: k_conv_first<8><<<(unsigned)tiles, 256, 0, st>>>(a); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (a.kind == KIND_C3) return conv_lds<KIND_C3>(a, st);
     if (a.kind == KIND_UP) return conv_lds<KIND_UP>(a, st);
     const long long nvox = (long long)a.n * a.od * a.oh * a.ow;
@@ -1101,8 +1195,14 @@ hipError_t pack(const float *w, int ntap, int cin, int cout, int cin_p, int cout
                 hipStream_t st)
 {
     const long long total = (long long)ntap * (cin_p / 16) * (cout_p / 16) * 256;
-    // 3^3 kernels with a multiple of 32 input channels run on 16x16x32 fragments
-    const int k32 = ntap == 27 && cin_p % 32 == 0;
+    // 3^3 kernels with a multiple of 32 input channels run on 16x16x32 fragments, and so does the
+    // 3^3 layer over 8 input channels (taps folded into K)
+    const int k32 = ntap == 27 && !transpose && cin == 8 ? 2 : (ntap == 27 && cin_p % 32 == 0);
+    if (k32 == 2) {
+        const long long n2 = (long long)FIRST_STEPS * (cout_p / 16) * 512;
+        k_pack<<<grid_for(n2), 256, 0, st>>>(w, ntap, cin, cout, cin_p, cout_p, transpose, k32, out);
+        return hipGetLastError();
+    }
     k_pack<<<grid_for(total), 256, 0, st>>>(w, ntap, cin, cout, cin_p, cout_p, transpose, k32, out);
     return hipGetLastError();
 }

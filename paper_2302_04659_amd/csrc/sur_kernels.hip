@@ -34,19 +34,25 @@ hipError_t launch_colliders_now(const StepArgs &a, int n_cols, const int *col_sc
     return hipGetLastError();
 }
 
-// Every node of every scene: collider channels of the input (4: clipped
-// distance to the nearest collider in cells, 5-7: that collider's velocity
-// at the node where it is closer than 3 cells), zeros in channels 0-3 (the
-// grid update fills the nodes that receive mass) and above 7, and a zero
-// start grid.
-__global__ __launch_bounds__(WG) void k_sur_dense(StepArgs a, int res, float *feat, int cf, float *grid0)
+// Every node of every scene's surrogate box (the whole grid without a box):
+// collider channels of the input (4: clipped distance to the nearest
+// collider in cells, 5-7: that collider's velocity at the node where it is
+// closer than 3 cells), zeros in channels 0-3 (the grid update fills the
+// nodes that receive mass) and above 7, and a zero start grid.
+__global__ __launch_bounds__(WG) void k_sur_init(StepArgs a, int res, float *feat, int cf, float *grid0)
 {
-    const long long R3 = (long long)res * res * res, total = R3 * a.n_scenes;
+    const int D = a.sur_org ? a.sur_box[0] : res, H = a.sur_org ? a.sur_box[1] : res, W = a.sur_org ? a.sur_box[2] : res;
+    const long long per = (long long)D * H * W, total = per * a.n_scenes;
     for (long long e = (long long)blockIdx.x * WG + threadIdx.x; e < total; e += (long long)gridDim.x * WG) {
-        const int s = (int)(e / R3);
-        const long long c = e - (long long)s * R3;
+        const int s = (int)(e / per);
+        const long long c = e - (long long)s * per;
         const SceneDev &S = a.scenes[s];
-        const int i = (int)(c / ((long long)res * res)), j = (int)((c / res) % res), k = (int)(c % res);
+        int i = (int)(c / ((long long)H * W)), j = (int)((c / W) % H), k = (int)(c % W);
+        if (a.sur_org) {
+            i += a.sur_org[3 * s];
+            j += a.sur_org[3 * s + 1];
+            k += a.sur_org[3 * s + 2];
+        }
         const float xi[3] = {i * S.dx, j * S.dx, k * S.dx};
         float phi_min = 3.0f * S.dx, vel[3] = {0.0f, 0.0f, 0.0f};
         const ColliderNow *cn = (const ColliderNow *)a.colnow + S.col_off;
@@ -73,11 +79,81 @@ __global__ __launch_bounds__(WG) void k_sur_dense(StepArgs a, int res, float *fe
     }
 }
 
-hipError_t launch_sur_dense(const StepArgs &a, int res, float *feat, int cf, float *grid0, hipStream_t st)
+hipError_t launch_sur_init(const StepArgs &a, int res, float *feat, int cf, float *grid0, hipStream_t st)
 {
-    const long long total = (long long)res * res * res * a.n_scenes;
-    const long long nb = (total + WG - 1) / WG;
-    k_sur_dense<<<(unsigned)(nb < 16384 ? nb : 16384), WG, 0, st>>>(a, res, feat, cf, grid0);
+    const long long per = a.sur_org ? (long long)a.sur_box[0] * a.sur_box[1] * a.sur_box[2] : (long long)res * res * res;
+    const long long nb = (per * a.n_scenes + WG - 1) / WG;
+    if (nb > 0) k_sur_init<<<(unsigned)(nb < 16384 ? nb : 16384), WG, 0, st>>>(a, res, feat, cf, grid0);
+    return hipGetLastError();
+}
+
+// Per scene, the box of grid nodes the particles' P2G stencils reach (base
+// node .. base + 2 on each axis): box[6 s ..] = (lo i, j, k, hi i, j, k),
+// inclusive; all zero for a scene without particles.  Workgroup (x, s) takes
+// a stride of scene s's particles.
+__global__ __launch_bounds__(WG) void k_sur_bbox(StepArgs a, int *box)
+{
+    __shared__ int red[6][WG / 64];
+    const int s = blockIdx.y;
+    const SceneDev &S = a.scenes[s];
+    const SceneK K = scene_k(S);
+    int lo[3] = {K.res, K.res, K.res}, hi[3] = {-1, -1, -1};
+    for (int p = S.p_begin + blockIdx.x * WG + threadIdx.x; p < S.p_end; p += gridDim.x * WG) {
+        int cl = 0;
+        for (int d = 0; d < 3; d++) {
+            int b;
+            float f;
+            particle_base(K, a.P[(long long)(X0 + d) * a.pstride + p], b, f, cl);
+            lo[d] = min(lo[d], b);
+            hi[d] = max(hi[d], b + 2);
+        }
+    }
+    for (int d = 0; d < 3; d++)
+        for (int o = 32; o > 0; o >>= 1) {
+            lo[d] = min(lo[d], __shfl_xor(lo[d], o, 64));
+            hi[d] = max(hi[d], __shfl_xor(hi[d], o, 64));
+        }
+    if ((threadIdx.x & 63) == 0)
+        for (int d = 0; d < 3; d++) {
+            red[d][threadIdx.x >> 6] = lo[d];
+            red[3 + d][threadIdx.x >> 6] = hi[d];
+        }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int d = threadIdx.x;
+        int l = red[d][0], h = red[3 + d][0];
+        for (int w = 1; w < WG / 64; w++) {
+            l = min(l, red[d][w]);
+            h = max(h, red[3 + d][w]);
+        }
+        if (h >= 0) {
+            atomicMin(box + 6 * s + d, l);
+            atomicMax(box + 6 * s + 3 + d, h);
+        }
+    }
+}
+
+// Empty scenes (no particle reached the reduction) get an all-zero box.
+__global__ void k_sur_bbox_final(int n, int *box)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    if (box[6 * s + 3] < 0)
+        for (int d = 0; d < 6; d++) box[6 * s + d] = 0;
+}
+
+__global__ void k_sur_bbox_init(int n, int res, int *box)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < 6 * n) box[e] = (e % 6) < 3 ? res : -1;
+}
+
+hipError_t launch_sur_bbox(const StepArgs &a, int res, int *box, hipStream_t st)
+{
+    if (a.n_scenes <= 0) return hipSuccess;
+    k_sur_bbox_init<<<(6 * a.n_scenes + 255) / 256, 256, 0, st>>>(a.n_scenes, res, box);
+    k_sur_bbox<<<dim3(16, a.n_scenes), WG, 0, st>>>(a, box);
+    k_sur_bbox_final<<<(a.n_scenes + 63) / 64, 64, 0, st>>>(a.n_scenes, box);
     return hipGetLastError();
 }
 
@@ -109,12 +185,13 @@ __device__ void sur_advance_item(const StepArgs &a, int it, const Item &item, fl
     const int nb = S.nb;
     const int bx = item.block / (nb * nb), by = (item.block / nb) % nb, bz = item.block % nb;
     const int org[3] = {bx * B - 1, by * B - 1, bz * B - 1};
-    const long long base = a.cap_off[s];
     for (int n = t; n < T3; n += WG) {
         const int gi = org[0] + n / (T * T), gj = org[1] + (n / T) % T, gk = org[2] + n % T;
         float vs[3] = {0.0f, 0.0f, 0.0f}, dv[3] = {0.0f, 0.0f, 0.0f};
-        if (gi >= 0 && gj >= 0 && gk >= 0 && gi < S.res && gj < S.res && gk < S.res)
-            sur_node(grid0, pred, cp, base + ((long long)gi * S.res + gj) * S.res + gk, vs, dv);
+        if (gi >= 0 && gj >= 0 && gk >= 0 && gi < S.res && gj < S.res && gk < S.res) {
+            const long long c = sur_index(a, s, S.res, gi, gj, gk);
+            if (c >= 0) sur_node(grid0, pred, cp, c, vs, dv);   // outside the box: no material, no change
+        }
         for (int d = 0; d < 3; d++) {
             vt[d * T3 + n] = fmaf(0.5f, dv[d], vs[d]);
             vt[(3 + d) * T3 + n] = vs[d] + dv[d];
@@ -158,9 +235,9 @@ __device__ void sur_advance_item(const StepArgs &a, int it, const Item &item, fl
                             ue[d] = vt[(3 + d) * T3 + n];
                         }
                     } else {
-                        float vs[3], dv[3];
-                        sur_node(grid0, pred, cp, base + ((long long)(b[0] + ox) * K.res + b[1] + oy) * K.res + b[2] + oz,
-                                 vs, dv);
+                        float vs[3] = {0.0f, 0.0f, 0.0f}, dv[3] = {0.0f, 0.0f, 0.0f};
+                        const long long c = sur_index(a, s, K.res, b[0] + ox, b[1] + oy, b[2] + oz);
+                        if (c >= 0) sur_node(grid0, pred, cp, c, vs, dv);
                         for (int d = 0; d < 3; d++) {
                             um[d] = fmaf(0.5f, dv[d], vs[d]);
                             ue[d] = vs[d] + dv[d];
@@ -254,14 +331,15 @@ __global__ __launch_bounds__(WG) void k_sur_residual(StepArgs a, int res, const 
                                                      const float *gend, float *acc)
 {
     __shared__ float red[4][WG / 64];
-    const long long R3 = (long long)res * res * res;
-    const long long c0 = (long long)blockIdx.x * RES_CHUNK;
-    const int s = (int)(c0 / R3);
+    const int s = blockIdx.y;
+    const long long per = a.sur_org ? (long long)a.sur_box[0] * a.sur_box[1] * a.sur_box[2] : (long long)res * res * res;
+    const long long base = a.sur_org ? (long long)s * per : a.cap_off[s];
+    const long long l0 = (long long)blockIdx.x * RES_CHUNK, l1 = min(per, l0 + RES_CHUNK);
     const SceneDev &S = a.scenes[s];
     const float mu = S.mass / S.vol * S.dx * S.dx * S.dx * SUR_DM;   // mass unit of the prediction
     float sm = 0.0f, sp = 0.0f, m0 = 0.0f, p0 = 0.0f;
-    for (int q = threadIdx.x; q < RES_CHUNK; q += WG) {
-        const long long c = c0 + q;
+    for (long long l = l0 + threadIdx.x; l < l1; l += WG) {
+        const long long c = base + l;
         const float4 g = *(const float4 *)(grid0 + 4 * c);
         const float4 r = *(const float4 *)(gend + 4 * c);
         if (g.x == 0.0f && r.x == 0.0f) continue;   // no material at this node before or after
@@ -273,6 +351,8 @@ __global__ __launch_bounds__(WG) void k_sur_residual(StepArgs a, int res, const 
         m0 += g.x;
         p0 += g.x * (fabsf(g.y) + fabsf(g.z) + fabsf(g.w));
     }
+    // re-splat mass outside the box has no prediction to match: all of it is mismatch
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.out_mass) sm += a.out_mass[s];
     float v4[4] = {sm, sp, m0, p0};
     for (int k = 0; k < 4; k++) {
         float v = v4[k];
@@ -290,9 +370,9 @@ __global__ __launch_bounds__(WG) void k_sur_residual(StepArgs a, int res, const 
 hipError_t launch_sur_residual(const StepArgs &a, int res, const float *grid0, const float *pred, int cp,
                                const float *gend, float *acc, hipStream_t st)
 {
-    const long long R3 = (long long)res * res * res;
-    if (R3 % RES_CHUNK) return hipErrorInvalidValue;
-    k_sur_residual<<<(unsigned)(R3 / RES_CHUNK * a.n_scenes), WG, 0, st>>>(a, res, grid0, pred, cp, gend, acc);
+    const long long per = a.sur_org ? (long long)a.sur_box[0] * a.sur_box[1] * a.sur_box[2] : (long long)res * res * res;
+    const long long nb = (per + RES_CHUNK - 1) / RES_CHUNK;
+    if (a.n_scenes > 0 && nb > 0) k_sur_residual<<<dim3((unsigned)nb, a.n_scenes), WG, 0, st>>>(a, res, grid0, pred, cp, gend, acc);
     return hipGetLastError();
 }
 

@@ -76,8 +76,10 @@ def lib():
         L.mpm_get_order.argtypes = [vp, vp]
         L.mpm_get_timing.argtypes = [vp, vp, vp, ct.c_int]
         L.mpm_set_scene_mask.argtypes = [vp, vp]
-        L.mpm_sur_features.argtypes = [vp, vp, ct.c_int, vp]
-        L.mpm_sur_block.argtypes = [vp, vp, ct.c_int, vp, ct.c_float, ct.c_int, vp, vp]
+        L.mpm_sur_bbox.argtypes = [vp, vp]
+        L.mpm_sur_features.argtypes = [vp, vp, ct.c_int, vp, vp, ct.c_int, ct.c_int, ct.c_int]
+        L.mpm_sur_block.argtypes = [vp, vp, ct.c_int, vp, vp, ct.c_int, ct.c_int, ct.c_int, ct.c_float, ct.c_int, vp,
+                                    vp]
         L.mpm_sur_targets.argtypes = [vp, vp, vp, vp, ct.c_int, vp]
         for name in ("mpm_num_scenes", "mpm_max_colliders"):
             getattr(L, name).argtypes = [vp]
@@ -215,16 +217,24 @@ class Sim:
         return self._check(self.L.mpm_set_scene_mask(self.h, a.ctypes.data), "set_scene_mask")
 
     # ----------------------------------------------------------------- grid surrogate (device tensors)
-    def sur_features(self, feat, grid0):
-        """feat [n_scenes, R, R, R, cf] and grid0 [n_scenes, R, R, R, 4] FP32 device tensors."""
-        return self._check(self.L.mpm_sur_features(self.h, _ptr(feat), int(feat.shape[-1]), _ptr(grid0)),
-                           "sur_features")
+    def sur_bbox(self, box):
+        """box [n_scenes, 6] int32 device tensor <- nodes the P2G stencils reach (lo, hi inclusive)."""
+        return self._check(self.L.mpm_sur_bbox(self.h, _ptr(box)), "sur_bbox")
+
+    def sur_features(self, feat, grid0, origin=None):
+        """feat [n_scenes, D, H, W, cf] and grid0 [n_scenes, D, H, W, 4] FP32 device tensors on the
+        per-scene boxes at `origin` ([n_scenes, 3] int32 device tensor), or on the whole grid
+        (origin None, D = H = W = res)."""
+        D, H, W = (int(d) for d in feat.shape[1:4])
+        return self._check(self.L.mpm_sur_features(self.h, _ptr(feat), int(feat.shape[-1]), _ptr(grid0), _ptr(origin),
+                                                   D, H, W), "sur_features")
 
     def sur_block(self, pred, grid0, threshold: float = 1e-3, fallback: bool = True, sync: bool = False,
-                  residual=None, n_fallback=None):
+                  residual=None, n_fallback=None, origin=None):
         flags = (0 if fallback else SUR_NO_FALLBACK) | (SUR_SYNC if sync else 0)
-        return self._check(self.L.mpm_sur_block(self.h, _ptr(pred), int(pred.shape[-1]), _ptr(grid0),
-                                                float(threshold), flags, _ptr(residual), _ptr(n_fallback)),
+        D, H, W = (int(d) for d in pred.shape[1:4])
+        return self._check(self.L.mpm_sur_block(self.h, _ptr(pred), int(pred.shape[-1]), _ptr(grid0), _ptr(origin),
+                                                D, H, W, float(threshold), flags, _ptr(residual), _ptr(n_fallback)),
                            "sur_block")
 
     def sur_targets(self, g0, g1, target, mask):

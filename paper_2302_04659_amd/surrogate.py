@@ -91,62 +91,78 @@ class GridSurrogate:
         self._cbuf = None
         torch.cuda.synchronize()      # weights and buffers made on other streams are ready
         with torch.cuda.stream(self.ts):
-            self.feat = torch.zeros((S, R, R, R, CIN), dtype=torch.float32, device=dev)
-            self.grid0 = torch.zeros((S, R, R, R, 4), dtype=torch.float32, device=dev)
-            self.pred = torch.zeros((S, R, R, R, COUT), dtype=torch.float32, device=dev)
             self.residual = torch.zeros(S, dtype=torch.float32, device=dev)
             self.n_fallback = torch.zeros(1, dtype=torch.int32, device=dev)
             self.box = torch.zeros((S, 6), dtype=torch.int32, device=dev)
             self.origin = torch.zeros((S, 3), dtype=torch.int32, device=dev)
+        self._dense = None            # whole-grid arrays (crop = False, block_with), made on first use
+        self._cur = None              # (prediction, start grid, box origin or None) of the last predict()
+
+    def dense(self):
+        """Whole-grid feat, grid0 and pred arrays (made on first use)."""
+        torch = _torch()
+        if self._dense is None:
+            S, R, dev = self.S, self.R, self.net.device
+            with torch.cuda.stream(self.ts):
+                self._dense = (torch.zeros((S, R, R, R, CIN), dtype=torch.float32, device=dev),
+                               torch.zeros((S, R, R, R, 4), dtype=torch.float32, device=dev),
+                               torch.zeros((S, R, R, R, COUT), dtype=torch.float32, device=dev))
+        return self._dense
 
     def predict(self):
         """Features of the current state and the network's prediction (device).
-        With crop = True the network runs on a box around each scene's
-        material (one host read of the boxes per call) and predicts zero
-        outside it."""
+        With crop = True the features are made and the network runs on a box
+        around each scene's material (the nodes the particles' P2G stencils
+        reach, plus a margin; one host read of the boxes per call), and the
+        prediction is zero outside it."""
         torch = _torch()
         L = self.net.L
         with torch.cuda.stream(self.ts):
             s = self.ts.cuda_stream
-            self.sim.sur_features(self.feat, self.grid0)
             if not self.crop:
+                feat, grid0, pred = self.dense()
+                self.sim.sur_features(feat, grid0)
                 for i in range(0, self.S, self.chunk):
                     j = min(self.S, i + self.chunk)
-                    self.net.forward(self.feat[i:j], out=self.pred[i:j])
+                    self.net.forward(feat[i:j], out=pred[i:j])
+                self._cur = (pred, grid0, None)
                 return
-            if L.mpm_nn_bbox(self.feat.data_ptr(), CIN, self.S, self.R, self.box.data_ptr(), s) != 0:
-                raise RuntimeError("mpm_nn_bbox failed")
+            self.sim.sur_bbox(self.box)
             shape = crop_shape(self.box.cpu().numpy(), self.margin, self.R)
             D, H, W = shape
             if L.mpm_nn_crop_origin(self.box.data_ptr(), self.S, self.R, D, H, W, self.origin.data_ptr(), s) != 0:
                 raise RuntimeError("mpm_nn_crop_origin failed")
             if self._cbuf is None or self._cbuf[0] != shape:
+                dev = self.net.device
                 self._cbuf = (shape,
-                              torch.zeros((self.S, D, H, W, CIN), dtype=torch.float32, device=self.net.device),
-                              torch.zeros((self.S, D, H, W, COUT), dtype=torch.float32, device=self.net.device))
-            _, fc, pc = self._cbuf
+                              torch.zeros((self.S, D, H, W, CIN), dtype=torch.float32, device=dev),
+                              torch.zeros((self.S, D, H, W, 4), dtype=torch.float32, device=dev),
+                              torch.zeros((self.S, D, H, W, COUT), dtype=torch.float32, device=dev))
+            _, fc, gc, pc = self._cbuf
             self.crop_shape = shape
-            _crop_all(L, s, self.feat, CIN, self.S, self.R, self.origin, shape, fc)
+            self.sim.sur_features(fc, gc, origin=self.origin)
             for i in range(0, self.S, self.chunk):
                 j = min(self.S, i + self.chunk)
                 self.net.forward(fc[i:j], out=pc[i:j])
-            _crop_all(L, s, pc, COUT, self.S, self.R, self.origin, shape, self.pred, uncrop=1)
+            self._cur = (pc, gc, self.origin)
 
     def block(self, fallback: bool = True, sync: bool = False):
         """One control step of every scene (surrogate, plain MPM where the
         residual is over the threshold)."""
         torch = _torch()
         self.predict()
+        pred, grid0, origin = self._cur
         with torch.cuda.stream(self.ts):
-            self.sim.sur_block(self.pred, self.grid0, self.threshold, fallback=fallback, sync=sync,
-                               residual=self.residual, n_fallback=self.n_fallback)
+            self.sim.sur_block(pred, grid0, self.threshold, fallback=fallback, sync=sync,
+                               residual=self.residual, n_fallback=self.n_fallback, origin=origin)
 
     def block_with(self, pred, fallback: bool = False):
-        """A control step from a given prediction (baselines)."""
+        """A control step from a given whole-grid prediction (baselines)."""
         torch = _torch()
+        feat, grid0, _ = self.dense()
         with torch.cuda.stream(self.ts):
-            self.sim.sur_features(self.feat, self.grid0)
-            self.sim.sur_block(pred, self.grid0, self.threshold, fallback=fallback, residual=self.residual,
+            self.sim.sur_features(feat, grid0)
+            self.sim.sur_block(pred, grid0, self.threshold, fallback=fallback, residual=self.residual,
                                n_fallback=self.n_fallback)
 
 

@@ -144,7 +144,12 @@ class UNet:
             w = self.params[name + ".w"]
             taps = TAPS[kind]
             fw = torch.zeros(taps * _ceil16(ci) * _ceil16(co), dtype=torch.int16, device=self.device)
-            _chk(self.L.mpm_nn_pack(w.data_ptr(), KIND[kind], ci, co, 0, fw.data_ptr(), self.stream), "pack")
+            if name == "e1a" and self.cin == 8:
+                # the first layer sees the 8 real input channels (taps folded into the MFMA K)
+                w8 = w[:, :8, :].contiguous()
+                _chk(self.L.mpm_nn_pack(w8.data_ptr(), KIND[kind], 8, co, 0, fw.data_ptr(), self.stream), "pack")
+            else:
+                _chk(self.L.mpm_nn_pack(w.data_ptr(), KIND[kind], ci, co, 0, fw.data_ptr(), self.stream), "pack")
             bw = torch.zeros(taps * _ceil16(co) * _ceil16(ci), dtype=torch.int16, device=self.device)
             _chk(self.L.mpm_nn_pack(w.data_ptr(), KIND[kind], ci, co, 1, bw.data_ptr(), self.stream), "pack")
             self.packs[name] = (fw, bw)
@@ -209,7 +214,7 @@ class UNet:
         c1, c2, c3 = 32 // w, 64 // w, 128 // w
         _chk(self.L.mpm_nn_to_bf16(x32.data_ptr(), x32.shape[-1], nvox, self.cin, b["x"].ptr, b["x"].c, 0,
                                    b["x"].c, self.stream), "to_bf16")
-        self._conv("e1a", b["x"], 0, b["x"].c, b["a1"], 0)
+        self._conv("e1a", b["x"], 0, 8 if self.cin == 8 else b["x"].c, b["a1"], 0)
         self._conv("e1b", b["a1"], 0, c1, b["cat1"], c1)
         self._conv("d1", b["cat1"], c1, c1, b["a2"], 0)
         self._conv("e2a", b["a2"], 0, c2, b["a3"], 0)

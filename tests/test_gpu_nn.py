@@ -83,6 +83,8 @@ CONV_CASES = [
     ("c3", 1, (6, 5, 4), 128, 0, 128, 128),
     ("c3", 1, (5, 4, 18), 40, 4, 32, 32),        # 8-byte staging (slice offset not a multiple of 8)
     ("c3", 1, (4, 5, 21), 64, 0, 64, 64),        # two x tiles, ragged
+    ("c3", 2, (5, 6, 19), 16, 0, 8, 32),         # first layer: 8 input channels, taps folded into K
+    ("c3", 1, (4, 4, 9), 24, 8, 8, 64),
     ("up", 1, (3, 5, 3), 64, 0, 64, 32),
     ("up", 2, (2, 3, 2), 128, 0, 128, 64),
     ("down", 2, (6, 4, 10), 64, 32, 32, 64),
@@ -116,7 +118,7 @@ def test_conv_forward(nn, case, relu, out32):
     L, s = nn.nn_lib(), _stream()
     x_d = _bf16_dev(X)
     w_d = _f32_dev(W.reshape(k ** 3, cin, cout))
-    fw = torch.zeros(k ** 3 * cin * ((cout + 15) // 16 * 16), dtype=torch.int16, device="cuda")
+    fw = torch.zeros(k ** 3 * ((cin + 15) // 16 * 16) * ((cout + 15) // 16 * 16), dtype=torch.int16, device="cuda")
     assert L.mpm_nn_pack(w_d.data_ptr(), nn.KIND[kind], cin, cout, 0, fw.data_ptr(), s) == 0
     b_d = _f32_dev(Bv)
     sentinel = 0x3F80  # bf16 1.0 marks channels the call must not touch

@@ -145,6 +145,110 @@ def test_features_match_oracle(env, orc):
     sim.close()
 
 
+def _state_sims(mpm, batch, ts, n):
+    """n contexts holding the same seeded (x, v, C, F) per scene, colliders at control step 0."""
+    sims = [mpm.Sim(batch, stream=ts.cuda_stream) for _ in range(n)]
+    for s, sc in enumerate(batch):
+        C, F = random_state(sc, 90 + s, c_scale=2.0, f_scale=0.03)
+        for sim in sims:
+            sim.set_state(sc.x, sc.v, C, F, scene=s)
+    for sim in sims:
+        sim.set_colliders_ctrl(0)
+    return sims
+
+
+def test_box_features_and_block_match_whole_grid(env):
+    """The surrogate calls on per-scene boxes give what the whole-grid calls
+    give inside the box: the stencil box of the particles exactly; features
+    and start grid equal to the whole-grid arrays cut to the box (up to the
+    order of the P2G's float flushes at block seams, which differs between
+    two runs); a control step from a prediction that is zero outside the box
+    moves the particles the same way, with the same residual.  A box that
+    cuts the material counts the re-splat mass outside it in full."""
+    torch, mpm = env
+    from paper_2302_04659_amd import surrogate, unet
+    batch = _batch()
+    announce("surrogate box vs whole grid", len(batch))
+    S, R = len(batch), batch[0].res
+    ts = _new_stream(torch)
+    whole, boxed, cut = _state_sims(mpm, batch, ts, 3)
+    L = unet.nn_lib()
+    with torch.cuda.stream(ts):
+        box = torch.zeros((S, 6), dtype=torch.int32, device="cuda")
+        boxed.sur_bbox(box)
+    torch.cuda.synchronize()
+    bh = box.cpu().numpy()
+    for s, sc in enumerate(batch):
+        x, *_ = boxed.get_state(s)
+        b = np.clip(np.floor(x.astype(np.float32) * np.float32(1.0 / sc.dx) - np.float32(0.5)), 0, R - 3).astype(int)
+        assert np.array_equal(bh[s, :3], b.min(axis=0)) and np.array_equal(bh[s, 3:], b.max(axis=0) + 2)
+    shape = surrogate.crop_shape(bh, 2, R)
+    D, H, W = shape
+    assert (D, H, W) != (R, R, R)
+    rng = np.random.default_rng(11)
+    with torch.cuda.stream(ts):
+        s_ = ts.cuda_stream
+        origin = torch.zeros((S, 3), dtype=torch.int32, device="cuda")
+        assert L.mpm_nn_crop_origin(box.data_ptr(), S, R, D, H, W, origin.data_ptr(), s_) == 0
+        fd = torch.zeros((S, R, R, R, 8), dtype=torch.float32, device="cuda")
+        gd = torch.zeros((S, R, R, R, 4), dtype=torch.float32, device="cuda")
+        fb = torch.zeros((S, D, H, W, 8), dtype=torch.float32, device="cuda")
+        gb = torch.zeros((S, D, H, W, 4), dtype=torch.float32, device="cuda")
+        whole.sur_features(fd, gd)
+        boxed.sur_features(fb, gb, origin=origin)
+    torch.cuda.synchronize()
+    o = origin.cpu().numpy()
+    fdh, gdh, fbh, gbh = (t.cpu().numpy() for t in (fd, gd, fb, gb))
+    pd = np.zeros((S, R, R, R, 4), np.float32)
+    for s in range(S):
+        sl = (s, slice(o[s, 0], o[s, 0] + D), slice(o[s, 1], o[s, 1] + H), slice(o[s, 2], o[s, 2] + W))
+        assert np.array_equal(fbh[s][..., 4:], fdh[sl][..., 4:])                      # collider channels
+        for c0, c1 in ((0, 1), (1, 4)):
+            assert rel_l2(fbh[s][..., c0:c1], fdh[sl][..., c0:c1]) <= 1e-6
+        assert rel_l2(gbh[s][..., 0], gdh[sl][..., 0]) <= 1e-6
+        assert rel_l2(gbh[s][..., 0:1] * gbh[s][..., 1:4], gdh[sl][..., 0:1] * gdh[sl][..., 1:4]) <= 1e-6
+        assert np.isclose(gbh[s, ..., 0].sum(), gdh[s, ..., 0].sum(), rtol=1e-6)   # all material inside
+        pd[sl] = (0.05 * rng.normal(size=(D, H, W, 4))).astype(np.float32)
+    pb = np.stack([pd[(s, slice(o[s, 0], o[s, 0] + D), slice(o[s, 1], o[s, 1] + H), slice(o[s, 2], o[s, 2] + W))]
+                   for s in range(S)])
+    with torch.cuda.stream(ts):
+        pd_d = torch.tensor(pd, device="cuda")
+        pb_d = torch.tensor(np.ascontiguousarray(pb), device="cuda")
+        rd = torch.zeros(S, dtype=torch.float32, device="cuda")
+        rb = torch.zeros(S, dtype=torch.float32, device="cuda")
+        whole.sur_block(pd_d, gd, threshold=1e-3, fallback=False, residual=rd)
+        boxed.sur_block(pb_d, gb, threshold=1e-3, fallback=False, residual=rb, origin=origin)
+    torch.cuda.synchronize()
+    assert whole.sync() >= 0 and boxed.sync() >= 0
+    for s, sc in enumerate(batch):
+        xw, vw, Cw, Fw = whole.get_state(s)
+        xb, vb, Cb, Fb = boxed.get_state(s)
+        assert np.abs(xw - xb).max() <= 1e-5 * sc.dx
+        for a, b in ((vw, vb), (Cw, Cb), (Fw - np.eye(3), Fb - np.eye(3))):
+            assert rel_l2(b, a) <= 1e-5
+    assert np.allclose(rb.cpu().numpy(), rd.cpu().numpy(), rtol=1e-3, atol=0.0)
+    # a box 8 nodes deep from the lowest material node of each scene on the first axis: it leaves out
+    # about half of the material
+    Dc = 8
+    with torch.cuda.stream(ts):
+        o_cut = origin.clone()
+        o_cut[:, 0] = box[:, 0]
+        fc = torch.zeros((S, Dc, H, W, 8), dtype=torch.float32, device="cuda")
+        gc = torch.zeros((S, Dc, H, W, 4), dtype=torch.float32, device="cuda")
+        cut.sur_features(fc, gc, origin=o_cut)
+        zero = torch.zeros((S, Dc, H, W, 4), dtype=torch.float32, device="cuda")
+        rc = torch.zeros(S, dtype=torch.float32, device="cuda")
+        cut.sur_block(zero, gc, threshold=1e-3, fallback=False, residual=rc, origin=o_cut)
+    torch.cuda.synchronize()
+    assert cut.sync() >= 0
+    m_in = float(gc[0, ..., 0].sum().item())
+    m_all = float(gdh[0, ..., 0].sum())
+    assert m_in < 0.9 * m_all
+    assert float(rc[0].item()) >= 0.9 * (m_all - m_in) / m_in   # about the mass the start grid missed
+    for sim in (whole, boxed, cut):
+        sim.close()
+
+
 def _linear_field_scene(seed):
     sc = scenes.small_scene(seed, n=4000, res=32, model=scenes.NEO_HOOKEAN, colliders=False, dt=1e-4)
     return dataclasses.replace(sc, gravity=(0.0, 0.0, 0.0))
