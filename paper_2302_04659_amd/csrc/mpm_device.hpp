@@ -28,6 +28,20 @@ __device__ __forceinline__ int active_wgs(int n)
     return min((int)gridDim.x, (n + 7) & ~7);
 }
 
+// Two signed 32-bit terms as one 64-bit addend hi * 2^32 + lo; a sum of such
+// addends (wrapping 64-bit integer adds) unpacks to the two exact sums while
+// each stays inside the int32 range.
+__device__ __forceinline__ unsigned long long pack2(int hi, int lo)
+{
+    return ((unsigned long long)(unsigned)hi << 32) + (unsigned long long)(long long)lo;
+}
+
+__device__ __forceinline__ void unpack2(long long v, int &hi, int &lo)
+{
+    lo = (int)(unsigned)(v & 0xffffffffLL);
+    hi = (int)((v - (long long)lo) >> 32);
+}
+
 __device__ __forceinline__ int cvt_rpi(float x)
 {
     int r;

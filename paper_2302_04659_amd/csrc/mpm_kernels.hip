@@ -419,7 +419,11 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
     const int bx = item.block / (nb * nb), by = (item.block / nb) % nb, bz = item.block % nb;
     const int org[3] = {bx * B - 1, by * B - 1, bz * B - 1};
 
-    for (int n = t; n < 4 * T3; n += WG) tile[n] = 0;
+    // LDS tile: per node two 64-bit sums, (m, p_x) and (p_y, p_z), each the
+    // exact sum of 32-bit fixed-point terms packed as hi * 2^32 + lo (an
+    // integer sum, so every half is recovered exactly while it fits in 32 bits)
+    long long *t64 = (long long *)tile;
+    for (int n = t; n < 2 * T3; n += WG) t64[n] = 0;
     // bound of this item's particles, left by the previous G2P (or the sort)
     const float bmax = a.L.ibound[it];
     if (it == a.L.scene_item_begin[s]) write_colliders_now(a, S);
@@ -470,7 +474,7 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
             for (int e = 0; e < 3; e++) Ad[c][e] = kk * A[3 * c + e] * K.dx;
             r0[c] = kk * K.mass * v[c] - (Ad[c][0] * f[0] + Ad[c][1] * f[1] + Ad[c][2] * f[2]);
         }
-        int *tb = tile + ((bp[0] - org[0]) * T + (bp[1] - org[1])) * T + (bp[2] - org[2]);
+        long long *tb = t64 + ((bp[0] - org[0]) * T + (bp[1] - org[1])) * T + (bp[2] - org[2]);
 #pragma unroll
         for (int ox = 0; ox < 3; ox++)
 #pragma unroll
@@ -483,17 +487,21 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
                 for (int oz = 0; oz < 3; oz++) {
                     float w = wxy * wz[oz];
                     int o = (ox * T + oy) * T + oz;
-                    atomicAdd(tb + o, cvt_rpi(w));
-#pragma unroll
-                    for (int c = 0; c < 3; c++)
-                        atomicAdd(tb + (c + 1) * T3 + o, cvt_rpi(w * (rxy[c] + (float)oz * Ad[c][2])));
+                    const int q0 = cvt_rpi(w);
+                    const int q1 = cvt_rpi(w * (rxy[0] + (float)oz * Ad[0][2]));
+                    const int q2 = cvt_rpi(w * (rxy[1] + (float)oz * Ad[1][2]));
+                    const int q3 = cvt_rpi(w * (rxy[2] + (float)oz * Ad[2][2]));
+                    atomicAdd((unsigned long long *)(tb + o), pack2(q0, q1));
+                    atomicAdd((unsigned long long *)(tb + T3 + o), pack2(q2, q3));
                 }
             }
     }
     __syncthreads();
     const float im = 1.0f / Sm, ip = 1.0f / Sp;
     for (int n = t; n < T3; n += WG) {
-        int m0 = tile[n], p0 = tile[T3 + n], p1 = tile[2 * T3 + n], p2 = tile[3 * T3 + n];
+        int m0, p0, p1, p2;
+        unpack2(t64[n], m0, p0);
+        unpack2(t64[T3 + n], p1, p2);
         if ((m0 | p0 | p1 | p2) == 0) continue;
         int tx = n / (T * T), ty = (n / T) % T, tz = n % T;
         int gi = org[0] + tx, gj = org[1] + ty, gk = org[2] + tz;
@@ -515,7 +523,7 @@ template <int B>
 __global__ __launch_bounds__(WG) void k_p2g(StepArgs a)
 {
     constexpr int T = B + 4, T3 = T * T * T;
-    __shared__ int tile[4 * T3];
+    __shared__ __align__(16) int tile[4 * T3];
     const int n_items = *a.L.n_items;
     const int G = active_wgs(n_items);
     if ((int)blockIdx.x >= G) return;
@@ -527,12 +535,14 @@ __global__ __launch_bounds__(WG) void k_p2g(StepArgs a)
 }
 
 // ---------------------------------------------------------------- grid update
-template <int B>
 // cl: this wave's LDS copy of the scene's colliders (at most
 // MAX_COLLIDERS_PER_SCENE).
 // The node loop stores to the grid; reading the colliders and the scene
 // constants from LDS and registers keeps the compiler from reloading them
 // from global memory (and waiting for the stores) on every node.
+// EXTRA = false: a plain substep (no capture, no surrogate arrays), built
+// without that code so that it keeps its registers and occupancy.
+template <int B, bool EXTRA = true>
 __device__ void grid_block(const StepArgs &a, int s, int lb, int lane, ColliderNow *cl)
 {
     const SceneDev &S = a.scenes[s];
@@ -558,7 +568,7 @@ __device__ void grid_block(const StepArgs &a, int s, int lb, int lane, ColliderN
         float m = a.gm[idx], px = a.gpx[idx], py = a.gpy[idx], pz = a.gpz[idx];
         if (m == 0.0f && px == 0.0f && py == 0.0f && pz == 0.0f) continue;
         int ii[3] = {bx * B + l / (B * B), by * B + (l / B) % B, bz * B + l % B};
-        if (a.cap) {
+        if (EXTRA && a.cap) {
             long long c = a.cap_off[s] + ((long long)ii[0] * K.res + ii[1]) * K.res + ii[2];
             a.cap[4 * c] = m;
             a.cap[4 * c + 1] = px;
@@ -578,9 +588,9 @@ __device__ void grid_block(const StepArgs &a, int s, int lb, int lane, ColliderN
             if (ii[d] < bound && v[d] < 0.0f) v[d] = 0.0f;
             if (ii[d] >= K.res - bound && v[d] > 0.0f) v[d] = 0.0f;
         }
-        const long long c = a.dense ? sur_index(a, s, K.res, ii[0], ii[1], ii[2]) : -1;
-        if (a.dense && c < 0 && a.out_mass && m > 0.0f) atomicAdd(a.out_mass + s, m);   // outside the box
-        if (c >= 0) {   // (m, p / m) of the P2G, before gravity, colliders and walls
+        const long long c = EXTRA && a.dense ? sur_index(a, s, K.res, ii[0], ii[1], ii[2]) : -1;
+        if (EXTRA && a.dense && c < 0 && a.out_mass && m > 0.0f) atomicAdd(a.out_mass + s, m);   // outside the box
+        if (EXTRA && c >= 0) {   // (m, p / m) of the P2G, before gravity, colliders and walls
             const float im = m > 0.0f ? 1.0f / m : 0.0f;
             *(float4 *)(a.dense + 4 * c) = make_float4(m, px * im, py * im, pz * im);
             if (a.feat) {
@@ -603,7 +613,7 @@ __device__ void grid_block(const StepArgs &a, int s, int lb, int lane, ColliderN
     if (lane == 0) *tf = 0;
 }
 
-template <int B>
+template <int B, bool EXTRA>
 __global__ __launch_bounds__(WG) void k_grid(StepArgs a)
 {
     const int lane = threadIdx.x & 63;
@@ -616,7 +626,7 @@ __global__ __launch_bounds__(WG) void k_grid(StepArgs a)
     const int w0 = xcd_remap(blockIdx.x, G) * (WG / 64) + (threadIdx.x >> 6);
     for (int w = w0; w < ng + no; w += nw) {
         int2 e = w < ng ? a.L.gitems[w] : a.L.ovf[w - ng];
-        grid_block<B>(a, e.x, e.y, lane, cls[threadIdx.x >> 6]);
+        grid_block<B, EXTRA>(a, e.x, e.y, lane, cls[threadIdx.x >> 6]);
         if (w >= ng && lane == 0) a.L.bflag[a.scenes[e.x].bin_off + e.y] = 0;
     }
 }
@@ -798,8 +808,14 @@ hipError_t launch_p2g(const StepArgs &a, int chunk, int n_wg, hipStream_t st)
 hipError_t launch_grid(const StepArgs &a, int n_wg, hipStream_t st)
 {
     n_wg = (n_wg + 7) & ~7;
-    if (a.B == 4) k_grid<4><<<n_wg, WG, 0, st>>>(a);
-    else k_grid<8><<<n_wg, WG, 0, st>>>(a);
+    const bool extra = a.cap || a.dense;
+    if (a.B == 4) {
+        if (extra) k_grid<4, true><<<n_wg, WG, 0, st>>>(a);
+        else k_grid<4, false><<<n_wg, WG, 0, st>>>(a);
+    } else {
+        if (extra) k_grid<8, true><<<n_wg, WG, 0, st>>>(a);
+        else k_grid<8, false><<<n_wg, WG, 0, st>>>(a);
+    }
     return hipGetLastError();
 }
 
@@ -839,7 +855,7 @@ template <int B>
 __global__ __launch_bounds__(WG) void k_substep_persistent(StepArgs a)
 {
     constexpr int T = B + 4, T3 = T * T * T;
-    __shared__ int smem[4 * T3];
+    __shared__ __align__(16) int smem[4 * T3];
     __shared__ int s_q;
     __shared__ ColliderNow cls[WG / 64][MAX_COLLIDERS_PER_SCENE];
     const int n_items = *a.L.n_items;
