@@ -15,7 +15,9 @@
  * channels-last [n][d][h][w][c]; a call reads / writes the channel slice
  * [off, off + count) of a tensor whose channel stride is `c...`.  Channel
  * counts on the MFMA paths are multiples of 16 (<= 128 input channels for
- * weight gradients).  Weights are FP32 [taps][cin][cout] (taps = 27, 8 or 1,
+ * weight gradients); a 3^3 convolution may also take exactly 8 input
+ * channels (the network's first layer; channel stride and offset of its
+ * input multiples of 8).  Weights are FP32 [taps][cin][cout] (taps = 27, 8 or 1,
  * z-major, as [kd][kh][kw]).  Every call returns 0 on success, -1 on an
  * invalid argument (nothing queued), -2 on a HIP error.
  *
@@ -32,11 +34,14 @@
 extern "C" {
 #endif
 
-/* Pack FP32 weights into the BF16 fragment order of mpm_nn_conv.
+/* Pack FP32 weights into the BF16 fragment order of mpm_nn_conv (the
+ * order depends on kind and cin_eff: 16x16x16 or 16x16x32 fragments, or the
+ * first-layer order with the taps in K for kind 0 and cin = 8).
  * transpose = 0: weights of the layer; 1: weights of its adjoint (input
  * gradient) convolution, taps mirrored and channels swapped.  out holds
  * taps * ceil16(cin_eff) * ceil16(cout_eff) BF16 values, where (cin_eff,
- * cout_eff) = (cin, cout), or (cout, cin) when transposed. */
+ * cout_eff) = (cin, cout), or (cout, cin) when transposed (the first-layer
+ * order uses 224 * ceil16(cout) of them). */
 int mpm_nn_pack(const float *w, int kind, int cin, int cout, int transpose, uint16_t *out, void *stream);
 
 /* y = act(conv(x) + bias): input [n][id][ih][iw] slice (cx, x_off, cin),

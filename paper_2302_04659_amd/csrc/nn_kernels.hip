@@ -5,15 +5,19 @@
 // so skip concatenation costs nothing.  Channel counts used by the MFMA
 // paths are multiples of 16.
 //
-// Convolution = implicit GEMM on v_mfma_f32_16x16x16bf16_1k:
+// Convolution = implicit GEMM on the BF16 MFMAs:
 //   forward  D[voxel][co] = sum_{tap, ci} X[p(voxel, tap)][ci] W[tap][ci][co]
 //   dgrad    the same kernel on dY with flipped, transposed weights
 //   wgrad    D[ci][co] += sum_voxel X[p(voxel, tap)][ci] dY[voxel][co]
 // with tap geometries: 3^3 zero-padded ("c3"), 3^3 over a nearest x2
-// upsampled input ("up"), 2^3 stride 2 ("down") and 1^3 ("c1").
+// upsampled input ("up"), 2^3 stride 2 ("down") and 1^3 ("c1").  The 3^3
+// kinds with a multiple of 32 input channels, and the 3^3 first layer over 8
+// channels, run on v_mfma_f32_16x16x32_bf16 (gfx950, twice the rate of the
+// 16x16x16 form); the rest on v_mfma_f32_16x16x16bf16_1k.
 // Operand lane layout (wave64, 16x16x16): A[i][k] sits in lane i + 16 (k/4),
 // element k % 4; B[k][j] in lane j + 16 (k/4), element k % 4; D[i][j] in lane
-// j + 16 (i/4), element i % 4.
+// j + 16 (i/4), element i % 4.  16x16x32: A[i][k] in lane i + 16 (k/8),
+// element k % 8; B[k][j] in lane j + 16 (k/8), element k % 8; D as above.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

@@ -300,6 +300,50 @@ def test_advance_reproduces_linear_field(env, u):
     sim.close()
 
 
+def test_residual_matches_oracle_resplat(env, orc):
+    """The gate's residual (c22 reading) recomputed on the CPU: the oracle's
+    P2G of the particles the GPU advanced, against the start grid and the
+    prediction, r = max(sum|m_r - m_pred| / sum m, sum|p_r - m_pred v_end| /
+    max(sum m |v|, sum m |g| T)) over nodes with material before or after."""
+    torch, mpm = env
+    batch = _batch()
+    announce("surrogate residual vs oracle re-splat", len(batch))
+    S, R = len(batch), batch[0].res
+    ts = _new_stream(torch)
+    sim, = _state_sims(mpm, batch, ts, 1)
+    rng = np.random.default_rng(17)
+    pred_h = (0.05 * rng.normal(size=(S, R, R, R, 4))).astype(np.float32)
+    with torch.cuda.stream(ts):
+        feat = torch.zeros((S, R, R, R, 8), dtype=torch.float32, device="cuda")
+        grid0 = torch.zeros((S, R, R, R, 4), dtype=torch.float32, device="cuda")
+        pred = torch.tensor(pred_h, device="cuda")
+        residual = torch.zeros(S, dtype=torch.float32, device="cuda")
+        sim.sur_features(feat, grid0)
+        sim.sur_block(pred, grid0, threshold=1e-3, fallback=False, residual=residual)
+    torch.cuda.synchronize()
+    assert sim.sync() >= 0
+    g = grid0.cpu().numpy().astype(np.float64)
+    r_gpu = residual.cpu().numpy()
+    for s, sc in enumerate(batch):
+        x, v, C, F = sim.get_state(s)
+        o = orc.Oracle(sc, x=x, v=v, C=C, F=F)
+        o.set_colliders(sc.ctrl_poses[0], sc.ctrl_vels[0])
+        m_r, p_r = o.p2g()
+        mu = sc.rho * sc.dx ** 3 / 32.0
+        m0, v0 = g[s, ..., 0], g[s, ..., 1:4]
+        mp = m0 + pred_h[s, ..., 3].astype(np.float64) * mu
+        ve = v0 + pred_h[s, ..., 0:3].astype(np.float64) * VEL
+        on = (m0 > 0) | (m_r > 0)
+        sm = np.abs(m_r - mp)[on].sum()
+        sp = np.abs(p_r - mp[..., None] * ve)[on].sum()
+        T = 25 * sc.dt
+        pref = max((m0[..., None] * np.abs(v0)).sum(), m0.sum() * float(np.linalg.norm(sc.gravity)) * T)
+        r = max(sm / m0.sum(), sp / pref)
+        print("scene", s, "gpu", r_gpu[s], "oracle re-splat", r)
+        assert abs(r_gpu[s] - r) <= 1e-4 * r
+    sim.close()
+
+
 @pytest.mark.parametrize("graph", [0, 1])
 def test_residual_gate_falls_back_per_scene(env, orc, graph):
     """Scene 1 gets a wild prediction and falls back (plain substeps, oracle
