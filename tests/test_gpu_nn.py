@@ -140,6 +140,43 @@ def test_conv_forward(nn, case, relu, out32):
     assert np.all(untouched == 1.0)
 
 
+LARGE_CASES = [
+    # kind, n, input spatial, cin, cout: the box shape of the surrogate (thousands of 4x4x16 tiles,
+    # ragged x tiles), BF16 output through the LDS-transposed store
+    ("c3", 4, (40, 24, 40), 32, 32),
+    ("c3", 4, (40, 24, 40), 64, 32),
+    ("c3", 4, (40, 24, 40), 32, 64),
+    ("up", 4, (20, 12, 20), 64, 32),
+]
+
+
+@pytest.mark.parametrize("case", LARGE_CASES, ids=[f"{c[0]}-{c[3]}x{c[4]}" for c in LARGE_CASES])
+def test_conv_forward_large(nn, case):
+    import torch
+    kind, n, sp, cin, cout = case
+    announce("nn conv large", kind, n, sp, cin, cout)
+    rng = np.random.default_rng(40 + LARGE_CASES.index(case))
+    X = rng.normal(size=(n,) + sp + (cin,))
+    W = rng.normal(0, 1.0 / np.sqrt(27 * cin), size=(3, 3, 3, cin, cout))
+    Bv = rng.normal(size=cout) * 0.1
+    xq, wq = ou.bf16_round(X), ou.bf16_round(W)
+    ref = np.maximum(_ref_conv(kind, xq, wq, Bv.astype(np.float32).astype(np.float64)), 0.0)
+    bound = _ref_conv(kind, np.abs(xq), np.abs(wq), np.abs(Bv))
+    osp = _out_shape(kind, sp)
+    L, s = nn.nn_lib(), _stream()
+    x_d = _bf16_dev(X)
+    w_d = _f32_dev(W.reshape(27, cin, cout))
+    fw = torch.zeros(27 * cin * cout, dtype=torch.int16, device="cuda")
+    assert L.mpm_nn_pack(w_d.data_ptr(), nn.KIND[kind], cin, cout, 0, fw.data_ptr(), s) == 0
+    b_d = _f32_dev(Bv)
+    y = torch.zeros((n,) + osp + (cout,), dtype=torch.int16, device="cuda")
+    assert L.mpm_nn_conv(nn.KIND[kind], x_d.data_ptr(), n, sp[0], sp[1], sp[2], cin, 0, cin, fw.data_ptr(),
+                         b_d.data_ptr(), 1, y.data_ptr(), cout, 0, cout, None, 0, s) == 0
+    torch.cuda.synchronize()
+    got = _from_bf16(y)
+    assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * bound + 1e-30)
+
+
 DGRAD_CASES = [
     ("c3", 2, (5, 6, 7), 32, 32),
     ("c3", 1, (4, 4, 4), 128, 64),
