@@ -36,6 +36,12 @@ __device__ __forceinline__ unsigned long long pack2(int hi, int lo)
     return ((unsigned long long)(unsigned)hi << 32) + (unsigned long long)(long long)lo;
 }
 
+// The same for lo >= 0 (no borrow into hi): the two halves as they are.
+__device__ __forceinline__ unsigned long long pack2_nonneg_lo(int hi, int lo)
+{
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo;
+}
+
 __device__ __forceinline__ void unpack2(long long v, int &hi, int &lo)
 {
     lo = (int)(unsigned)(v & 0xffffffffLL);

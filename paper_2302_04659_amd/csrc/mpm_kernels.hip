@@ -419,9 +419,10 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
     const int bx = item.block / (nb * nb), by = (item.block / nb) % nb, bz = item.block % nb;
     const int org[3] = {bx * B - 1, by * B - 1, bz * B - 1};
 
-    // LDS tile: per node two 64-bit sums, (m, p_x) and (p_y, p_z), each the
-    // exact sum of 32-bit fixed-point terms packed as hi * 2^32 + lo (an
-    // integer sum, so every half is recovered exactly while it fits in 32 bits)
+    // LDS tile: per node two 64-bit sums, (p_x, m) and (p_y, p_z) as (hi, lo),
+    // each the exact sum of 32-bit fixed-point terms packed as hi * 2^32 + lo
+    // (an integer sum, so both halves are recovered exactly while they fit in
+    // 32 bits)
     long long *t64 = (long long *)tile;
     for (int n = t; n < 2 * T3; n += WG) t64[n] = 0;
     // bound of this item's particles, left by the previous G2P (or the sort)
@@ -475,6 +476,9 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
             r0[c] = kk * K.mass * v[c] - (Ad[c][0] * f[0] + Ad[c][1] * f[1] + Ad[c][2] * f[2]);
         }
         long long *tb = t64 + ((bp[0] - org[0]) * T + (bp[1] - org[1])) * T + (bp[2] - org[2]);
+        // r at offset (ox, oy, oz): r0 + ox Ad_x + oy Ad_y + oz Ad_z, one add per axis step
+        // (offset 0 adds nothing, 1 adds Ad, 2 adds 2 Ad)
+        auto step = [](float r, float d, int o) { return o == 0 ? r : (o == 1 ? r + d : fmaf(2.0f, d, r)); };
 #pragma unroll
         for (int ox = 0; ox < 3; ox++)
 #pragma unroll
@@ -482,16 +486,16 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
                 float wxy = wx[ox] * wy[oy];
                 float rxy[3];
 #pragma unroll
-                for (int c = 0; c < 3; c++) rxy[c] = r0[c] + (float)ox * Ad[c][0] + (float)oy * Ad[c][1];
+                for (int c = 0; c < 3; c++) rxy[c] = step(step(r0[c], Ad[c][0], ox), Ad[c][1], oy);
 #pragma unroll
                 for (int oz = 0; oz < 3; oz++) {
                     float w = wxy * wz[oz];
                     int o = (ox * T + oy) * T + oz;
-                    const int q0 = cvt_rpi(w);
-                    const int q1 = cvt_rpi(w * (rxy[0] + (float)oz * Ad[0][2]));
-                    const int q2 = cvt_rpi(w * (rxy[1] + (float)oz * Ad[1][2]));
-                    const int q3 = cvt_rpi(w * (rxy[2] + (float)oz * Ad[2][2]));
-                    atomicAdd((unsigned long long *)(tb + o), pack2(q0, q1));
+                    const int q0 = cvt_rpi(w);     // mass term, >= 0: the low half of its pair needs no sign fix
+                    const int q1 = cvt_rpi(w * step(rxy[0], Ad[0][2], oz));
+                    const int q2 = cvt_rpi(w * step(rxy[1], Ad[1][2], oz));
+                    const int q3 = cvt_rpi(w * step(rxy[2], Ad[2][2], oz));
+                    atomicAdd((unsigned long long *)(tb + o), pack2_nonneg_lo(q1, q0));
                     atomicAdd((unsigned long long *)(tb + T3 + o), pack2(q2, q3));
                 }
             }
@@ -500,7 +504,7 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
     const float im = 1.0f / Sm, ip = 1.0f / Sp;
     for (int n = t; n < T3; n += WG) {
         int m0, p0, p1, p2;
-        unpack2(t64[n], m0, p0);
+        unpack2(t64[n], p0, m0);
         unpack2(t64[T3 + n], p1, p2);
         if ((m0 | p0 | p1 | p2) == 0) continue;
         int tx = n / (T * T), ty = (n / T) % T, tz = n % T;
