@@ -10,6 +10,11 @@ and the per-scene stepping mask, through the C ABI.
     reproduces it exactly, so x, v, C and F follow in closed form);
   * residual gate: scenes over the threshold are put back and run the plain
     substeps (oracle bar); scenes under it are untouched by the fallback;
+    the residual itself equals the one recomputed from the oracle's P2G of
+    the advanced particles;
+  * per-scene boxes: the stencil box of the particles, features, start grid,
+    particle advance and residual on a box agree with the whole-grid calls;
+    mass outside a box that cuts the material counts in the residual;
   * training targets: the definition on seeded arrays.
 """
 import dataclasses
