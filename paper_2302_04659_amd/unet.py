@@ -242,7 +242,9 @@ class UNet:
             vox = x.n * x.d * x.h * x.w // 8
         else:
             vox = x.vox
-        chunk = 8192
+        # voxels per partial sum: about 256 partials per layer, so that even a small batch gives the
+        # weight-gradient kernel enough workgroups (its grid is partials x input-channel groups x 4)
+        chunk = min(8192, max(256, (vox // 256 + 15) // 16 * 16))
         nchunk = (vox + chunk - 1) // chunk
         need = nchunk * TAPS[kind] * cin * co
         if self._partial is None or self._partial.numel() < need:
