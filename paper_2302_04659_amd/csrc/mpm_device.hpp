@@ -57,15 +57,55 @@ __device__ __forceinline__ int cvt_rpi(float x)
 
 // Particle component c of slot j: base pointer per component (uniform) plus a
 // 32-bit byte offset, so loads and stores use scalar-base addressing.
+typedef __attribute__((address_space(1))) char gchar;
+
+__device__ __forceinline__ gchar *sgpr_base(const float *p)
+{
+    gchar *g = (gchar *)p;
+    asm("" : "+s"(g));
+    return g;
+}
+
 __device__ __forceinline__ float pload(const float *P, long long ps, int c, unsigned joff)
 {
-    return *(const float *)((const char *)(P + c * ps) + joff);
+    return *(const __attribute__((address_space(1))) float *)(sgpr_base(P + c * ps) + joff);
 }
 
 __device__ __forceinline__ void pstore(float *P, long long ps, int c, unsigned joff, float v)
 {
-    *(float *)((char *)(P + c * ps) + joff) = v;
+    *(__attribute__((address_space(1))) float *)(sgpr_base(P + c * ps) + joff) = v;
 }
+
+// G2P prefetch: the 12 state components it reads (x, then G) of up to 64
+// consecutive particle slots, copied by the wave straight into its LDS
+// slice pw[c * 64 + lane] (global_load_lds: no registers held while in flight).
+constexpr int PF_COMPS = 12;
+
+// One float per lane from global src into LDS at dst_wave + lane (dst_wave is
+// the wave's LDS base, the same on every lane).
+__device__ __forceinline__ void lds_copy(const float *src, float *dst_wave)
+{
+    typedef __attribute__((address_space(3))) void lds_void;
+    typedef const __attribute__((address_space(1))) void glob_void;
+    __builtin_amdgcn_global_load_lds((glob_void *)src, (lds_void *)dst_wave, 4, 0, 0);
+}
+
+__device__ __forceinline__ void pf_issue(const float *P, long long ps, int first, int n_left, int lane, float *pw)
+{
+    if (lane >= n_left) return;
+    const unsigned jo = (unsigned)(first + lane) << 2;
+    typedef __attribute__((address_space(3))) void lds_void;
+    typedef const __attribute__((address_space(1))) void glob_void;
+#pragma unroll
+    for (int c = 0; c < PF_COMPS; c++) {
+        const int comp = c < 3 ? X0 + c : G00 + (c - 3);
+        __builtin_amdgcn_global_load_lds((glob_void *)(sgpr_base(P + comp * ps) + jo), (lds_void *)(pw + c * 64), 4, 0, 0);
+    }
+}
+
+// Waits the compiler does not insert for LDS written by global_load_lds.
+__device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void wait_lds() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 __device__ __forceinline__ long long node_index(const SceneDev &S, int B, int i, int j, int k)
 {
@@ -118,6 +158,12 @@ struct SceneK {
 };
 
 __device__ __forceinline__ float uniform_f(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uniform_ll(long long v)
+{
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v), hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
 
 __device__ __forceinline__ SceneK scene_k(const SceneDev &S)
 {

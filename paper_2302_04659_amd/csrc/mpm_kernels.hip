@@ -531,7 +531,10 @@ __global__ __launch_bounds__(WG) void k_p2g(StepArgs a)
     const int n_items = *a.L.n_items;
     const int G = active_wgs(n_items);
     if ((int)blockIdx.x >= G) return;
-    for (int it = xcd_remap(blockIdx.x, G); it < n_items; it += G) {
+    // items in reverse order: G2P walks them forward, so the particles it wrote last
+    // are still in the memory-side cache when P2G starts on them
+    for (int r = xcd_remap(blockIdx.x, G); r < n_items; r += G) {
+        const int it = n_items - 1 - r;
         Item item = a.L.items[it];
         if (!a.active[item.scene]) continue;
         p2g_item<B>(a, it, item, tile);
@@ -636,8 +639,8 @@ __global__ __launch_bounds__(WG) void k_grid(StepArgs a)
 }
 
 // ---------------------------------------------------------------- G2P + integration
-template <int B>
-__device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt)
+template <int B, bool PF>
+__device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt, float *pf)
 {
     constexpr int T = B + 4, T3 = T * T * T;
     const int t = threadIdx.x;
@@ -646,32 +649,77 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt)
     const int nb = S.nb;
     const int bx = item.block / (nb * nb), by = (item.block / nb) % nb, bz = item.block % nb;
     const int org[3] = {bx * B - 1, by * B - 1, bz * B - 1};
-    for (int n = t; n < T3; n += WG) {
-        int gi = org[0] + n / (T * T), gj = org[1] + (n / T) % T, gk = org[2] + n % T;
-        float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
-        if (gi >= 0 && gj >= 0 && gk >= 0 && gi < S.res && gj < S.res && gk < S.res) {
-            long long idx = node_index(S, B, gi, gj, gk);
-            v0 = a.gvx[idx];
-            v1 = a.gvy[idx];
-            v2 = a.gvz[idx];
-        }
-        vt[n] = v0;
-        vt[T3 + n] = v1;
-        vt[2 * T3 + n] = v2;
-    }
-    __syncthreads();
+    const long long ps = a.pstride;
+    const int lane = t & 63;
+    float *pw = PF ? pf + uniform_i(t >> 6) * (PF_COMPS * 64) : nullptr;
+    // scene constants in registers before any copy into LDS (the copies may alias memory for
+    // the compiler, which would reload them after each one)
     const Material mat = material_of(S);
     const SceneK K = scene_k(S);
-    const long long ps = a.pstride;
+    if (PF) {
+        const int res = uniform_i(S.res);
+        const SceneDev Sg = {0, 0, res, uniform_i(S.nb), uniform_ll(S.grid_off)};
+        // the wave's first 64 particles: x and G copied into LDS while the tile is staged
+        pf_issue(a.P, ps, item.start + (t - lane), item.count - (t - lane), lane, pw);
+        // tile nodes copied straight into LDS, all in flight at once; nodes outside the grid are zeroed
+        for (int n0 = t - lane; n0 < T3; n0 += WG) {
+            const int n = n0 + lane;
+            if (n >= T3) break;
+            int gi = org[0] + n / (T * T), gj = org[1] + (n / T) % T, gk = org[2] + n % T;
+            if (gi >= 0 && gj >= 0 && gk >= 0 && gi < res && gj < res && gk < res) {
+                long long idx = node_index(Sg, B, gi, gj, gk);
+                lds_copy(a.gvx + idx, vt + n0);
+                lds_copy(a.gvy + idx, vt + T3 + n0);
+                lds_copy(a.gvz + idx, vt + 2 * T3 + n0);
+            } else {
+                vt[n] = 0.0f;
+                vt[T3 + n] = 0.0f;
+                vt[2 * T3 + n] = 0.0f;
+            }
+        }
+        wait_vmem();
+    } else {
+        for (int n = t; n < T3; n += WG) {
+            int gi = org[0] + n / (T * T), gj = org[1] + (n / T) % T, gk = org[2] + n % T;
+            float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
+            if (gi >= 0 && gj >= 0 && gk >= 0 && gi < S.res && gj < S.res && gk < S.res) {
+                long long idx = node_index(S, B, gi, gj, gk);
+                v0 = a.gvx[idx];
+                v1 = a.gvy[idx];
+                v2 = a.gvz[idx];
+            }
+            vt[n] = v0;
+            vt[T3 + n] = v1;
+            vt[2 * T3 + n] = v2;
+        }
+    }
+    __syncthreads();
     int bad_any = 0, cl_any = 0;
     float bnd = 0.0f;
-    for (int li = t; li < item.count; li += WG) {
+    // wave-uniform loop: lane li = k0 + lane of each 64-particle batch
+    for (int k0 = t - lane; k0 < item.count; k0 += WG) {
+        const int li = k0 + lane;
         const unsigned jo = (unsigned)(item.start + li) << 2;
         float x[3], G[9];
+        if (PF) {
 #pragma unroll
-        for (int d = 0; d < 3; d++) x[d] = pload(a.P, ps, X0 + d, jo);
+            for (int d = 0; d < 3; d++) x[d] = pw[d * 64 + lane];
 #pragma unroll
-        for (int e = 0; e < 9; e++) G[e] = pload(a.P, ps, G00 + e, jo);
+            for (int e = 0; e < 9; e++) G[e] = pw[(3 + e) * 64 + lane];
+            wait_lds();
+            // the next batch streams into LDS while this one computes
+            pf_issue(a.P, ps, item.start + k0 + WG, item.count - (k0 + WG), lane, pw);
+        }
+        if (li >= item.count) {
+            if (PF) wait_vmem();
+            continue;
+        }
+        if (!PF) {
+#pragma unroll
+            for (int d = 0; d < 3; d++) x[d] = pload(a.P, ps, X0 + d, jo);
+#pragma unroll
+            for (int e = 0; e < 9; e++) G[e] = pload(a.P, ps, G00 + e, jo);
+        }
         int b[3], cl = 0, in = 1;
         float f[3];
 #pragma unroll
@@ -763,6 +811,9 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt)
         }
         bad |= !(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]));
         bad_any |= bad;
+        // the prefetch has had the whole computation to land; waiting here (not at
+        // the top of the next batch) keeps the wait off this batch's stores
+        if (PF) wait_vmem();
 #pragma unroll
         for (int d = 0; d < 3; d++) {
             pstore(a.P, ps, X0 + d, jo, x[d]);
@@ -789,6 +840,7 @@ __global__ __launch_bounds__(WG, 4) void k_g2p(StepArgs a)
 {
     constexpr int T = B + 4, T3 = T * T * T;
     __shared__ float vt[3 * T3];
+    __shared__ float pf[(WG / 64) * PF_COMPS * 64];
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(a.L.n_ovf, 0);   // grid update has consumed the list
     const int n_items = *a.L.n_items;
     const int G = active_wgs(n_items);
@@ -796,7 +848,7 @@ __global__ __launch_bounds__(WG, 4) void k_g2p(StepArgs a)
     for (int it = xcd_remap(blockIdx.x, G); it < n_items; it += G) {
         Item item = a.L.items[it];
         if (!a.active[item.scene]) continue;
-        g2p_item<B>(a, it, item, vt);
+        g2p_item<B, true>(a, it, item, vt, pf);
     }
 }
 
@@ -916,7 +968,7 @@ __global__ __launch_bounds__(WG) void k_substep_persistent(StepArgs a)
             if (threadIdx.x == 0)
                 wait_counter(&grid_done[s], a.L.scene_gitem_begin[s + 1] - a.L.scene_gitem_begin[s] + 1, a.flags + s);
             __syncthreads();
-            g2p_item<B>(a, qi, item, (float *)smem);
+            g2p_item<B, false>(a, qi, item, (float *)smem, nullptr);
         }
     }
     if (threadIdx.x == 0) {
