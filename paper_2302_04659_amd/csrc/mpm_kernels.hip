@@ -408,6 +408,10 @@ __device__ void write_colliders_now(const StepArgs &a, const SceneDev &S)
     }
 }
 
+// Rounding by addition: RND = 1.5 * 2^23, whose float spacing is 1 for sums in [2^23, 2^24).
+constexpr float RND = 12582912.0f;
+constexpr unsigned long long RND_PAIR = 0x4B4000004B400000ull;   // RND's bits in both halves
+
 template <int B>
 __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
 {
@@ -432,9 +436,10 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
     if (t == 0 && !a.keep_bound) a.L.ibound[it] = 0.0f;   // this substep's G2P accumulates the next bound
 
     // Power-of-two fixed-point scales keeping every node sum below 2^30:
-    // |contribution| <= w * bound, w <= 0.421875, at most item.count particles.
+    // |contribution| <= w * bound, w <= 0.421875, at most item.count particles;
+    // and every single term within 2^22 (rounded by the RND addition below).
     const SceneK K = scene_k(S);
-    const float lim = 1073741824.0f / (0.421875f * (float)item.count);
+    const float lim = fminf(1073741824.0f / (0.421875f * (float)item.count), 4194304.0f / 0.421875f);
     int em = ilogbf(lim / K.mass);
     em = min(max(em, -120), 120);
     int ep = bmax > 0.0f ? ilogbf(lim / bmax) : 120;
@@ -491,12 +496,15 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
                 for (int oz = 0; oz < 3; oz++) {
                     float w = wxy * wz[oz];
                     int o = (ox * T + oy) * T + oz;
-                    const int q0 = cvt_rpi(w);     // mass term, >= 0: the low half of its pair needs no sign fix
-                    const int q1 = cvt_rpi(w * step(rxy[0], Ad[0][2], oz));
-                    const int q2 = cvt_rpi(w * step(rxy[1], Ad[1][2], oz));
-                    const int q3 = cvt_rpi(w * step(rxy[2], Ad[2][2], oz));
-                    atomicAdd((unsigned long long *)(tb + o), pack2_nonneg_lo(q1, q0));
-                    atomicAdd((unsigned long long *)(tb + T3 + o), pack2(q2, q3));
+                    // x + RND (|x| <= 2^22) holds round(x) in its low mantissa bits: bits = RND_BITS + round(x).
+                    // A pair of such bit patterns as hi * 2^32 + lo, minus RND_BITS * (2^32 + 1), is
+                    // round(x_hi) * 2^32 + round(x_lo) exactly (one 64-bit subtraction per pair).
+                    const unsigned b0 = __float_as_uint(fmaf(wxy, wz[oz], RND));   // mass term
+                    const unsigned b1 = __float_as_uint(fmaf(w, step(rxy[0], Ad[0][2], oz), RND));
+                    const unsigned b2 = __float_as_uint(fmaf(w, step(rxy[1], Ad[1][2], oz), RND));
+                    const unsigned b3 = __float_as_uint(fmaf(w, step(rxy[2], Ad[2][2], oz), RND));
+                    atomicAdd((unsigned long long *)(tb + o), ((unsigned long long)b1 << 32 | b0) - RND_PAIR);
+                    atomicAdd((unsigned long long *)(tb + T3 + o), ((unsigned long long)b2 << 32 | b3) - RND_PAIR);
                 }
             }
     }
