@@ -104,7 +104,9 @@ def main():
     ap.add_argument("--sort-every", type=int, default=0)
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the library defaults (block 4, chunk 2048, re-sort every 25) unless given")
-    ap.add_argument("--graph", type=int, default=-1)
+    ap.add_argument("--graph", type=int, default=1,
+                    help="1: replay each 25-substep control step from a captured hipGraph (the default "
+                         "production path), 0: launch every kernel from the host")
     ap.add_argument("--persistent", type=int, default=-1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-scenes", type=int, default=64)

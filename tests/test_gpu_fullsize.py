@@ -3,13 +3,15 @@ benchmark times (block, chunk and re-sort cadence the autotuner picks on
 the MI355X), against the FP64 oracle on what the oracle can afford:
 
   * cfg3, all 256 scenes (7.7 M particles) stepped together, one control
-    step (25 substeps) with block 8, chunk 8192: sampled scenes (the first,
+    step (25 substeps, replayed from a captured hipGraph as the benchmark
+    runs it) with block 8, chunk 8192: sampled scenes (the first,
     the last, the largest, the smallest) against the oracle run on each
     alone (the scenes are independent), 1e-3 dx; every scene's state stays
     finite and inside its grid;
   * cfg4, the 1,048,576-particle heap on a 128^3 grid with 3 colliders,
-    20 substeps with block 4, chunk 8192, re-sort every 10 (two sorts in
-    the run): every particle against the oracle, 1e-3 dx.
+    one control step (25 substeps, graph replay) with block 4, chunk 8192,
+    re-sort every 10 (three sorts in the run): every particle against the
+    oracle, 1e-3 dx.
 """
 import numpy as np
 import pytest
@@ -37,6 +39,7 @@ def test_cfg3_full_batch_sampled_scenes(mpm, orc):
     sim.set_option(mpm.OPT_BLOCK, 8)
     sim.set_option(mpm.OPT_CHUNK, 8192)
     sim.set_option(mpm.OPT_SORT_EVERY, 50)
+    sim.set_option(mpm.OPT_GRAPH, 1)
     sim.set_colliders_ctrl(0)
     sim.step(25)
     assert sim.sync() == mpm.OK
@@ -64,14 +67,15 @@ def test_cfg4_full_scene(mpm, orc):
     sim.set_option(mpm.OPT_BLOCK, 4)
     sim.set_option(mpm.OPT_CHUNK, 8192)
     sim.set_option(mpm.OPT_SORT_EVERY, 10)
+    sim.set_option(mpm.OPT_GRAPH, 1)
     sim.set_colliders_ctrl(0)
-    sim.step(20)
+    sim.step(25)
     assert sim.sync() == mpm.OK
     o = orc.Oracle(sc)
     o.set_colliders(sc.ctrl_poses[0], sc.ctrl_vels[0])
-    o.step(20)
+    o.step(25)
     x, v, C, F = sim.get_state(0)
     err = np.abs(x - o.x).max() / sc.dx
-    print("cfg4 max |dx| / dx after 20 substeps:", err, "rms", np.sqrt(((x - o.x) ** 2).sum(1).mean()) / sc.dx)
+    print("cfg4 max |dx| / dx after 25 substeps:", err, "rms", np.sqrt(((x - o.x) ** 2).sum(1).mean()) / sc.dx)
     assert err <= 1e-3
     sim.close()
