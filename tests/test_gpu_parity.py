@@ -155,6 +155,34 @@ def test_batched_equals_single(mpm, orc):
     sim.close()
 
 
+RAGGED_COUNTS = (1, 2, 63, 64, 65, 127, 129, 255, 257, 700)
+
+
+@pytest.mark.parametrize("block,chunk", [(4, 64), (8, 96)])
+@pytest.mark.parametrize("graph", [0, 1])
+def test_ragged_items_match_oracle(mpm, orc, block, chunk, graph):
+    """Work items of every awkward size: scenes of 1 to 700 particles, split
+    into chunks of 64 or 96, give items that end inside a wave, on a wave
+    boundary and inside a workgroup's last wave (the G2P batch loop, its LDS
+    prefetch of the next batch and the tile staging all see partial waves),
+    eager and graph-replayed, against the oracle after two control steps."""
+    batch = [scenes.small_scene(200 + k, n=n, res=16, model=k % 2, n_ctrl=2) for k, n in enumerate(RAGGED_COUNTS)]
+    announce("ragged items", "B", block, "chunk", chunk, "graph", graph, "counts", RAGGED_COUNTS)
+    sim = mpm.Sim(batch)
+    sim.set_option(mpm.OPT_BLOCK, block)
+    sim.set_option(mpm.OPT_CHUNK, chunk)
+    sim.set_option(mpm.OPT_GRAPH, graph)
+    sim.run_schedule(2)
+    assert sim.sync() == mpm.OK
+    for s, sc in enumerate(batch):
+        o = orc.Oracle(sc)
+        o.run_schedule(2)
+        x, _, _, _ = sim.get_state(s)
+        err = np.abs(x - o.x).max() / sc.dx
+        assert err <= 1e-3, (sc.n, err)
+    sim.close()
+
+
 @pytest.mark.parametrize("persistent", [0, 1])
 @pytest.mark.parametrize("block,chunk,sort_every", [(4, 1024, 25), (8, 512, 1), (8, 256, 25), (4, 256, 7)])
 def test_launch_modes_match_oracle(mpm, orc, persistent, block, chunk, sort_every):
