@@ -137,7 +137,10 @@ mpm_status mpm_get_particles(mpm_ctx ctx, int scene, float *x, float *v, float *
 /* Full particle state (checkpoint / teacher forcing): x, v [n][3]; affine
  * velocity C and deformation gradient F [n][3][3] of one scene or all
  * (scene = -1).  mpm_set_state replaces that state (all four arrays are
- * required) and re-sorts the particles. */
+ * required) and re-sorts the particles.  Host arrays with a non-finite x or
+ * v are refused (MPM_ERR_ARG); any other non-finite value (device arrays,
+ * C, F, or an F without a defined stress) is reported by the next
+ * mpm_sync as MPM_ERR_NONFINITE. */
 mpm_status mpm_get_state(mpm_ctx ctx, int scene, float *x, float *v, float *C, float *F, int on_device);
 mpm_status mpm_set_state(mpm_ctx ctx, int scene, const float *x, const float *v, const float *C,
                          const float *F, int on_device);

@@ -645,7 +645,7 @@ mpm_status create_impl(mpm_ctx ctx, const mpm_scene_desc *scenes, int n_scenes)
         if (d.v) HIPCHK(hipMemcpy(dv_, d.v, sizeof(float) * 3 * d.n_particles, hipMemcpyHostToDevice));
         HIPCHK(launch_init_particles(ctx->d_scenes, n_scenes, ctx->d_psc, ctx->d_P[ctx->cur], ctx->pstride, dx_,
                                      d.v ? dv_ : nullptr, nullptr, nullptr, ctx->h_scenes[s].p_begin,
-                                     ctx->h_scenes[s].p_end, ctx->stream));
+                                     ctx->h_scenes[s].p_end, ctx->d_flags, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
     }
     st = do_sort(ctx);
@@ -852,7 +852,7 @@ mpm_status mpm_set_state(mpm_ctx ctx, int scene, const float *x, const float *v,
     if ((st = to_device(ctx, dC_, C, 36 * n, on_device)) != MPM_OK) return st;
     if ((st = to_device(ctx, dF_, F, 36 * n, on_device)) != MPM_OK) return st;
     HIPCHK(launch_init_particles(ctx->d_scenes, ctx->n_scenes, ctx->d_psc, ctx->d_P[ctx->cur], ctx->pstride, dx_, dv_,
-                                 dC_, dF_, b, e, ctx->stream));
+                                 dC_, dF_, b, e, ctx->d_flags, ctx->stream));
     ctx->since_sort = 1 << 30;
     return MPM_OK;
 }

@@ -834,7 +834,10 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
             pstore(a.P, ps, A00 + e, jo, An[e]);
             pstore(a.P, ps, G00 + e, jo, Gn[e]);
         }
-        bnd = fmaxf(bnd, scatter_bound(K.mass, K.dx, vp, An));
+        // a non-finite v or A (the next P2G would scatter it as garbage fixed-point terms)
+        const float sb = scatter_bound(K.mass, K.dx, vp, An);
+        bad_any |= !(sb <= 3.0e38f);
+        bnd = fmaxf(bnd, sb);
     }
     bnd = wave_max(bnd);
     if ((t & 63) == 0 && bnd > 0.0f) atomicMax((int *)(a.L.ibound + it), __float_as_int(bnd));
@@ -1021,9 +1024,12 @@ hipError_t launch_collider_advance(ColliderDev *cols, int n_cols, const int *col
 }
 
 // ====================================================================== boundary conversions
+// A non-finite x, v, C or F (or an F whose stress is not defined) sets the
+// scene's FLAG_NONFINITE: inside a substep the fixed-point P2G would turn it
+// into finite garbage rather than propagate it.
 __global__ __launch_bounds__(WG) void k_init_particles(const SceneDev *scenes, const int *psc, float *P,
                                                        long long ps, const float *x, const float *v, const float *C,
-                                                       const float *F, int begin, int end)
+                                                       const float *F, int begin, int end, int *flags)
 {
     int i = begin + blockIdx.x * WG + threadIdx.x;
     if (i >= end) return;
@@ -1037,10 +1043,15 @@ __global__ __launch_bounds__(WG) void k_init_particles(const SceneDev *scenes, c
     }
     int bad = 0;
     stress_of(G, mat, tau, bad);
+    float chk = 0.0f;   // NaN or infinity in any input makes it fail the test below
     for (int d = 0; d < 3; d++) {
-        P[(X0 + d) * ps + i] = x[3 * (long long)k + d];
-        P[(V0 + d) * ps + i] = v ? v[3 * (long long)k + d] : 0.0f;
+        const float xv = x[3 * (long long)k + d], vv = v ? v[3 * (long long)k + d] : 0.0f;
+        chk += fabsf(xv) + fabsf(vv);
+        P[(X0 + d) * ps + i] = xv;
+        P[(V0 + d) * ps + i] = vv;
     }
+    for (int e = 0; e < 9; e++) chk += fabsf(G[e]) + fabsf(Cm[e]) + fabsf(tau[e]);
+    if (bad || !(chk <= 3.0e38f)) atomicOr(flags + psc[i], (int)FLAG_NONFINITE);
     for (int e = 0; e < 9; e++) {
         P[(A00 + e) * ps + i] = fmaf(S.mass, Cm[e], -S.kstress * tau[e]);
         P[(G00 + e) * ps + i] = G[e];
@@ -1050,10 +1061,11 @@ __global__ __launch_bounds__(WG) void k_init_particles(const SceneDev *scenes, c
 
 hipError_t launch_init_particles(const SceneDev *scenes, int n_scenes, const int *psc, float *P, long long pstride,
                                  const float *x, const float *v, const float *C, const float *F, int begin, int end,
-                                 hipStream_t st)
+                                 int *flags, hipStream_t st)
 {
     (void)n_scenes;
-    if (end > begin) k_init_particles<<<(end - begin + WG - 1) / WG, WG, 0, st>>>(scenes, psc, P, pstride, x, v, C, F, begin, end);
+    if (end > begin)
+        k_init_particles<<<(end - begin + WG - 1) / WG, WG, 0, st>>>(scenes, psc, P, pstride, x, v, C, F, begin, end, flags);
     return hipGetLastError();
 }
 

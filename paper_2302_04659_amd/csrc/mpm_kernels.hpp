@@ -68,7 +68,7 @@ hipError_t launch_collider_advance(ColliderDev *cols, int n_cols, const int *col
 // Boundary conversions (creation order <-> sorted SoA).
 hipError_t launch_init_particles(const SceneDev *scenes, int n_scenes, const int *psc, float *P, long long pstride,
                                  const float *x, const float *v, const float *C, const float *F, int begin, int end,
-                                 hipStream_t st);
+                                 int *flags, hipStream_t st);
 hipError_t launch_get_state(const SceneDev *scenes, const int *psc, const float *P, long long pstride, int begin,
                             int end, float *x, float *v, float *C, float *F, hipStream_t st);
 hipError_t launch_clear_f(float *p, long long n, hipStream_t st);

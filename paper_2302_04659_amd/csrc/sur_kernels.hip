@@ -288,7 +288,10 @@ __device__ void sur_advance_item(const StepArgs &a, int it, const Item &item, fl
             pstore(a.P, ps, A00 + e, jo, An[e]);
             pstore(a.P, ps, G00 + e, jo, Gn[e]);
         }
-        bnd = fmaxf(bnd, scatter_bound(K.mass, K.dx, ve, An));
+        // a non-finite v or A: flagged, so that the scene falls back
+        const float sb = scatter_bound(K.mass, K.dx, ve, An);
+        bad_any |= !(sb <= 3.0e38f);
+        bnd = fmaxf(bnd, sb);
     }
     bnd = wave_max(bnd);
     if ((t & 63) == 0 && bnd > 0.0f) atomicMax((int *)(a.L.ibound + it), __float_as_int(bnd));

@@ -220,6 +220,31 @@ def test_persistent_option_is_refused(mpm):
     sim.close()
 
 
+def test_nonfinite_state_is_reported(mpm):
+    """A non-finite state handed in is refused (host x / v: MPM_ERR_ARG) or
+    reported by the next sync (C, F: MPM_ERR_NONFINITE), and a clean state
+    clears the report; no substep runs on the broken state."""
+    sc = scenes.small_scene(300, n=500, res=16)
+    announce("non-finite state", sc.n)
+    sim = mpm.Sim([sc])
+    x, v, C, F = sim.get_state(-1)
+    bad_x = x.copy()
+    bad_x[11, 1] = np.nan
+    with pytest.raises(mpm.MPMError) as e:
+        sim.set_state(bad_x, v, C, F)
+    assert e.value.status == mpm.ERR_ARG
+    for which, val in (("C", np.nan), ("F", np.inf)):
+        C2, F2 = C.copy(), F.copy()
+        (C2 if which == "C" else F2)[7, 1, 2] = val
+        sim.set_state(x, v, C2, F2)
+        with pytest.raises(mpm.MPMError) as e:
+            sim.sync()
+        assert e.value.status == mpm.ERR_NONFINITE, which
+    sim.set_state(x, v, C, F)
+    assert sim.sync() == mpm.OK
+    sim.close()
+
+
 def test_graph_replays_match_eager(mpm, orc):
     """25-substep control steps replayed from captured hipGraphs (with eager
     work and host syncs between replays) match the eager path after every
