@@ -45,7 +45,7 @@ class SceneC(ct.Structure):
                 ("dx", ct.c_double), ("dt", ct.c_double), ("g", ct.c_double * 3), ("bound", ct.c_int),
                 ("model", ct.c_int), ("E", ct.c_double), ("nu", ct.c_double), ("rho", ct.c_double),
                 ("yield_stress", ct.c_double), ("yield_form", ct.c_int), ("p_vol", ct.c_double),
-                ("n_col", ct.c_int), ("col", ct.POINTER(Collider))]
+                ("n_col", ct.c_int), ("col", ct.POINTER(Collider)), ("wrench", ct.POINTER(ct.c_double))]
 
 
 _lib = None
@@ -95,7 +95,7 @@ class OracleError(RuntimeError):
 class Oracle:
     """One scene held in FP64.  State arrays are numpy views you may edit."""
 
-    def __init__(self, scene, x=None, v=None, C=None, F=None):
+    def __init__(self, scene, x=None, v=None, C=None, F=None, wrench: bool = False):
         n = scene.n
         self.scene = scene
         self.x = np.ascontiguousarray(scene.x if x is None else x, dtype=np.float64).reshape(n, 3).copy()
@@ -115,6 +115,9 @@ class Oracle:
             self.cols[k].half_length = c.half_length
             self.cols[k].friction = c.friction
             self.cols[k].quat[:] = [1.0, 0.0, 0.0, 0.0]
+        # impulse (3) and angular impulse about the centre (3) received by each
+        # collider, summed over the grid updates since the last take_wrench()
+        self.wrench = np.zeros((max(scene.n_colliders, 1), 6)) if wrench else None
         self.s = SceneC()
         self._bind()
 
@@ -130,6 +133,7 @@ class Oracle:
         s.p_vol = sc.particle_volume
         s.n_col = sc.n_colliders
         s.col = ct.cast(self.cols, ct.POINTER(Collider))
+        s.wrench = _dp(self.wrench) if self.wrench is not None else ct.POINTER(ct.c_double)()
 
     # -- colliders ---------------------------------------------------------
     def set_colliders(self, poses, vels):
@@ -140,6 +144,13 @@ class Oracle:
             self.cols[k].quat[:] = poses[k, 3:].tolist()
             self.cols[k].vlin[:] = vels[k, :3].tolist()
             self.cols[k].omega[:] = vels[k, 3:].tolist()
+
+    def take_wrench(self):
+        """[n_colliders][6]: impulse on each collider and angular impulse
+        about its centre since the last call (then zeroed)."""
+        w = self.wrench[: self.scene.n_colliders].copy()
+        self.wrench[:] = 0.0
+        return w
 
     def collider_poses(self):
         return np.array([list(c.pos) + list(c.quat) for c in self.cols[: self.scene.n_colliders]]).reshape(-1, 7)
@@ -196,6 +207,7 @@ def _scene_struct(scene):
     n = 1
     o.x = np.zeros((n, 3)); o.v = np.zeros((n, 3)); o.C = np.zeros((n, 3, 3)); o.F = np.zeros((n, 3, 3))
     o.cols = (Collider * 1)()
+    o.wrench = None
     o.s = SceneC()
     o._bind()
     return o

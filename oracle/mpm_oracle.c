@@ -72,6 +72,8 @@ typedef struct {
     double p_vol;
     int n_col;
     orc_collider *col;
+    double *wrench;           /* [n_col][6] or NULL: impulse on each collider and its
+                                 angular impulse about the collider centre, summed */
 } orc_scene;
 
 #define SIGMA_MIN 1e-6
@@ -428,11 +430,20 @@ int orc_p2g(const orc_scene *s, double *gm, double *gp)
     return err;
 }
 
-/* Grid velocity update: vg[res^3][3] from m, p. */
+/* Grid velocity update: vg[res^3][3] from m, p.
+ *
+ * Two-way coupling (Algorithm 1 accumulates the soft body's forces on the
+ * rigid bodies during the soft steps): with contact on grid nodes, what
+ * collider c exerts on the material in this substep is the momentum its
+ * projection adds at the nodes it touches, m_i (v_after - v_before); by
+ * Newton's third law the collider receives the opposite impulse, and the
+ * opposite angular impulse (x_i - c) x m_i (v_after - v_before) about its
+ * centre c at this substep's pose.  With s->wrench set they are summed into
+ * s->wrench (then the node loop runs serially, in node order). */
 void orc_grid_op(const orc_scene *s, const double *gm, const double *gp, double *vg)
 {
     int R = s->res;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (s->wrench == NULL)
     for (int i = 0; i < R; i++)
         for (int j = 0; j < R; j++)
             for (int k = 0; k < R; k++) {
@@ -441,7 +452,20 @@ void orc_grid_op(const orc_scene *s, const double *gm, const double *gp, double 
                 for (int a = 0; a < 3; a++) v[a] = gm[idx] > 0 ? gp[3 * idx + a] / gm[idx] : 0.0;
                 for (int a = 0; a < 3; a++) v[a] += s->dt * s->g[a];
                 double xi[3] = {i * s->dx, j * s->dx, k * s->dx};
-                for (int c = 0; c < s->n_col; c++) orc_collide(&s->col[c], xi, v);
+                for (int c = 0; c < s->n_col; c++) {
+                    double v0[3] = {v[0], v[1], v[2]};
+                    if (!orc_collide(&s->col[c], xi, v) || !s->wrench) continue;
+                    double dp[3], r[3], t[3];
+                    for (int a = 0; a < 3; a++) {
+                        dp[a] = gm[idx] * (v[a] - v0[a]);
+                        r[a] = xi[a] - s->col[c].pos[a];
+                    }
+                    cross3(r, dp, t);
+                    for (int a = 0; a < 3; a++) {
+                        s->wrench[6 * c + a] -= dp[a];
+                        s->wrench[6 * c + 3 + a] -= t[a];
+                    }
+                }
                 int ii[3] = {i, j, k};
                 for (int a = 0; a < 3; a++) {
                     if (ii[a] < s->bound && v[a] < 0) v[a] = 0;

@@ -157,6 +157,53 @@ def test_substep_conserves_momenta(orc, model):
     assert np.allclose(L1, L0, rtol=0, atol=1e-12 * scale)
 
 
+@pytest.mark.parametrize("model", [scenes.NEO_HOOKEAN, scenes.HENCKY_VM])
+def test_collider_wrench_is_what_the_material_receives(orc, model):
+    """Two-way coupling (Algorithm 1 accumulates the soft body's forces on
+    the rigid bodies), pinned by Newton's third law: with gravity off and
+    the walls out of reach, only the colliders change the material's
+    momenta, so over every substep the material's change of linear and
+    angular momentum (the APIC form, C included) equals minus the impulse
+    and minus the angular impulse about the origin that the colliders
+    receive (their angular impulse about their own centre plus c x J, at
+    the substep's pose).  Moving, rotating box and capsule."""
+    sc = replace(scenes.small_scene(7, n=400, res=16, model=model, speed=0.8, omega=3.0, n_ctrl=1, dt=2e-4),
+                 gravity=(0.0, 0.0, 0.0))
+    o = orc.Oracle(sc, wrench=True)
+    o.set_colliders(sc.ctrl_poses[0], sc.ctrl_vels[0])
+    m = sc.rho * sc.particle_volume
+
+    def momenta():
+        skew = o.C - np.transpose(o.C, (0, 2, 1))
+        vec = np.stack([skew[:, 2, 1], skew[:, 0, 2], skew[:, 1, 0]], -1)
+        return m * o.v.sum(0), (m * (np.cross(o.x, o.v) + sc.dx ** 2 / 4 * vec)).sum(0)
+
+    touched = 0.0
+    for _ in range(30):
+        P0, L0 = momenta()
+        c = o.collider_poses()[:, :3].copy()
+        o.step(1)
+        w = o.take_wrench()
+        P1, L1 = momenta()
+        J, T = w[:, :3], w[:, 3:]
+        scale = m * (np.abs(o.v).sum() + 1.0)
+        assert np.allclose(P1 - P0, -J.sum(0), rtol=0, atol=1e-11 * scale)
+        assert np.allclose(L1 - L0, -(T + np.cross(c, J)).sum(0), rtol=0, atol=1e-11 * scale)
+        touched += np.abs(J).sum()
+    assert touched > 1e-3 * m * sc.n, "the colliders never touched the material"
+
+
+def test_collider_wrench_zero_without_contact(orc):
+    """Colliders away from the material receive nothing (exactly)."""
+    sc = scenes.small_scene(8, n=300, res=16, n_ctrl=1, dt=2e-4)
+    o = orc.Oracle(sc, wrench=True)
+    poses = np.array(sc.ctrl_poses[0], np.float64).reshape(-1, 7).copy()
+    poses[:, :3] = [0.9, 0.9, 0.9]
+    o.set_colliders(poses, np.zeros((sc.n_colliders, 6)))
+    o.step(5)
+    assert not o.take_wrench().any()
+
+
 def test_affine_field_reproduction(orc):
     """v = v0 + M x, C = M, F = I, no forces: the grid holds v0 + M x_i and
     G2P returns (v0 + M x_p, M) exactly."""
