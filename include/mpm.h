@@ -11,6 +11,8 @@
  *     integrate (Algorithm 1, inner loop)                             -> mpm_step
  *   - hand particle positions to the consumer, ideally by one device-to-device
  *     copy (App. C.2)                                                  -> mpm_get_particles
+ *   - read out the forces the soft body exerts on the rigid bodies
+ *     (Algorithm 1 accumulates them for the rigid step)               -> mpm_get_collider_wrenches
  * The method of a substep is MLS-MPM with APIC transfers and quadratic
  * B-splines (Sec. 3 names MLS-MPM); colliders are analytic box / capsule
  * SDFs applied on grid nodes (Sec. 3: the grid-node variant the simulator
@@ -119,6 +121,23 @@ mpm_status mpm_destroy(mpm_ctx ctx);
  * calls each collider moves kinematically: substep k of a call uses
  * c + k dt v and exp(k dt w / 2) (x) q, the start-of-substep pose. */
 mpm_status mpm_set_colliders(mpm_ctx ctx, const float *poses, const float *velocities, int on_device);
+
+/* Two-way coupling read-out (Algorithm 1 accumulates the soft body's forces
+ * on the rigid bodies over the soft steps and applies them in the rigid
+ * step).  With contact on grid nodes, the impulse collider k receives in a
+ * substep is minus the momentum its projection gives the material,
+ * -sum_i m_i (v_i after - v_i before) over the nodes it touches, and its
+ * angular impulse about its own centre (at that substep's pose) is
+ * -sum_i (x_i - c_k) x m_i (v_i after - v_i before).  out
+ * [n_scenes][max_colliders][6] = impulse xyz (N s), angular impulse xyz
+ * (N m s), summed over every substep since the previous call (or since
+ * mpm_create); entries past a scene's own collider count are zero.  Divide
+ * by the elapsed time (substeps x dt) for the mean force and torque.  The
+ * call resets the sums.  Only plain substeps contribute (a control step the
+ * surrogate takes adds nothing; its fallback substeps do); mpm_autotune
+ * leaves the sums as they were.  The sums use floating-point atomics, so
+ * their last bits vary from run to run. */
+mpm_status mpm_get_collider_wrenches(mpm_ctx ctx, float *out, int on_device);
 
 /* Run n_substeps >= 0 substeps of every scene (Algorithm 1, inner loop).
  * Queued on the context stream; returns without waiting.  Warnings and

@@ -217,4 +217,27 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
+// Sum over the 64 lanes, returned on every lane (all lanes must be active).
+// An inclusive scan with DPP moves (VALU, no LDS round trip): shifts by 1, 2, 4
+// and 8 inside each row of 16 lanes (lanes shifted in from outside the row read
+// 0), then row 0's last lane added to row 1 and row 2's to row 3 (row_bcast:15),
+// then lane 31 added to rows 2 and 3 (row_bcast:31); lane 63 ends with the total.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float t)
+{
+    const int moved = __builtin_amdgcn_update_dpp(0, __float_as_int(t), CTRL, ROW_MASK, 0xf, true);
+    return t + __int_as_float(moved);
+}
+
+__device__ __forceinline__ float wave_total(float v)
+{
+    v = dpp_add<0x111, 0xf>(v);   // row_shr:1
+    v = dpp_add<0x112, 0xf>(v);   // row_shr:2
+    v = dpp_add<0x114, 0xf>(v);   // row_shr:4
+    v = dpp_add<0x118, 0xf>(v);   // row_shr:8
+    v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 }  // namespace mpm

@@ -93,6 +93,8 @@ struct mpm_ctx_s {
     // grid surrogate: re-splat grid and residual sums
     float *d_sur_gend = nullptr, *d_sur_acc = nullptr, *d_sur_out = nullptr;
     int *d_sur_nfb = nullptr;
+    float *d_wrench = nullptr;       // per collider: [6] impulse and angular impulse received, summed
+    float *d_wrench_out = nullptr;   // [n_scenes][max_col][6] staging for mpm_get_collider_wrenches
 
     // debug capture of the P2G grid
     int capture = 0;
@@ -360,6 +362,7 @@ StepArgs step_args(mpm_ctx ctx, int substep)
     a.feat = nullptr;
     a.cf = 0;
     a.keep_bound = 0;
+    a.wrench = ctx->d_wrench;
     return a;
 }
 
@@ -510,7 +513,8 @@ void release(mpm_ctx ctx)
                     ctx->d_tsum, ctx->d_dil, ctx->L.items, ctx->L.gitems, ctx->L.n_items, ctx->L.n_gitems,
                     ctx->L.scene_item_begin, ctx->L.scene_gitem_begin, ctx->L.bflag, ctx->L.ovf, ctx->L.n_ovf, ctx->L.ibound, ctx->L.touched,
                     ctx->d_flags, ctx->d_queue, ctx->d_scene_done, ctx->d_cap, ctx->d_cap_off, ctx->d_io,
-                    ctx->d_active, ctx->d_sur_gend, ctx->d_sur_acc, ctx->d_sur_out, ctx->d_sur_nfb};
+                    ctx->d_active, ctx->d_sur_gend, ctx->d_sur_acc, ctx->d_sur_out, ctx->d_sur_nfb,
+                    ctx->d_wrench, ctx->d_wrench_out};
     for (void *p : bufs)
         if (p) hipFree(p);
     for (int i = 0; i < STAGE_RING; i++) {
@@ -570,6 +574,8 @@ mpm_status create_impl(mpm_ctx ctx, const mpm_scene_desc *scenes, int n_scenes)
     HIPCHK(dalloc(&ctx->d_grid, (size_t)7 * nodes));
     HIPCHK(dalloc(&ctx->d_cols, ctx->h_cols.size()));
     HIPCHK(hipMalloc(&ctx->d_colnow, std::max<size_t>(ctx->h_cols.size(), 1) * 128));
+    HIPCHK(dalloc(&ctx->d_wrench, std::max<size_t>(ctx->h_cols.size(), 1) * 6));
+    HIPCHK(dalloc(&ctx->d_wrench_out, std::max<size_t>((size_t)n_scenes * ctx->max_col, 1) * 6));
     HIPCHK(dalloc(&ctx->d_col_scene, ctx->h_cols.size()));
     HIPCHK(dalloc(&ctx->d_scene_bin_off, n_scenes + 1));
     HIPCHK(dalloc(&ctx->d_keys, N));
@@ -622,6 +628,7 @@ mpm_status create_impl(mpm_ctx ctx, const mpm_scene_desc *scenes, int n_scenes)
     HIPCHK(hipMemsetAsync(ctx->d_flags, 0, sizeof(int) * n_scenes, ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->d_queue, 0, sizeof(int) * 4, ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->d_scene_done, 0, sizeof(int) * 3 * n_scenes, ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->d_wrench, 0, sizeof(float) * 6 * std::max<size_t>(ctx->h_cols.size(), 1), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->d_P[0], 0, sizeof(float) * NCOMP * ctx->pstride, ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->d_P[1], 0, sizeof(float) * NCOMP * ctx->pstride, ctx->stream));
     if (!ctx->h_cols.empty()) {
@@ -770,6 +777,17 @@ mpm_status mpm_set_colliders(mpm_ctx ctx, const float *poses, const float *veloc
                           hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipEventRecord(ctx->stage_ev[slot], ctx->stream));
     return MPM_OK;
+}
+
+mpm_status mpm_get_collider_wrenches(mpm_ctx ctx, float *out, int on_device)
+{
+    ARGCHK(ctx, "null context");
+    ARGCHK(out, "out must not be NULL");
+    hipSetDevice(ctx->dev);
+    const size_t n = (size_t)ctx->n_scenes * ctx->max_col * 6;
+    if (n == 0) return MPM_OK;
+    HIPCHK(launch_wrench_out(ctx->d_scenes, ctx->n_scenes, ctx->max_col, ctx->d_wrench, ctx->d_wrench_out, ctx->stream));
+    return from_device(ctx, out, ctx->d_wrench_out, sizeof(float) * n, on_device);
 }
 
 mpm_status mpm_step(mpm_ctx ctx, int n_substeps)
@@ -1054,6 +1072,7 @@ mpm_status mpm_sur_features(mpm_ctx ctx, float *feat, int cf, float *grid0, cons
     a.feat = feat;
     a.cf = cf;
     a.keep_bound = 1;   // the state does not change: its scatter bounds stay valid
+    a.wrench = nullptr;   // not a substep: no impulse on the colliders
     HIPCHK(launch_p2g(a, ctx->CH, substep_wgs(ctx), ctx->stream));
     HIPCHK(launch_grid(a, grid_wgs(ctx), ctx->stream));
     HIPCHK(launch_fill_i(ctx->L.n_ovf, 1, 0, ctx->stream));   // the overflow list has been consumed
@@ -1103,6 +1122,7 @@ mpm_status mpm_sur_block(mpm_ctx ctx, const float *pred, int cp, const float *gr
     r.out_mass = ctx->d_sur_out;
     a.out_mass = ctx->d_sur_out;   // read by the residual
     r.keep_bound = 1;   // bounds now cover both the start and the advanced state
+    r.wrench = nullptr;   // the re-splat is a check, not a substep
     HIPCHK(launch_p2g(r, ctx->CH, substep_wgs(ctx), ctx->stream));
     HIPCHK(launch_grid(r, grid_wgs(ctx), ctx->stream));
     HIPCHK(launch_fill_i(ctx->L.n_ovf, 1, 0, ctx->stream));
@@ -1193,6 +1213,10 @@ mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_l
         if (!ctx->h_cols.empty())
             HIPCHK(hipMemcpyAsync(csnap, ctx->d_cols, sizeof(ColliderDev) * ctx->h_cols.size(),
                                   hipMemcpyDeviceToDevice, ctx->stream));
+        // the trials' collider impulses are not the caller's: keep the accumulated wrenches
+        std::vector<float> wsnap(6 * std::max<size_t>(ctx->h_cols.size(), 1));
+        HIPCHK(hipMemcpyAsync(wsnap.data(), ctx->d_wrench, sizeof(float) * wsnap.size(), hipMemcpyDeviceToHost,
+                              ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
         const int saved[3] = {ctx->B, ctx->CH, ctx->sort_every};
         const int saved_timing = ctx->timing, saved_graph = ctx->graph;
@@ -1246,6 +1270,8 @@ mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_l
         if (!ctx->h_cols.empty())
             HIPCHK(hipMemcpyAsync(ctx->d_cols, csnap, sizeof(ColliderDev) * ctx->h_cols.size(),
                                   hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(ctx->d_wrench, wsnap.data(), sizeof(float) * wsnap.size(), hipMemcpyHostToDevice,
+                              ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
         (void)hipFree(snap);
         (void)hipFree(csnap);

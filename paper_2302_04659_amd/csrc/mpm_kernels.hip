@@ -578,12 +578,15 @@ __device__ void grid_block(const StepArgs &a, int s, int lb, int lane, ColliderN
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    // B^3 is a multiple of 64: every lane runs every iteration, so the wave sums of the
+    // collider wrenches below see all lanes (a lane on an empty node adds zero)
     for (int l = lane; l < B * B * B; l += 64) {
         long long idx = goff + (long long)lb * (B * B * B) + l;
         float m = a.gm[idx], px = a.gpx[idx], py = a.gpy[idx], pz = a.gpz[idx];
-        if (m == 0.0f && px == 0.0f && py == 0.0f && pz == 0.0f) continue;
+        const bool live = !(m == 0.0f && px == 0.0f && py == 0.0f && pz == 0.0f);
+        if (!__any(live)) continue;
         int ii[3] = {bx * B + l / (B * B), by * B + (l / B) % B, bz * B + l % B};
-        if (EXTRA && a.cap) {
+        if (EXTRA && a.cap && live) {
             long long c = a.cap_off[s] + ((long long)ii[0] * K.res + ii[1]) * K.res + ii[2];
             a.cap[4 * c] = m;
             a.cap[4 * c + 1] = px;
@@ -598,7 +601,30 @@ __device__ void grid_block(const StepArgs &a, int s, int lb, int lane, ColliderN
         }
         for (int d = 0; d < 3; d++) v[d] += gdt[d];
         float xi[3] = {ii[0] * K.dx, ii[1] * K.dx, ii[2] * K.dx};
-        for (int c = 0; c < n_col; c++) collide_node(cl[c], xi, v);
+        for (int c = 0; c < n_col; c++) {
+            const float v0[3] = {v[0], v[1], v[2]};
+            const bool hit = collide_node(cl[c], xi, v) && live && m > 0.0f;
+            // two-way coupling: the collider receives minus the momentum its projection gives
+            // the node, and minus its moment about the collider centre; one wave sum and one
+            // atomic per component, only where the wave touched this collider
+            if (a.wrench && __any(hit)) {
+                float dp[3], r[3];
+                for (int d = 0; d < 3; d++) {
+                    dp[d] = hit ? m * (v[d] - v0[d]) : 0.0f;
+                    r[d] = xi[d] - cl[c].c[d];
+                }
+                const float w6[6] = {dp[0], dp[1], dp[2], r[1] * dp[2] - r[2] * dp[1], r[2] * dp[0] - r[0] * dp[2],
+                                     r[0] * dp[1] - r[1] * dp[0]};
+                float *acc = a.wrench + 6 * (long long)(S.col_off + c);
+                float tot[6];
+#pragma unroll
+                for (int j = 0; j < 6; j++) tot[j] = wave_total(w6[j]);
+                if (lane == 0)
+#pragma unroll
+                    for (int j = 0; j < 6; j++) atomicAdd(acc + j, -tot[j]);
+            }
+        }
+        if (!live) continue;
         for (int d = 0; d < 3; d++) {
             if (ii[d] < bound && v[d] < 0.0f) v[d] = 0.0f;
             if (ii[d] >= K.res - bound && v[d] > 0.0f) v[d] = 0.0f;
@@ -1024,6 +1050,28 @@ hipError_t launch_collider_advance(ColliderDev *cols, int n_cols, const int *col
 }
 
 // ====================================================================== boundary conversions
+__global__ void k_wrench_out(const SceneDev *scenes, int n_scenes, int max_col, float *acc, float *out)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;   // (scene, slot, component)
+    if (e >= n_scenes * max_col * 6) return;
+    const int s = e / (max_col * 6), k = (e / 6) % max_col, j = e % 6;
+    const SceneDev &S = scenes[s];
+    float val = 0.0f;
+    if (k < S.n_col) {
+        float *p = acc + 6 * (long long)(S.col_off + k) + j;
+        val = *p;
+        *p = 0.0f;
+    }
+    out[e] = val;
+}
+
+hipError_t launch_wrench_out(const SceneDev *scenes, int n_scenes, int max_col, float *acc, float *out, hipStream_t st)
+{
+    const int n = n_scenes * max_col * 6;
+    if (n > 0) k_wrench_out<<<(n + 255) / 256, 256, 0, st>>>(scenes, n_scenes, max_col, acc, out);
+    return hipGetLastError();
+}
+
 // A non-finite x, v, C or F (or an F whose stress is not defined) sets the
 // scene's FLAG_NONFINITE: inside a substep the fixed-point P2G would turn it
 // into finite garbage rather than propagate it.

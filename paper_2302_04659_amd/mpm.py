@@ -64,6 +64,7 @@ def lib():
         L.mpm_create.argtypes = [ct.POINTER(SceneDesc), ct.c_int, vp, ct.POINTER(vp)]
         L.mpm_destroy.argtypes = [vp]
         L.mpm_set_colliders.argtypes = [vp, vp, vp, ct.c_int]
+        L.mpm_get_collider_wrenches.argtypes = [vp, vp, ct.c_int]
         L.mpm_step.argtypes = [vp, ct.c_int]
         L.mpm_sync.argtypes = [vp]
         L.mpm_get_particles.argtypes = [vp, ct.c_int, vp, vp, vp, ct.c_int]
@@ -192,6 +193,13 @@ class Sim:
         P = _f32(poses, (self.n_scenes, self.max_col, 7))
         V = _f32(vels, (self.n_scenes, self.max_col, 6))
         return self._check(self.L.mpm_set_colliders(self.h, P.ctypes.data, V.ctypes.data, 0), "set_colliders")
+
+    def collider_wrenches(self):
+        """[n_scenes][max_colliders][6]: impulse and angular impulse (about
+        each collider's centre) the colliders received since the last call."""
+        out = np.zeros((self.n_scenes, max(self.max_col, 1), 6), np.float32)
+        self._check(self.L.mpm_get_collider_wrenches(self.h, out.ctypes.data, 0), "get_collider_wrenches")
+        return out[:, : self.max_col]
 
     def set_colliders_ctrl(self, k: int):
         """Hand over every scene's poses / velocities of control step k."""
