@@ -32,6 +32,12 @@
  *     c <- c + dt v and q <- exp(dt w / 2) (x) q;
  *   - SVD: singular values sorted descending, U and V proper rotations, the
  *     last singular value negative when det F < 0; clamp at 1e-6 before ln.
+ *   - weakly compressible fluid (model 2, for the paper's pouring / filling
+ *     tasks; it prints no fluid law): Tait equation of state with exponent 7
+ *     and the bulk modulus K = lambda + 2 mu / 3 of (E, nu),
+ *     p(J) = (K / 7) (J^-7 - 1), Kirchhoff stress tau = -J p(J) I; after the
+ *     F update F is replaced by J^(1/3) I (the fluid keeps its volume change
+ *     and no shear).
  *   - a particle whose stencil leaves the grid is an error (return -2).
  *
  * Grid layout: node (i, j, k) sits at (i dx, j dx, k dx) and is stored at
@@ -66,7 +72,7 @@ typedef struct {
     double dx, dt;
     double g[3];
     int bound;
-    int model;                /* 0 neo-Hookean, 1 Hencky + von Mises */
+    int model;                /* 0 neo-Hookean, 1 Hencky + von Mises, 2 weakly compressible fluid */
     double E, nu, rho, yield_stress;
     int yield_form;
     double p_vol;
@@ -214,6 +220,13 @@ void orc_stress(const orc_scene *s, const double *F, double *tau)
 {
     double mu, la;
     lame(s, &mu, &la);
+    if (s->model == 2) {
+        double J = det3(F);
+        double K = la + 2.0 * mu / 3.0;
+        double p = K / 7.0 * (pow(J, -7.0) - 1.0);
+        for (int i = 0; i < 9; i++) tau[i] = i % 4 == 0 ? -J * p : 0.0;
+        return;
+    }
     if (s->model == 0) {
         double J = det3(F);
         double lnJ = log(J);
@@ -506,7 +519,12 @@ int orc_g2p(orc_scene *s, const double *vg)
         double M[9];
         for (int i = 0; i < 9; i++) M[i] = (i % 4 == 0 ? 1.0 : 0.0) + s->dt * C[i];
         matmul(M, F, F);
-        orc_return_map(s, F);
+        if (s->model == 2) {   /* fluid: only the volume change is kept */
+            double c = cbrt(det3(F));
+            for (int i = 0; i < 9; i++) F[i] = i % 4 == 0 ? c : 0.0;
+        } else {
+            orc_return_map(s, F);
+        }
     }
     return err;
 }

@@ -38,6 +38,7 @@ BOX = 0
 CAPSULE = 1
 NEO_HOOKEAN = 0
 HENCKY_VM = 1
+FLUID = 2          # weakly compressible fluid (Tait pressure, volume-only state)
 SUBSTEPS_PER_CTRL = 25
 
 

@@ -132,7 +132,7 @@ def test_p2g_conservation(orc, model):
 
 
 # ---------------------------------------------------------------- G2P and full substeps
-@pytest.mark.parametrize("model", [scenes.NEO_HOOKEAN, scenes.HENCKY_VM])
+@pytest.mark.parametrize("model", [scenes.NEO_HOOKEAN, scenes.HENCKY_VM, scenes.FLUID])
 def test_substep_conserves_momenta(orc, model):
     """No gravity, walls or colliders: a substep keeps P and L exactly."""
     n = 300
@@ -278,6 +278,45 @@ def test_neo_hookean_closed_forms(orc):
     R = Rotation.from_rotvec([0.3, -0.5, 0.8]).as_matrix()
     F = np.eye(3) + 0.2 * np.random.default_rng(1).normal(size=(3, 3))
     assert np.allclose(orc.stress(s, R @ F), R @ orc.stress(s, F) @ R.T, rtol=1e-12, atol=1e-9)
+
+
+def test_fluid_closed_forms(orc):
+    """Weakly compressible fluid: hydrostatic Kirchhoff stress -J p(J) I with
+    the Tait law p(J) = (K/7)(J^-7 - 1), K = lambda + 2 mu / 3; zero at rest;
+    blind to shear and rotation (it depends on det F only)."""
+    s = _scene(model=scenes.FLUID)
+    mu, la = _mu_la(s.E, s.nu)
+    K = la + 2.0 * mu / 3.0
+    assert np.abs(orc.stress(s, np.eye(3))).max() == 0.0
+    for J in (0.9, 0.999, 1.0005, 1.1):
+        p = K / 7.0 * (J ** -7 - 1.0)
+        tau = orc.stress(s, np.diag([J, 1.0, 1.0]))
+        assert np.allclose(tau, -J * p * np.eye(3), rtol=1e-13, atol=1e-12 * K), J
+        # a pure shear of the same determinant and a rotation change nothing
+        sh = np.array([[J, 0.3, 0.0], [0.0, 1.0, -0.2], [0.0, 0.0, 1.0]])
+        from scipy.spatial.transform import Rotation
+        R = Rotation.from_rotvec([0.4, 0.1, -0.7]).as_matrix()
+        assert np.allclose(orc.stress(s, R @ sh), tau, rtol=1e-12, atol=1e-12 * K), J
+    # compression (J < 1) pushes outward: positive pressure, negative tau
+    assert orc.stress(s, 0.95 ** (1 / 3) * np.eye(3))[0, 0] < 0.0
+
+
+def test_fluid_state_keeps_volume_only(orc):
+    """After a substep every fluid particle's F is J^(1/3) I, with J the
+    determinant of the updated F (I + dt C) F_old."""
+    n = 200
+    s = _scene(n=n, res=16, model=scenes.FLUID, seed=21, dt=2e-4)
+    rng = np.random.default_rng(22)
+    C = rng.normal(size=(n, 3, 3)) * 3
+    c0 = (1.0 + 0.01 * rng.normal(size=n)) ** (1 / 3)
+    F = c0[:, None, None] * np.eye(3)
+    o = orc.Oracle(s, C=C, F=F)
+    o.p2g()
+    o.grid_op()
+    o.g2p()
+    J_new = (np.eye(3)[None] + s.dt * o.C) @ F
+    J_new = np.linalg.det(J_new)
+    assert np.allclose(o.F, np.cbrt(J_new)[:, None, None] * np.eye(3), rtol=1e-13, atol=1e-15)
 
 
 def test_hencky_closed_forms(orc):
