@@ -62,7 +62,17 @@ typedef enum {
     MPM_ERR_STATE = -5        /* call not valid in the current state */
 } mpm_status;
 
-typedef enum { MPM_NEO_HOOKEAN = 0, MPM_HENCKY_VON_MISES = 1 } mpm_model;
+/* Materials (App. C.3 gives E, nu and the yield stress of the elastoplastic
+ * bodies; the liquid of the Pour task (Sec. 2.1 "Heterogeneous Task Families",
+ * and the soft-body task table of the appendix) has no printed law):
+ *   MPM_NEO_HOOKEAN           tau = mu (F F^T - I) + lambda ln(J) I
+ *   MPM_HENCKY_VON_MISES      Hencky elasticity, von Mises return map on the
+ *                             principal log strain (yield_stress, yield_form)
+ *   MPM_WEAKLY_COMPRESSIBLE_FLUID
+ *                             tau = -J p(J) I, p(J) = (K / 7) (J^-7 - 1),
+ *                             K = lambda + 2 mu / 3 from (E, nu); F is kept as
+ *                             J^(1/3) I (volume change only, no shear) */
+typedef enum { MPM_NEO_HOOKEAN = 0, MPM_HENCKY_VON_MISES = 1, MPM_WEAKLY_COMPRESSIBLE_FLUID = 2 } mpm_model;
 typedef enum { MPM_BOX = 0, MPM_CAPSULE = 1 } mpm_shape_type;
 
 typedef struct {

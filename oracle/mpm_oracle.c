@@ -32,8 +32,8 @@
  *     c <- c + dt v and q <- exp(dt w / 2) (x) q;
  *   - SVD: singular values sorted descending, U and V proper rotations, the
  *     last singular value negative when det F < 0; clamp at 1e-6 before ln.
- *   - weakly compressible fluid (model 2, for the paper's pouring / filling
- *     tasks; it prints no fluid law): Tait equation of state with exponent 7
+ *   - weakly compressible fluid (model 2, for the liquid of the Pour task,
+ *     Sec. 2.1; the paper prints no fluid law): Tait equation of state with exponent 7
  *     and the bulk modulus K = lambda + 2 mu / 3 of (E, nu),
  *     p(J) = (K / 7) (J^-7 - 1), Kirchhoff stress tau = -J p(J) I; after the
  *     F update F is replaced by J^(1/3) I (the fluid keeps its volume change

@@ -163,7 +163,7 @@ mpm_status validate_desc(mpm_ctx ctx, const mpm_scene_desc &d, int i)
     if (!(d.dt > 0) || !std::isfinite(d.dt)) return bad("dt must be > 0");
     if (d.bound < 0 || 2 * d.bound >= d.res) return bad("bound out of range");
     if (!(d.particle_volume > 0)) return bad("particle_volume must be > 0");
-    if (d.mat.model != 0 && d.mat.model != 1) return bad("unknown material model");
+    if (d.mat.model < 0 || d.mat.model > 2) return bad("unknown material model");
     if (!(d.mat.E > 0) || !(d.mat.nu > -1.0f && d.mat.nu < 0.5f) || !(d.mat.rho > 0)) return bad("bad material");
     if (d.mat.yield_form != 0 && d.mat.yield_form != 1) return bad("yield_form must be 0 or 1");
     if (d.n_colliders < 0 || d.n_colliders > MPM_MAX_COLLIDERS) return bad("n_colliders out of range");

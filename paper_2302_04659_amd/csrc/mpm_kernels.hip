@@ -840,6 +840,8 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
             tau_neo_hookean(Gt, mat.mu, mat.la, tau, bad);
 #pragma unroll
             for (int e = 0; e < 9; e++) Gn[e] = Gt[e];
+        } else if (mat.model == 2) {
+            fluid_update(Gt, mat, Gn, tau, bad);
         } else {
             hencky_update(Gt, mat, Gn, tau, bad);
         }

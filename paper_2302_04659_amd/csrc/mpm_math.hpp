@@ -345,11 +345,36 @@ MPM_HD int hencky_update(const float *Gt, const Material &mat, float *Gout, floa
     return yielded;
 }
 
+// Weakly compressible fluid: Tait pressure p(J) = (K / 7) (J^-7 - 1) with the
+// bulk modulus K = lambda + 2 mu / 3, Kirchhoff stress tau = -J p(J) I, and the
+// state reduced to J^(1/3) I (volume change only).  With L = ln J from
+// log1p(J - 1): J^(1/3) - 1 = expm1(L / 3) and J^-7 - 1 = expm1(-7 L), so
+// small volume changes keep their relative precision.
+MPM_HD void fluid_update(const float *Gt, const Material &mat, float *Gout, float tau[9], int &bad)
+{
+    const float jm1 = det_minus_one(Gt);
+    bad |= !(jm1 > -1.0f);
+    const float L = flog1p(jm1);
+    const float g = fexpm1(L * (1.0f / 3.0f));
+    const float K = mat.la + (2.0f / 3.0f) * mat.mu;
+    const float t = -(1.0f + jm1) * (K * (1.0f / 7.0f)) * fexpm1(-7.0f * L);
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+        Gout[i] = (i % 4 == 0) ? g : 0.0f;
+        tau[i] = (i % 4 == 0) ? t : 0.0f;
+    }
+}
+
 // Stress of a state without any return map (a state handed in from outside).
 MPM_HD void stress_of(const float *G, const Material &mat, float tau[9], int &bad)
 {
     if (mat.model == 0) {
         tau_neo_hookean(G, mat.mu, mat.la, tau, bad);
+        return;
+    }
+    if (mat.model == 2) {
+        float Gc[9];
+        fluid_update(G, mat, Gc, tau, bad);   // the stress depends on det F only
         return;
     }
     Material m2 = mat;

@@ -273,6 +273,8 @@ __device__ void sur_advance_item(const StepArgs &a, int it, const Item &item, fl
         if (mat.model == 0) {
             tau_neo_hookean(Gt, mat.mu, mat.la, tau, bad);
             for (int e = 0; e < 9; e++) Gn[e] = Gt[e];
+        } else if (mat.model == 2) {
+            fluid_update(Gt, mat, Gn, tau, bad);
         } else {
             hencky_update(Gt, mat, Gn, tau, bad);
         }

@@ -27,6 +27,7 @@ def _teacher_scenes():
     return [
         ("small-nh", scenes.small_scene(1, n=3000, res=16, model=scenes.NEO_HOOKEAN)),
         ("small-hencky", scenes.small_scene(2, n=3000, res=16, model=scenes.HENCKY_VM)),
+        ("small-fluid", scenes.small_scene(5, n=3000, res=16, model=scenes.FLUID)),
         ("cfg1b", scenes.cfg1b()),
         ("cfg2", scenes.cfg2()),
     ]
@@ -68,10 +69,12 @@ def test_teacher_forced_p2g_and_substep(mpm, orc, name, idx, block):
     sim.close()
 
 
-@pytest.mark.parametrize("name", ["cfg1", "cfg1b", "cfg2", "small-hencky", "small-sticky"])
+@pytest.mark.parametrize("name", ["cfg1", "cfg1b", "cfg2", "small-hencky", "small-sticky", "small-fluid"])
 def test_free_running_100(mpm, orc, name):
     if name == "small-hencky":
         sc = scenes.small_scene(3, n=4000, res=32, model=scenes.HENCKY_VM, n_ctrl=4, dt=1e-4)
+    elif name == "small-fluid":
+        sc = scenes.small_scene(6, n=4000, res=32, model=scenes.FLUID, n_ctrl=4, dt=1e-4, omega=2.0)
     elif name == "small-sticky":
         sc = scenes.small_scene(4, n=4000, res=32, model=scenes.NEO_HOOKEAN, n_ctrl=4, dt=1e-4,
                                 friction=float("inf"), omega=2.0)
