@@ -36,7 +36,27 @@ def build(force: bool = True) -> str:
 class Collider(ct.Structure):
     _fields_ = [("type", ct.c_int), ("half_extents", ct.c_double * 3), ("radius", ct.c_double),
                 ("half_length", ct.c_double), ("friction", ct.c_double), ("pos", ct.c_double * 3),
-                ("quat", ct.c_double * 4), ("vlin", ct.c_double * 3), ("omega", ct.c_double * 3)]
+                ("quat", ct.c_double * 4), ("vlin", ct.c_double * 3), ("omega", ct.c_double * 3),
+                ("sdf", ct.POINTER(ct.c_double)), ("sdf_dims", ct.c_int * 3), ("sdf_cell", ct.c_double),
+                ("sdf_origin", ct.c_double * 3)]
+
+
+def set_collider_shape(col, c, keep):
+    """Fill a Collider struct from a scene shape; keep holds the FP64 copy
+    of a sampled SDF volume alive."""
+    col.type = c.type
+    col.half_extents[:] = [float(h) for h in c.half_extents]
+    col.radius = c.radius
+    col.half_length = c.half_length
+    col.friction = c.friction
+    col.quat[:] = [1.0, 0.0, 0.0, 0.0]
+    if getattr(c, "sdf", None) is not None:
+        a = np.ascontiguousarray(c.sdf, np.float64)
+        keep.append(a)
+        col.sdf = _dp(a)
+        col.sdf_dims[:] = list(a.shape)
+        col.sdf_cell = float(c.sdf_cell)
+        col.sdf_origin[:] = [float(o) for o in c.sdf_origin]
 
 
 class SceneC(ct.Structure):
@@ -108,13 +128,9 @@ class Oracle:
         self.gp = np.zeros((nn, 3))
         self.vg = np.zeros((nn, 3))
         self.cols = (Collider * max(scene.n_colliders, 1))()
+        self._sdf_keep = []
         for k, c in enumerate(scene.colliders):
-            self.cols[k].type = c.type
-            self.cols[k].half_extents[:] = [float(h) for h in c.half_extents]
-            self.cols[k].radius = c.radius
-            self.cols[k].half_length = c.half_length
-            self.cols[k].friction = c.friction
-            self.cols[k].quat[:] = [1.0, 0.0, 0.0, 0.0]
+            set_collider_shape(self.cols[k], c, self._sdf_keep)
         # impulse (3) and angular impulse about the centre (3) received by each
         # collider, summed over the grid updates since the last take_wrench()
         self.wrench = np.zeros((max(scene.n_colliders, 1), 6)) if wrench else None
@@ -236,9 +252,8 @@ def weights(f):
 
 def make_collider(shape, pose, vel=(0, 0, 0, 0, 0, 0)):
     c = Collider()
-    c.type = shape.type
-    c.half_extents[:] = [float(h) for h in shape.half_extents]
-    c.radius, c.half_length, c.friction = shape.radius, shape.half_length, shape.friction
+    c._keep = []     # the FP64 copy of a sampled SDF volume lives as long as the struct
+    set_collider_shape(c, shape, c._keep)
     c.pos[:] = [float(p) for p in pose[:3]]
     c.quat[:] = [float(q) for q in pose[3:]]
     c.vlin[:] = [float(a) for a in vel[:3]]

@@ -54,7 +54,7 @@
 #endif
 
 typedef struct {
-    int type;                 /* 0 box, 1 capsule */
+    int type;                 /* 0 box, 1 capsule, 2 sampled SDF volume */
     double half_extents[3];   /* box half sizes, body frame */
     double radius;            /* capsule radius */
     double half_length;       /* capsule half segment length along body y */
@@ -63,6 +63,12 @@ typedef struct {
     double quat[4];           /* orientation w, x, y, z (body -> world) */
     double vlin[3];           /* linear velocity of the centre */
     double omega[3];          /* angular velocity (world frame) */
+    /* type 2: samples of the body-frame signed distance at sdf_origin + (i, j, k) sdf_cell,
+     * stored [nx][ny][nz]; the distance is their trilinear interpolant */
+    const double *sdf;
+    int sdf_dims[3];
+    double sdf_cell;
+    double sdf_origin[3];
 } orc_collider;
 
 typedef struct {
@@ -301,6 +307,42 @@ static void quat_rotate_inv(const double *q, const double *v, double *out)
     quat_rotate(qc, v, out);
 }
 
+/* Sampled SDF volume (a mesh collider stored as a 3D grid of distances, as
+ * the paper keeps its mesh SDFs in 3D textures, Sec. 3): the distance at a
+ * body-frame point p is the trilinear interpolant of the eight samples of the
+ * cell holding p, the normal the normalised gradient of that interpolant
+ * (body +x where it vanishes).  Outside the sampled box there is no contact:
+ * the distance is +DBL_MAX. */
+static double sdf_volume(const orc_collider *c, const double *p, double *nb)
+{
+    double u[3], f[3];
+    int i0[3];
+    nb[0] = 1.0; nb[1] = 0.0; nb[2] = 0.0;
+    for (int a = 0; a < 3; a++) {
+        u[a] = (p[a] - c->sdf_origin[a]) / c->sdf_cell;
+        if (!(u[a] >= 0.0 && u[a] <= c->sdf_dims[a] - 1)) return DBL_MAX;
+        i0[a] = (int)floor(u[a]);
+        if (i0[a] > c->sdf_dims[a] - 2) i0[a] = c->sdf_dims[a] - 2;
+        f[a] = u[a] - i0[a];
+    }
+    int ny = c->sdf_dims[1], nz = c->sdf_dims[2];
+    double phi = 0.0, g[3] = {0.0, 0.0, 0.0};
+    for (int dx_ = 0; dx_ < 2; dx_++)
+        for (int dy = 0; dy < 2; dy++)
+            for (int dz = 0; dz < 2; dz++) {
+                double s = c->sdf[((size_t)(i0[0] + dx_) * ny + (i0[1] + dy)) * nz + (i0[2] + dz)];
+                double wx = dx_ ? f[0] : 1.0 - f[0], wy = dy ? f[1] : 1.0 - f[1], wz = dz ? f[2] : 1.0 - f[2];
+                phi += wx * wy * wz * s;
+                g[0] += (dx_ ? 1.0 : -1.0) * wy * wz * s;
+                g[1] += (dy ? 1.0 : -1.0) * wx * wz * s;
+                g[2] += (dz ? 1.0 : -1.0) * wx * wy * s;
+            }
+    double len = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    if (len > 0.0)
+        for (int a = 0; a < 3; a++) nb[a] = g[a] / len;
+    return phi;
+}
+
 /* Signed distance of world point x to the collider and the outward unit
  * normal (world frame).  Box inside: nearest face, ties to the lowest axis,
  * + before -.  Capsule on its axis: body +x. */
@@ -309,7 +351,9 @@ double orc_sdf(const orc_collider *c, const double *x, double *n)
     double r[3] = {x[0] - c->pos[0], x[1] - c->pos[1], x[2] - c->pos[2]};
     double p[3], nb[3] = {0, 0, 0}, phi;
     quat_rotate_inv(c->quat, r, p);
-    if (c->type == 0) {
+    if (c->type == 2) {
+        phi = sdf_volume(c, p, nb);
+    } else if (c->type == 0) {
         double q[3], outside = 0;
         for (int a = 0; a < 3; a++) {
             q[a] = fabs(p[a]) - c->half_extents[a];

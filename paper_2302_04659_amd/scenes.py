@@ -36,6 +36,7 @@ import numpy as np
 
 BOX = 0
 CAPSULE = 1
+SDF_VOLUME = 2     # sampled signed distance brick (a mesh collider), trilinear
 NEO_HOOKEAN = 0
 HENCKY_VM = 1
 FLUID = 2          # weakly compressible fluid (Tait pressure, volume-only state)
@@ -44,11 +45,14 @@ SUBSTEPS_PER_CTRL = 25
 
 @dataclass
 class ColliderShape:
-    type: int                       # BOX or CAPSULE
+    type: int                       # BOX, CAPSULE or SDF_VOLUME
     half_extents: tuple = (0.0, 0.0, 0.0)   # box, body frame
     radius: float = 0.0             # capsule
     half_length: float = 0.0        # capsule, along body y
     friction: float = 0.5           # Coulomb coefficient; math.inf = sticky
+    sdf: object = None              # SDF_VOLUME: float32 [nx][ny][nz] body-frame distances
+    sdf_cell: float = 0.0           #   sample spacing (m)
+    sdf_origin: tuple = (0.0, 0.0, 0.0)     # body-frame position of sample (0, 0, 0)
 
 
 @dataclass
@@ -303,6 +307,63 @@ def small_scene(seed: int, n: int = 256, res: int = 16, model: int = HENCKY_VM,
         V = np.zeros((n_ctrl, 0, 6), np.float32)
     return Scene(f"small[{seed}]", x, v, res, dx, dt, (0.0, -9.8, 0.0), 3, model, 1e4, 0.3, 1e3,
                  300.0 if model == HENCKY_VM else 0.0, 0, (hi - lo) ** 3 / n, shapes, P, V)
+
+
+def beaker_sdf(radius: float, height: float, wall: float, cell: float, margin: int = 3):
+    """A synthetic container mesh as a sampled SDF brick (stand-in for the
+    paper's beakers and buckets, whose meshes are not available): an
+    open-top cup along body y, outer radius `radius`, height `height`,
+    wall and bottom thickness `wall`, centred on the origin.  The solid is
+    the outer capped cylinder minus the inner cavity (a cylinder of radius
+    radius - wall from the bottom's top face up through the opening); its
+    distance is max(outer, -cavity), sampled every `cell` over a box
+    `margin` cells larger than the cup.  Returns (samples float32
+    [nx][ny][nz], origin)."""
+    ext = np.array([radius, height / 2, radius]) + margin * cell
+    n = np.ceil(2 * ext / cell).astype(int) + 1
+    origin = -ext
+    axes = [origin[a] + cell * np.arange(n[a]) for a in range(3)]
+    X, Y, Z = np.meshgrid(*axes, indexing="ij")
+    rho = np.sqrt(X * X + Z * Z)
+
+    def capped(r, y0, y1):
+        # signed distance to the solid cylinder rho <= r, y0 <= y <= y1
+        dr = rho - r
+        dy = np.abs(Y - 0.5 * (y0 + y1)) - 0.5 * (y1 - y0)
+        out = np.sqrt(np.maximum(dr, 0) ** 2 + np.maximum(dy, 0) ** 2)
+        return out + np.minimum(np.maximum(dr, dy), 0.0)
+
+    outer = capped(radius, -height / 2, height / 2)
+    cavity = capped(radius - wall, -height / 2 + wall, height / 2 + 4 * cell)
+    return np.maximum(outer, -cavity).astype(np.float32), tuple(float(o) for o in origin)
+
+
+def pour_scene(seed: int = 0, n: int = 6000, res: int = 32, model: int = FLUID, dt: float = 1e-4,
+               n_ctrl: int = 4) -> Scene:
+    """Material dropped into a beaker (an SDF-volume collider), the beaker
+    sliding and tilting slowly: a seeded stand-in for the Pour / Fill tasks."""
+    rng = np.random.default_rng(seed)
+    dx = 1.0 / res
+    floor = 3 * dx
+    R, H, W = 0.16, 0.22, 0.03
+    c0 = np.array([0.5, floor + H / 2 + 0.01, 0.5])
+    # a column of material above the opening
+    x = np.stack([rng.uniform(0.5 - 0.08, 0.5 + 0.08, n), rng.uniform(c0[1] + 0.02, c0[1] + 0.18, n),
+                  rng.uniform(0.5 - 0.08, 0.5 + 0.08, n)], 1).astype(np.float32)
+    v = np.zeros((n, 3), np.float32)
+    v[:, 1] = -0.5
+    sdf, origin = beaker_sdf(R, H, W, dx / 2)
+    shape = ColliderShape(SDF_VOLUME, friction=0.3, sdf=sdf, sdf_cell=dx / 2, sdf_origin=origin)
+    vel = np.zeros((n_ctrl, 6))
+    for j in range(n_ctrl):
+        vel[j, :3] = 0.05 * rng.normal(size=3)
+        vel[j, 1] = 0.0
+        vel[j, 3:] = [0.0, 0.0, 0.5 * rng.normal()]
+    q0 = np.array([1.0, 0.0, 0.0, 0.0])
+    P, V = _pack([_trajectory(c0, q0, vel, dt)], [vel])
+    vol = 0.16 * 0.16 * 0.16 / n
+    return Scene(f"pour[{seed}]", x, v, res, dx, dt, (0.0, -9.8, 0.0), 3, model, 1e4, 0.3, 1e3,
+                 300.0 if model == HENCKY_VM else 0.0, 0, vol, [shape], P, V)
 
 
 WORKLOADS = {"cfg1": cfg1, "cfg1b": cfg1b, "cfg2": cfg2, "cfg3": cfg3, "cfg4": cfg4}

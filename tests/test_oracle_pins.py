@@ -425,6 +425,86 @@ def test_sdf_hand_picked_points(orc):
         assert np.allclose(n, case["n"], atol=1e-12), case
 
 
+def _brick(fn, origin, cell, dims):
+    ax = [origin[a] + cell * np.arange(dims[a]) for a in range(3)]
+    P = np.stack(np.meshgrid(*ax, indexing="ij"), -1)
+    return fn(P).astype(np.float64)
+
+
+def test_sdf_volume_is_trilinear(orc):
+    """Sampled SDF volume (a mesh collider as a distance brick): a plane
+    sampled on the brick comes back exactly everywhere inside it (the
+    trilinear interpolant of a linear function is that function), with its
+    normal; brick nodes return their samples; outside the brick there is no
+    contact.  Rotated and translated pose."""
+    from scipy.spatial.transform import Rotation
+    nrm = np.array([0.3, -0.8, 0.52])
+    nrm /= np.linalg.norm(nrm)
+    origin, cell, dims = (-0.2, -0.15, -0.1), 0.02, (21, 16, 11)
+    plane = _brick(lambda P: P @ nrm - 0.01, origin, cell, dims)
+    sh = scenes.ColliderShape(scenes.SDF_VOLUME, sdf=plane, sdf_cell=cell, sdf_origin=origin)
+    q = Rotation.from_rotvec([0.2, 0.7, -0.4]).as_quat()          # x, y, z, w
+    pose = np.array([0.5, 0.45, 0.55, q[3], q[0], q[1], q[2]])
+    c = orc.make_collider(sh, pose)
+    R = Rotation.from_quat(q).as_matrix()
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        pb = np.array(origin) + rng.uniform(0, 1, 3) * (np.array(dims) - 1) * cell
+        phi, n = orc.sdf(c, pose[:3] + R @ pb)
+        assert abs(phi - (pb @ nrm - 0.01)) < 1e-12
+        assert np.allclose(n, R @ nrm, atol=1e-12)
+    rand = _brick(lambda P: np.sin(7 * P[..., 0]) * np.cos(5 * P[..., 1]) + P[..., 2], origin, cell, dims)
+    c2 = orc.make_collider(scenes.ColliderShape(scenes.SDF_VOLUME, sdf=rand, sdf_cell=cell, sdf_origin=origin), pose)
+    for ijk in [(1, 1, 1), (19, 14, 9), (7, 3, 9), (12, 8, 1)]:   # interior nodes (a face node may round outside)
+        pb = np.array(origin) + cell * np.array(ijk)
+        phi, _ = orc.sdf(c2, pose[:3] + R @ pb)
+        assert abs(phi - rand[ijk]) < 1e-12
+    far = pose[:3] + R @ (np.array(origin) - 0.05)
+    assert orc.sdf(c2, far)[0] > 1e300
+    _, hit = orc.collide(c2, far, np.array([0.0, -5.0, 0.0]))
+    assert not hit
+
+
+def test_sdf_volume_of_a_box_matches_the_box(orc):
+    """A box's distance sampled on a brick matches the analytic box where
+    the box distance is linear over a whole cell (near a face centre, inside
+    and outside)."""
+    he = np.array([0.08, 0.05, 0.06])
+
+    def box(P):
+        q = np.abs(P) - he
+        out = np.sqrt((np.maximum(q, 0) ** 2).sum(-1))
+        return out + np.minimum(q.max(-1), 0.0)
+
+    origin, cell = (-0.12, -0.09, -0.1), 0.01
+    dims = (25, 19, 21)
+    sh = scenes.ColliderShape(scenes.SDF_VOLUME, sdf=_brick(box, origin, cell, dims), sdf_cell=cell, sdf_origin=origin)
+    pose = np.array([0.4, 0.5, 0.6, 1.0, 0.0, 0.0, 0.0])
+    c = orc.make_collider(sh, pose)
+    cb = orc.make_collider(scenes.ColliderShape(scenes.BOX, tuple(he)), pose)
+    rng = np.random.default_rng(6)
+    for _ in range(40):
+        # near the +x face centre, within 2.5 cells of the face: one face is nearest
+        pb = np.array([he[0] + rng.uniform(-0.025, 0.025), rng.uniform(-0.02, 0.02), rng.uniform(-0.02, 0.02)])
+        p1, n1 = orc.sdf(c, pose[:3] + pb)
+        p2, n2 = orc.sdf(cb, pose[:3] + pb)
+        assert abs(p1 - p2) < 1e-12 and np.allclose(n1, n2, atol=1e-12), pb
+
+
+def test_beaker_sdf_signs(orc):
+    """The synthetic beaker: negative in its walls and bottom, positive in
+    the cavity and outside; its brick reaches past the cup on every side."""
+    sdf, origin = scenes.beaker_sdf(0.16, 0.22, 0.03, 1.0 / 64)
+    sh = scenes.ColliderShape(scenes.SDF_VOLUME, sdf=sdf, sdf_cell=1.0 / 64, sdf_origin=origin)
+    c = orc.make_collider(sh, np.array([0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0]))
+    assert orc.sdf(c, np.array([0.145, 0.0, 0.0]))[0] < 0      # in the side wall
+    assert orc.sdf(c, np.array([0.0, -0.1, 0.0]))[0] < 0       # in the bottom
+    assert orc.sdf(c, np.array([0.0, 0.0, 0.0]))[0] > 0        # in the cavity
+    assert orc.sdf(c, np.array([0.2, 0.0, 0.0]))[0] > 0        # outside
+    assert orc.sdf(c, np.array([0.0, 0.2, 0.0]))[0] > 0        # above the opening
+    assert sdf.min() < 0 < sdf.max() and all(d > 4 for d in sdf.shape)
+
+
 def test_sdf_gradient_is_unit_normal(orc):
     from scipy.spatial.transform import Rotation
     rng = np.random.default_rng(4)
