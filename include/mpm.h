@@ -73,7 +73,7 @@ typedef enum {
  *                             K = lambda + 2 mu / 3 from (E, nu); F is kept as
  *                             J^(1/3) I (volume change only, no shear) */
 typedef enum { MPM_NEO_HOOKEAN = 0, MPM_HENCKY_VON_MISES = 1, MPM_WEAKLY_COMPRESSIBLE_FLUID = 2 } mpm_model;
-typedef enum { MPM_BOX = 0, MPM_CAPSULE = 1 } mpm_shape_type;
+typedef enum { MPM_BOX = 0, MPM_CAPSULE = 1, MPM_SDF_VOLUME = 2 } mpm_shape_type;
 
 typedef struct {
     int model;             /* mpm_model */
@@ -90,6 +90,17 @@ typedef struct {
     float radius;          /* capsule radius */
     float half_length;     /* capsule half segment length along body y */
     float friction;        /* Coulomb coefficient >= 0; +inf = sticky */
+    /* MPM_SDF_VOLUME: a mesh collider as a sampled signed distance (the paper
+     * keeps mesh SDFs as 3D textures, Sec. 3): host samples [nx][ny][nz] of
+     * the body-frame distance at sdf_origin + (i, j, k) sdf_cell, copied by
+     * mpm_create.  The distance is their trilinear interpolant, the normal its
+     * normalised gradient; outside the sampled box there is no contact, so
+     * the brick must enclose the surface.  Each dimension >= 2, sdf_cell > 0,
+     * samples finite.  Ignored by the other types (may be NULL / 0). */
+    const float *sdf;
+    int sdf_dims[3];
+    float sdf_cell;
+    float sdf_origin[3];
 } mpm_collider_shape;
 
 typedef struct {

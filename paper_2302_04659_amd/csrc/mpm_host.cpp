@@ -62,6 +62,8 @@ struct mpm_ctx_s {
     std::vector<mpm_scene_desc> descs;
     std::vector<ColliderDev> h_cols;
     std::vector<int> h_col_scene;
+    std::vector<float> h_sdf;        // samples of every SDF-volume collider, concatenated
+    float *d_sdf = nullptr;
     int max_col = 0;
 
     SceneDev *d_scenes = nullptr;
@@ -170,7 +172,20 @@ mpm_status validate_desc(mpm_ctx ctx, const mpm_scene_desc &d, int i)
     if (d.n_colliders > 0 && !d.colliders) return bad("colliders is NULL");
     for (int k = 0; k < d.n_colliders; k++) {
         const mpm_collider_shape &c = d.colliders[k];
-        if (c.type != 0 && c.type != 1) return bad("unknown collider type");
+        if (c.type < 0 || c.type > 2) return bad("unknown collider type");
+        if (c.type == 2) {
+            if (!c.sdf) return bad("SDF volume: sdf is NULL");
+            long long n = 1;
+            for (int a = 0; a < 3; a++) {
+                if (c.sdf_dims[a] < 2) return bad("SDF volume: every dimension must be >= 2");
+                if (!std::isfinite(c.sdf_origin[a])) return bad("SDF volume: origin not finite");
+                n *= c.sdf_dims[a];
+            }
+            if (!(c.sdf_cell > 0) || !std::isfinite(c.sdf_cell)) return bad("SDF volume: cell must be > 0");
+            if (n > (1LL << 28)) return bad("SDF volume: too many samples");
+            for (long long i = 0; i < n; i++)
+                if (!std::isfinite(c.sdf[i])) return bad("SDF volume: non-finite sample");
+        }
         if (!(c.friction >= 0)) return bad("collider friction must be >= 0");
         if (c.type == 0 && !(c.half_extents[0] >= 0 && c.half_extents[1] >= 0 && c.half_extents[2] >= 0))
             return bad("box half extents must be >= 0");
@@ -363,6 +378,7 @@ StepArgs step_args(mpm_ctx ctx, int substep)
     a.cf = 0;
     a.keep_bound = 0;
     a.wrench = ctx->d_wrench;
+    a.sdf = ctx->d_sdf;
     return a;
 }
 
@@ -514,7 +530,7 @@ void release(mpm_ctx ctx)
                     ctx->L.scene_item_begin, ctx->L.scene_gitem_begin, ctx->L.bflag, ctx->L.ovf, ctx->L.n_ovf, ctx->L.ibound, ctx->L.touched,
                     ctx->d_flags, ctx->d_queue, ctx->d_scene_done, ctx->d_cap, ctx->d_cap_off, ctx->d_io,
                     ctx->d_active, ctx->d_sur_gend, ctx->d_sur_acc, ctx->d_sur_out, ctx->d_sur_nfb,
-                    ctx->d_wrench, ctx->d_wrench_out};
+                    ctx->d_wrench, ctx->d_wrench_out, ctx->d_sdf};
     for (void *p : bufs)
         if (p) hipFree(p);
     for (int i = 0; i < STAGE_RING; i++) {
@@ -550,6 +566,16 @@ mpm_status create_impl(mpm_ctx ctx, const mpm_scene_desc *scenes, int n_scenes)
             cd.half_length = c.half_length;
             cd.friction = c.friction;
             cd.quat[0] = 1.0f;
+            if (c.type == 2) {
+                const long long n = (long long)c.sdf_dims[0] * c.sdf_dims[1] * c.sdf_dims[2];
+                cd.sdf_off = (int)ctx->h_sdf.size();
+                ctx->h_sdf.insert(ctx->h_sdf.end(), c.sdf, c.sdf + n);
+                for (int a = 0; a < 3; a++) {
+                    cd.sdf_dims[a] = c.sdf_dims[a];
+                    cd.sdf_origin[a] = c.sdf_origin[a];
+                }
+                cd.sdf_cell = c.sdf_cell;
+            }
             ctx->h_cols.push_back(cd);
             ctx->h_col_scene.push_back(s);
         }
@@ -573,7 +599,14 @@ mpm_status create_impl(mpm_ctx ctx, const mpm_scene_desc *scenes, int n_scenes)
     for (int b = 0; b < 2; b++) HIPCHK(dalloc(&ctx->d_P[b], (size_t)NCOMP * ctx->pstride));
     HIPCHK(dalloc(&ctx->d_grid, (size_t)7 * nodes));
     HIPCHK(dalloc(&ctx->d_cols, ctx->h_cols.size()));
-    HIPCHK(hipMalloc(&ctx->d_colnow, std::max<size_t>(ctx->h_cols.size(), 1) * 128));
+    HIPCHK(hipMalloc(&ctx->d_colnow, std::max<size_t>(ctx->h_cols.size(), 1) * collider_now_bytes()));
+    if (ctx->h_sdf.size() > (size_t)INT32_MAX) {
+        ctx->last_error = "SDF volumes: more than 2^31 samples in total";
+        return MPM_ERR_ARG;
+    }
+    HIPCHK(dalloc(&ctx->d_sdf, std::max<size_t>(ctx->h_sdf.size(), 1)));
+    if (!ctx->h_sdf.empty())
+        HIPCHK(hipMemcpy(ctx->d_sdf, ctx->h_sdf.data(), sizeof(float) * ctx->h_sdf.size(), hipMemcpyHostToDevice));
     HIPCHK(dalloc(&ctx->d_wrench, std::max<size_t>(ctx->h_cols.size(), 1) * 6));
     HIPCHK(dalloc(&ctx->d_wrench_out, std::max<size_t>((size_t)n_scenes * ctx->max_col, 1) * 6));
     HIPCHK(dalloc(&ctx->d_col_scene, ctx->h_cols.size()));

@@ -603,7 +603,7 @@ __device__ void grid_block(const StepArgs &a, int s, int lb, int lane, ColliderN
         float xi[3] = {ii[0] * K.dx, ii[1] * K.dx, ii[2] * K.dx};
         for (int c = 0; c < n_col; c++) {
             const float v0[3] = {v[0], v[1], v[2]};
-            const bool hit = collide_node(cl[c], xi, v) && live && m > 0.0f;
+            const bool hit = collide_node(cl[c], xi, v, a.sdf) && live && m > 0.0f;
             // two-way coupling: the collider receives minus the momentum its projection gives
             // the node, and minus its moment about the collider centre; one wave sum and one
             // atomic per component, only where the wave touched this collider
@@ -655,7 +655,7 @@ __device__ void grid_block(const StepArgs &a, int s, int lb, int lane, ColliderN
 }
 
 template <int B, bool EXTRA>
-__global__ __launch_bounds__(WG) void k_grid(StepArgs a)
+__global__ __launch_bounds__(WG, (B == 8 && !EXTRA) ? 7 : 1) void k_grid(StepArgs a)
 {
     const int lane = threadIdx.x & 63;
     __shared__ ColliderNow cls[WG / 64][MAX_COLLIDERS_PER_SCENE];
@@ -1052,6 +1052,8 @@ hipError_t launch_collider_advance(ColliderDev *cols, int n_cols, const int *col
 }
 
 // ====================================================================== boundary conversions
+size_t collider_now_bytes() { return sizeof(ColliderNow); }
+
 __global__ void k_wrench_out(const SceneDev *scenes, int n_scenes, int max_col, float *acc, float *out)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;   // (scene, slot, component)

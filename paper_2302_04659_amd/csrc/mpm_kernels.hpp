@@ -32,6 +32,7 @@ struct StepArgs {
     const int *sur_org;       // surrogate box of scene s: origin sur_org[3 s ..] (device), size sur_box;
     int sur_box[3];           //   null = the whole grid (res^3 per scene, offset cap_off[s])
     float *out_mass;          // per scene: P2G mass the grid update found outside the box (added), or null
+    const float *sdf;         // samples of the SDF-volume colliders (ColliderNow::sdf_off into it)
     float *wrench;            // per collider (global index): [6] impulse and angular impulse about its centre
                               //   received from the material, summed over grid updates (or null)
 };
@@ -68,6 +69,8 @@ hipError_t launch_collider_advance(ColliderDev *cols, int n_cols, const int *col
                                    int n_substeps, hipStream_t st);
 
 // Boundary conversions (creation order <-> sorted SoA).
+// Bytes of one collider's per-substep pose record (the device array a.colnow).
+size_t collider_now_bytes();
 // Collider wrenches out as [n_scenes][max_col][6] (zero past a scene's colliders), accumulators cleared.
 hipError_t launch_wrench_out(const SceneDev *scenes, int n_scenes, int max_col, float *acc, float *out, hipStream_t st);
 hipError_t launch_init_particles(const SceneDev *scenes, int n_scenes, const int *psc, float *P, long long pstride,

@@ -414,6 +414,8 @@ struct ColliderNow {
     int type;
     float he[3], radius, half_length, friction;
     float c[3], R[9], v[3], w[3];
+    int sdf_off, sdf_dims[3];
+    float sdf_cell, sdf_origin[3];
 };
 
 MPM_HD void collider_at(const ColliderDev &cd, float tk, ColliderNow &cn)
@@ -428,21 +430,74 @@ MPM_HD void collider_at(const ColliderDev &cd, float tk, ColliderNow &cn)
     cn.radius = cd.radius;
     cn.half_length = cd.half_length;
     cn.friction = cd.friction;
+    cn.sdf_off = cd.sdf_off;
+    cn.sdf_cell = cd.sdf_cell;
+    for (int a = 0; a < 3; a++) {
+        cn.sdf_dims[a] = cd.sdf_dims[a];
+        cn.sdf_origin[a] = cd.sdf_origin[a];
+    }
     float q[4];
     quat_advance(cd.quat, cd.omega, tk, q);
     quat_to_mat(q, cn.R);
 }
 
+// Sampled SDF volume at body-frame point p: trilinear interpolant of the
+// eight samples of the cell holding p, normal = normalised gradient of that
+// interpolant (body +x where it vanishes); outside the brick no contact
+// (a large positive distance).
+MPM_HD float sdf_volume(const ColliderNow &c, const float *sdf, const float p[3], float nb[3])
+{
+    float f[3];
+    int i0[3];
+    nb[0] = 1.0f;
+    nb[1] = 0.0f;
+    nb[2] = 0.0f;
+    const float ic = 1.0f / c.sdf_cell;
+    for (int a = 0; a < 3; a++) {
+        const float u = (p[a] - c.sdf_origin[a]) * ic;
+        if (!(u >= 0.0f && u <= (float)(c.sdf_dims[a] - 1))) return 3.0e38f;
+        i0[a] = (int)floorf(u);
+        if (i0[a] > c.sdf_dims[a] - 2) i0[a] = c.sdf_dims[a] - 2;
+        f[a] = u - (float)i0[a];
+    }
+    const int ny = c.sdf_dims[1], nz = c.sdf_dims[2];
+    const float *s0 = sdf + c.sdf_off + ((long long)i0[0] * ny + i0[1]) * nz + i0[2];
+    const long long sx = (long long)ny * nz, sy = nz;
+    const float s000 = s0[0], s001 = s0[1], s010 = s0[sy], s011 = s0[sy + 1];
+    const float s100 = s0[sx], s101 = s0[sx + 1], s110 = s0[sx + sy], s111 = s0[sx + sy + 1];
+    // interpolate along z, then y, then x; the gradient from the same partial sums
+    const float a00 = s000 + f[2] * (s001 - s000), a01 = s010 + f[2] * (s011 - s010);
+    const float a10 = s100 + f[2] * (s101 - s100), a11 = s110 + f[2] * (s111 - s110);
+    const float b0 = a00 + f[1] * (a01 - a00), b1 = a10 + f[1] * (a11 - a10);
+    const float phi = b0 + f[0] * (b1 - b0);
+    const float gx = b1 - b0;
+    const float gy = (a01 - a00) + f[0] * ((a11 - a10) - (a01 - a00));
+    const float dz0 = (s001 - s000) + f[1] * ((s011 - s010) - (s001 - s000));
+    const float dz1 = (s101 - s100) + f[1] * ((s111 - s110) - (s101 - s100));
+    const float gz = dz0 + f[0] * (dz1 - dz0);
+    const float len2 = gx * gx + gy * gy + gz * gz;
+    if (len2 > 0.0f) {
+        const float il = 1.0f / sqrtf(len2);
+        nb[0] = gx * il;
+        nb[1] = gy * il;
+        nb[2] = gz * il;
+    }
+    return phi;
+}
+
 // Signed distance and outward unit normal (world).  Box interior: nearest
 // face, ties to the lowest axis, + before -.  Capsule on its axis: body +x.
-MPM_HD float sdf_eval(const ColliderNow &c, const float x[3], float n[3])
+// sdf: the context's buffer of SDF-volume samples (read by type 2 only).
+MPM_HD float sdf_eval(const ColliderNow &c, const float x[3], float n[3], const float *sdf)
 {
     float r[3] = {x[0] - c.c[0], x[1] - c.c[1], x[2] - c.c[2]};
     float p[3];
     for (int a = 0; a < 3; a++) p[a] = c.R[a] * r[0] + c.R[3 + a] * r[1] + c.R[6 + a] * r[2];   // R^T r
     float nb[3] = {0.0f, 0.0f, 0.0f};
     float phi;
-    if (c.type == 0) {
+    if (c.type == 2) {
+        phi = sdf_volume(c, sdf, p, nb);
+    } else if (c.type == 0) {
         float q[3], out = 0.0f;
         for (int a = 0; a < 3; a++) {
             q[a] = fabsf(p[a]) - c.he[a];
@@ -476,10 +531,10 @@ MPM_HD float sdf_eval(const ColliderNow &c, const float x[3], float n[3])
 }
 
 // Grid-node contact: separating test and Coulomb friction (in place).
-MPM_HD int collide_node(const ColliderNow &c, const float xi[3], float v[3])
+MPM_HD int collide_node(const ColliderNow &c, const float xi[3], float v[3], const float *sdf)
 {
     float n[3];
-    float phi = sdf_eval(c, xi, n);
+    float phi = sdf_eval(c, xi, n, sdf);
     float r[3] = {xi[0] - c.c[0], xi[1] - c.c[1], xi[2] - c.c[2]};
     float vc[3] = {c.v[0] + (c.w[1] * r[2] - c.w[2] * r[1]),
                    c.v[1] + (c.w[2] * r[0] - c.w[0] * r[2]),

@@ -40,13 +40,17 @@ struct SceneDev {
 };
 
 struct ColliderDev {
-    int type;                 // 0 box, 1 capsule
+    int type;                 // 0 box, 1 capsule, 2 sampled SDF volume
     float he[3];
     float radius, half_length, friction;
     float pos[3];             // centre at the start of the current mpm_step call
     float quat[4];            // w x y z at the start of the current call
     float vlin[3];
     float omega[3];
+    int sdf_off;              // type 2: first sample in the context's SDF buffer
+    int sdf_dims[3];          //   samples per axis, stored [nx][ny][nz]
+    float sdf_cell;           //   spacing
+    float sdf_origin[3];      //   body-frame position of sample (0, 0, 0)
 };
 
 // One unit of particle work: a chunk of the particles binned to one grid

@@ -58,7 +58,7 @@ __global__ __launch_bounds__(WG) void k_sur_init(StepArgs a, int res, float *fea
         const ColliderNow *cn = (const ColliderNow *)a.colnow + S.col_off;
         for (int q = 0; q < S.n_col; q++) {
             float n[3];
-            const float phi = sdf_eval(cn[q], xi, n);
+            const float phi = sdf_eval(cn[q], xi, n, a.sdf);
             if (phi < phi_min) {
                 phi_min = phi;
                 const float r[3] = {xi[0] - cn[q].c[0], xi[1] - cn[q].c[1], xi[2] - cn[q].c[2]};

@@ -34,7 +34,8 @@ class Material(ct.Structure):
 
 class ColliderShape(ct.Structure):
     _fields_ = [("type", ct.c_int), ("half_extents", ct.c_float * 3), ("radius", ct.c_float),
-                ("half_length", ct.c_float), ("friction", ct.c_float)]
+                ("half_length", ct.c_float), ("friction", ct.c_float), ("sdf", ct.POINTER(ct.c_float)),
+                ("sdf_dims", ct.c_int * 3), ("sdf_cell", ct.c_float), ("sdf_origin", ct.c_float * 3)]
 
 
 class SceneDesc(ct.Structure):
@@ -154,6 +155,13 @@ class Sim:
                     cs[k].half_extents[:] = [float(h) for h in c.half_extents]
                     cs[k].radius, cs[k].half_length = c.radius, c.half_length
                     cs[k].friction = c.friction
+                    if getattr(c, "sdf", None) is not None:       # sampled SDF volume
+                        a = np.ascontiguousarray(c.sdf, np.float32)
+                        self._keep.append(a)
+                        cs[k].sdf = a.ctypes.data_as(ct.POINTER(ct.c_float))
+                        cs[k].sdf_dims[:] = list(a.shape)
+                        cs[k].sdf_cell = c.sdf_cell
+                        cs[k].sdf_origin[:] = [float(o) for o in c.sdf_origin]
                 self._keep.append(cs)
                 d.colliders = ct.cast(cs, ct.POINTER(ColliderShape))
         h = ct.c_void_p()
