@@ -118,7 +118,7 @@ def main():
                          "times (the reference kernel for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(scenes would shard across GPUs with no per-substep exchange).", file=sys.stderr)
         sys.exit(2)
 

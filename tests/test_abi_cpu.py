@@ -86,3 +86,15 @@ def test_bin_scramble_multiplier_is_prime():
     for size in (1, 2, 3, 63, 64, 512, 4097, M, 2 * M):
         mul = M if size % M else 1
         assert len(set((r * mul) % size for r in range(size))) == size
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asked for more it exits with a message
+    (before touching any device)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=root)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr), r.stdout + r.stderr
