@@ -4,8 +4,8 @@ Plain, slow reference for the surrogate network's forward pass, backward
 pass, masked MSE loss and Adam update.  Only the tests and the smoke check
 use it; the product path runs its own HIP kernels.
 
-The paper has no learned component; the network shape is this build's
-reading of the surrogate it adds (a 3-level grid U-Net, 32/64/128 channels,
+The paper has no learned component; the network shape is the reading
+taken here of the grid surrogate (a 3-level grid U-Net, 32/64/128 channels,
 3^3 convolutions, predicting the grid velocity / mass change of a
 25-substep block from mass, momentum and collider fields):
 
