@@ -92,10 +92,14 @@ def test_scene_mask_steps_only_active_scenes(env, orc):
     sim.close()
 
 
-def test_features_match_oracle(env, orc):
+@pytest.mark.parametrize("kind", ["analytic", "sdf-volume"])
+def test_features_match_oracle(env, orc, kind):
+    """Surrogate input channels (P2G mass and momentum, clipped distance to
+    the nearest collider, that collider's velocity) against the oracle, with
+    box / capsule colliders and with a sampled-SDF-volume beaker."""
     torch, mpm = env
-    batch = _batch()
-    announce("surrogate features", len(batch))
+    batch = _batch() if kind == "analytic" else [scenes.pour_scene(seed=s, n=3000) for s in range(2)]
+    announce("surrogate features", kind, len(batch))
     S, R = len(batch), batch[0].res
     ts = _new_stream(torch)
     sim = mpm.Sim(batch, stream=ts.cuda_stream)
