@@ -65,7 +65,8 @@ class SceneC(ct.Structure):
                 ("dx", ct.c_double), ("dt", ct.c_double), ("g", ct.c_double * 3), ("bound", ct.c_int),
                 ("model", ct.c_int), ("E", ct.c_double), ("nu", ct.c_double), ("rho", ct.c_double),
                 ("yield_stress", ct.c_double), ("yield_form", ct.c_int), ("p_vol", ct.c_double),
-                ("n_col", ct.c_int), ("col", ct.POINTER(Collider)), ("wrench", ct.POINTER(ct.c_double))]
+                ("n_col", ct.c_int), ("col", ct.POINTER(Collider)), ("wrench", ct.POINTER(ct.c_double)),
+                ("contact", ct.c_int)]
 
 
 _lib = None
@@ -115,7 +116,7 @@ class OracleError(RuntimeError):
 class Oracle:
     """One scene held in FP64.  State arrays are numpy views you may edit."""
 
-    def __init__(self, scene, x=None, v=None, C=None, F=None, wrench: bool = False):
+    def __init__(self, scene, x=None, v=None, C=None, F=None, wrench: bool = False, contact: int = 0):
         n = scene.n
         self.scene = scene
         self.x = np.ascontiguousarray(scene.x if x is None else x, dtype=np.float64).reshape(n, 3).copy()
@@ -134,6 +135,7 @@ class Oracle:
         # impulse (3) and angular impulse about the centre (3) received by each
         # collider, summed over the grid updates since the last take_wrench()
         self.wrench = np.zeros((max(scene.n_colliders, 1), 6)) if wrench else None
+        self.contact = contact    # 0 grid-node projection, 1 particle penalty, 2 both
         self.s = SceneC()
         self._bind()
 
@@ -150,6 +152,7 @@ class Oracle:
         s.n_col = sc.n_colliders
         s.col = ct.cast(self.cols, ct.POINTER(Collider))
         s.wrench = _dp(self.wrench) if self.wrench is not None else ct.POINTER(ct.c_double)()
+        s.contact = getattr(self, "contact", 0)
 
     # -- colliders ---------------------------------------------------------
     def set_colliders(self, poses, vels):

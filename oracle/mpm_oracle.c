@@ -86,6 +86,7 @@ typedef struct {
     orc_collider *col;
     double *wrench;           /* [n_col][6] or NULL: impulse on each collider and its
                                  angular impulse about the collider centre, summed */
+    int contact;              /* 0 grid-node projection, 1 particle penalty, 2 both */
 } orc_scene;
 
 #define SIGMA_MIN 1e-6
@@ -509,7 +510,7 @@ void orc_grid_op(const orc_scene *s, const double *gm, const double *gp, double 
                 for (int a = 0; a < 3; a++) v[a] = gm[idx] > 0 ? gp[3 * idx + a] / gm[idx] : 0.0;
                 for (int a = 0; a < 3; a++) v[a] += s->dt * s->g[a];
                 double xi[3] = {i * s->dx, j * s->dx, k * s->dx};
-                for (int c = 0; c < s->n_col; c++) {
+                for (int c = 0; c < s->n_col && s->contact != 1; c++) {
                     double v0[3] = {v[0], v[1], v[2]};
                     if (!orc_collide(&s->col[c], xi, v) || !s->wrench) continue;
                     double dp[3], r[3], t[3];
@@ -532,12 +533,43 @@ void orc_grid_op(const orc_scene *s, const double *gm, const double *gp, double 
             }
 }
 
+/* Particle penalty contact (the paper's default contact model, Sec. 3; its
+ * stiffness is not printed): a particle found inside collider c after its
+ * position update (phi < 0 at the substep's pose) receives the velocity
+ * change -phi n / (4 dt), a spring of stiffness m / (4 dt^2) along the
+ * outward normal that removes a quarter of the penetration per substep; the
+ * collider receives the opposite impulse and angular impulse about its
+ * centre (summed into s->wrench when set). */
+static void penalty(orc_scene *s, const double *x, double *v)
+{
+    double m = s->rho * s->p_vol;
+    for (int c = 0; c < s->n_col; c++) {
+        double n[3];
+        double phi = orc_sdf(&s->col[c], x, n);
+        if (!(phi < 0.0)) continue;
+        double dp[3], r[3], t[3];
+        for (int a = 0; a < 3; a++) {
+            double dv = -phi * n[a] / (4.0 * s->dt);
+            v[a] += dv;
+            dp[a] = m * dv;
+            r[a] = x[a] - s->col[c].pos[a];
+        }
+        if (!s->wrench) continue;
+        cross3(r, dp, t);
+        for (int a = 0; a < 3; a++) {
+            s->wrench[6 * c + a] -= dp[a];
+            s->wrench[6 * c + 3 + a] -= t[a];
+        }
+    }
+}
+
 /* Grid to particle, particle integration and return map. */
 int orc_g2p(orc_scene *s, const double *vg)
 {
     int err = 0;
     double D = 4.0 / (s->dx * s->dx);
-#pragma omp parallel for schedule(static) reduction(min : err)
+    /* with penalty wrenches summed, particles run in order (one accumulator) */
+#pragma omp parallel for schedule(static) reduction(min : err) if (!(s->wrench && s->contact != 0))
     for (int p = 0; p < s->n; p++) {
         int base[3];
         double f[3], w[3][3];
@@ -560,6 +592,7 @@ int orc_g2p(orc_scene *s, const double *vg)
         for (int i = 0; i < 3; i++) v[i] = nv[i];
         for (int i = 0; i < 9; i++) C[i] = D * B[i];
         for (int i = 0; i < 3; i++) x[i] += s->dt * v[i];
+        if (s->contact != 0) penalty(s, x, v);
         double M[9];
         for (int i = 0; i < 9; i++) M[i] = (i % 4 == 0 ? 1.0 : 0.0) + s->dt * C[i];
         matmul(M, F, F);

@@ -157,8 +157,9 @@ def test_substep_conserves_momenta(orc, model):
     assert np.allclose(L1, L0, rtol=0, atol=1e-12 * scale)
 
 
+@pytest.mark.parametrize("contact", [0, 1, 2])
 @pytest.mark.parametrize("model", [scenes.NEO_HOOKEAN, scenes.HENCKY_VM])
-def test_collider_wrench_is_what_the_material_receives(orc, model):
+def test_collider_wrench_is_what_the_material_receives(orc, model, contact):
     """Two-way coupling (Algorithm 1 accumulates the soft body's forces on
     the rigid bodies), pinned by Newton's third law: with gravity off and
     the walls out of reach, only the colliders change the material's
@@ -166,10 +167,15 @@ def test_collider_wrench_is_what_the_material_receives(orc, model):
     angular momentum (the APIC form, C included) equals minus the impulse
     and minus the angular impulse about the origin that the colliders
     receive (their angular impulse about their own centre plus c x J, at
-    the substep's pose).  Moving, rotating box and capsule."""
+    the substep's pose).  Moving, rotating box and capsule; grid-node
+    projection, particle penalty, and both."""
     sc = replace(scenes.small_scene(7, n=400, res=16, model=model, speed=0.8, omega=3.0, n_ctrl=1, dt=2e-4),
                  gravity=(0.0, 0.0, 0.0))
-    o = orc.Oracle(sc, wrench=True)
+    if contact != 0:
+        # the colliders start inside the blob: penalty kicks are large, so no walls (they are
+        # not bodies and would take momentum) and fewer substeps (nothing leaves the grid)
+        sc = replace(sc, bound=0)
+    o = orc.Oracle(sc, wrench=True, contact=contact)
     o.set_colliders(sc.ctrl_poses[0], sc.ctrl_vels[0])
     m = sc.rho * sc.particle_volume
 
@@ -179,7 +185,7 @@ def test_collider_wrench_is_what_the_material_receives(orc, model):
         return m * o.v.sum(0), (m * (np.cross(o.x, o.v) + sc.dx ** 2 / 4 * vec)).sum(0)
 
     touched = 0.0
-    for _ in range(30):
+    for _ in range(30 if contact == 0 else 10):
         P0, L0 = momenta()
         c = o.collider_poses()[:, :3].copy()
         o.step(1)
@@ -191,6 +197,29 @@ def test_collider_wrench_is_what_the_material_receives(orc, model):
         assert np.allclose(L1 - L0, -(T + np.cross(c, J)).sum(0), rtol=0, atol=1e-11 * scale)
         touched += np.abs(J).sum()
     assert touched > 1e-3 * m * sc.n, "the colliders never touched the material"
+
+
+def test_penalty_closed_form(orc):
+    """Particle penalty contact: one particle at rest inside a static box,
+    gravity off, projection off: the transfers return its velocity
+    unchanged (single-particle round trip), so after the substep it carries
+    exactly -phi n / (4 dt) for the distance phi < 0 and normal n at its
+    position, and the box receives minus that momentum."""
+    box = scenes.ColliderShape(scenes.BOX, (0.1, 0.06, 0.08))
+    sc = _scene(n=1, res=16)
+    sc = replace(sc, x=np.array([[0.52, 0.47, 0.51]], np.float32), v=np.zeros((1, 3), np.float32),
+                 colliders=[box], ctrl_poses=np.array([[[0.5, 0.5, 0.5, 1.0, 0.0, 0.0, 0.0]]], np.float32),
+                 ctrl_vels=np.zeros((1, 1, 6), np.float32))
+    o = orc.Oracle(sc, wrench=True, contact=1)
+    o.set_colliders(sc.ctrl_poses[0], sc.ctrl_vels[0])
+    c = orc.make_collider(box, sc.ctrl_poses[0, 0])
+    phi, n = orc.sdf(c, o.x[0].copy())
+    assert phi < 0
+    o.step(1)
+    dv = -phi * n / (4 * sc.dt)
+    assert np.allclose(o.v[0], dv, rtol=1e-12, atol=1e-12)
+    m = sc.rho * sc.particle_volume
+    assert np.allclose(o.take_wrench()[0, :3], -m * dv, rtol=1e-12, atol=1e-15)
 
 
 def test_collider_wrench_zero_without_contact(orc):
