@@ -199,7 +199,12 @@ typedef enum {
     MPM_OPT_PERSISTENT = 3,     /* 1: one persistent launch per substep; 0: three launches */
     MPM_OPT_GRAPH = 4,          /* 1: replay a captured hipGraph for 25-substep blocks */
     MPM_OPT_CAPTURE_GRID = 5,   /* 1: keep the last P2G grid for mpm_get_grid (slow, debug) */
-    MPM_OPT_TIMING = 6          /* 1: time every kernel launch with HIP events (see mpm_get_timing) */
+    MPM_OPT_TIMING = 6,         /* 1: time every kernel launch with HIP events (see mpm_get_timing) */
+    MPM_OPT_CONTACT = 7         /* collider contact, default 0 (Sec. 3 names both models):
+                                 * 0: on grid nodes (separating projection with Coulomb friction);
+                                 * 1: particle penalty: a particle inside a collider after its
+                                 *    position update gets -phi n / (4 dt) (stiffness m / (4 dt^2));
+                                 * 2: both.  Either reaction goes into mpm_get_collider_wrenches. */
 } mpm_option;
 
 /* Kernel classes reported by mpm_get_timing. */

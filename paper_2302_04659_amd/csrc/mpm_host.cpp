@@ -105,6 +105,7 @@ struct mpm_ctx_s {
     long long cap_nodes = 0;
 
     int persistent = 0, graph = 0;
+    int contact = 0;                 // MPM_OPT_CONTACT
     std::map<GraphKey, GraphEntry> graphs;
 
     // per-kernel-class timing with HIP events on the context stream
@@ -379,6 +380,7 @@ StepArgs step_args(mpm_ctx ctx, int substep)
     a.keep_bound = 0;
     a.wrench = ctx->d_wrench;
     a.sdf = ctx->d_sdf;
+    a.contact = ctx->contact;
     return a;
 }
 
@@ -976,6 +978,11 @@ mpm_status mpm_set_option(mpm_ctx ctx, int option, int value)
         ARGCHK(value == 0 || value == 1, "graph must be 0 or 1");
         ctx->graph = value;
         return MPM_OK;
+    case MPM_OPT_CONTACT:
+        ARGCHK(value >= 0 && value <= 2, "contact must be 0, 1 or 2");
+        ctx->contact = value;
+        clear_graphs(ctx);   // the captured kernels depend on it
+        return MPM_OK;
     case MPM_OPT_CAPTURE_GRID:
         ARGCHK(value == 0 || value == 1, "capture must be 0 or 1");
         if (value && !ctx->d_cap) {
@@ -1002,6 +1009,7 @@ mpm_status mpm_get_option(mpm_ctx ctx, int option, int *value)
     case MPM_OPT_CHUNK: *value = ctx->CH; return MPM_OK;
     case MPM_OPT_PERSISTENT: *value = ctx->persistent; return MPM_OK;
     case MPM_OPT_GRAPH: *value = ctx->graph; return MPM_OK;
+    case MPM_OPT_CONTACT: *value = ctx->contact; return MPM_OK;
     case MPM_OPT_CAPTURE_GRID: *value = ctx->capture; return MPM_OK;
     case MPM_OPT_TIMING: *value = ctx->timing; return MPM_OK;
     }

@@ -601,7 +601,7 @@ __device__ void grid_block(const StepArgs &a, int s, int lb, int lane, ColliderN
         }
         for (int d = 0; d < 3; d++) v[d] += gdt[d];
         float xi[3] = {ii[0] * K.dx, ii[1] * K.dx, ii[2] * K.dx};
-        for (int c = 0; c < n_col; c++) {
+        for (int c = 0; c < (a.contact == 1 ? 0 : n_col); c++) {   // contact 1: particle penalty only
             const float v0[3] = {v[0], v[1], v[2]};
             const bool hit = collide_node(cl[c], xi, v, a.sdf) && live && m > 0.0f;
             // two-way coupling: the collider receives minus the momentum its projection gives
@@ -673,7 +673,8 @@ __global__ __launch_bounds__(WG, (B == 8 && !EXTRA) ? 7 : 1) void k_grid(StepArg
 }
 
 // ---------------------------------------------------------------- G2P + integration
-template <int B, bool PF>
+// PEN: particle penalty contact after the position update (MPM_OPT_CONTACT 1 or 2).
+template <int B, bool PF, bool PEN>
 __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt, float *pf)
 {
     constexpr int T = B + 4, T3 = T * T * T;
@@ -730,6 +731,13 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
     __syncthreads();
     int bad_any = 0, cl_any = 0;
     float bnd = 0.0f;
+    // penalty contact: this substep's collider poses of the scene (uniform), the per-lane sums of
+    // the momentum and its moment given to the particles, and which colliders were touched
+    const ColliderNow *cn = (const ColliderNow *)a.colnow + S.col_off;
+    const int pen_ncol = PEN ? uniform_i(S.n_col) : 0;
+    const float pen_rate = 0.25f / K.dt;
+    float pacc[PEN ? MAX_COLLIDERS_PER_SCENE : 1][6] = {};
+    unsigned pen_hit = 0;
     // wave-uniform loop: lane li = k0 + lane of each 64-particle batch
     for (int k0 = t - lane; k0 < item.count; k0 += WG) {
         const int li = k0 + lane;
@@ -823,6 +831,34 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
             for (int e = 0; e < 3; e++) C[3 * c + e] = Dd * fmaf(-vp[c], f[e], So[c][e]);
 #pragma unroll
         for (int d = 0; d < 3; d++) x[d] = fmaf(K.dt, vp[d], x[d]);
+        if (PEN) {
+            // inside collider c at the new position: v += -phi n / (4 dt), a spring of stiffness
+            // m / (4 dt^2) along the outward normal (the stored v, hence the next scatter bound,
+            // includes it)
+#pragma unroll
+            for (int c = 0; c < (PEN ? MAX_COLLIDERS_PER_SCENE : 1); c++) {
+                if (c >= pen_ncol) break;
+                float nrm[3];
+                const float phi = sdf_eval(cn[c], x, nrm, a.sdf);
+                if (phi < 0.0f) {
+                    float dp[3], r[3];
+#pragma unroll
+                    for (int d = 0; d < 3; d++) {
+                        const float dv = -phi * pen_rate * nrm[d];
+                        vp[d] += dv;
+                        dp[d] = K.mass * dv;
+                        r[d] = x[d] - cn[c].c[d];
+                    }
+                    pacc[c][0] += dp[0];
+                    pacc[c][1] += dp[1];
+                    pacc[c][2] += dp[2];
+                    pacc[c][3] += r[1] * dp[2] - r[2] * dp[1];
+                    pacc[c][4] += r[2] * dp[0] - r[0] * dp[2];
+                    pacc[c][5] += r[0] * dp[1] - r[1] * dp[0];
+                    pen_hit |= 1u << c;
+                }
+            }
+        }
         // F <- (I + dt C) F  ->  G <- G + dt C + dt C G
         float Gt[9];
 #pragma unroll
@@ -869,12 +905,27 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
     }
     bnd = wave_max(bnd);
     if ((t & 63) == 0 && bnd > 0.0f) atomicMax((int *)(a.L.ibound + it), __float_as_int(bnd));
+    if (PEN && a.wrench) {
+        // the colliders receive minus what the penalty gave the particles: one wave sum and
+        // one atomic per component, for the colliders a lane of the wave touched
+#pragma unroll
+        for (int c = 0; c < (PEN ? MAX_COLLIDERS_PER_SCENE : 1); c++) {
+            if (c >= pen_ncol) break;
+            if (!__any((pen_hit >> c) & 1u)) continue;
+            float tot[6];
+#pragma unroll
+            for (int j = 0; j < 6; j++) tot[j] = wave_total(pacc[c][j]);
+            if ((t & 63) == 0)
+#pragma unroll
+                for (int j = 0; j < 6; j++) atomicAdd(a.wrench + 6 * (long long)(S.col_off + c) + j, -tot[j]);
+        }
+    }
     if (bad_any) atomicOr(a.flags + s, (int)FLAG_NONFINITE);
     if (cl_any) atomicOr(a.flags + s, (int)FLAG_CLAMPED);
     __syncthreads();
 }
 
-template <int B>
+template <int B, bool PEN>
 __global__ __launch_bounds__(WG, 4) void k_g2p(StepArgs a)
 {
     constexpr int T = B + 4, T3 = T * T * T;
@@ -887,7 +938,7 @@ __global__ __launch_bounds__(WG, 4) void k_g2p(StepArgs a)
     for (int it = xcd_remap(blockIdx.x, G); it < n_items; it += G) {
         Item item = a.L.items[it];
         if (!a.active[item.scene]) continue;
-        g2p_item<B, true>(a, it, item, vt, pf);
+        g2p_item<B, true, PEN>(a, it, item, vt, pf);
     }
 }
 
@@ -917,8 +968,14 @@ hipError_t launch_grid(const StepArgs &a, int n_wg, hipStream_t st)
 hipError_t launch_g2p(const StepArgs &a, int n_wg, hipStream_t st)
 {
     n_wg = (n_wg + 7) & ~7;
-    if (a.B == 4) k_g2p<4><<<n_wg, WG, 0, st>>>(a);
-    else k_g2p<8><<<n_wg, WG, 0, st>>>(a);
+    const bool pen = a.contact != 0;
+    if (a.B == 4) {
+        if (pen) k_g2p<4, true><<<n_wg, WG, 0, st>>>(a);
+        else k_g2p<4, false><<<n_wg, WG, 0, st>>>(a);
+    } else {
+        if (pen) k_g2p<8, true><<<n_wg, WG, 0, st>>>(a);
+        else k_g2p<8, false><<<n_wg, WG, 0, st>>>(a);
+    }
     return hipGetLastError();
 }
 
@@ -1007,7 +1064,7 @@ __global__ __launch_bounds__(WG) void k_substep_persistent(StepArgs a)
             if (threadIdx.x == 0)
                 wait_counter(&grid_done[s], a.L.scene_gitem_begin[s + 1] - a.L.scene_gitem_begin[s] + 1, a.flags + s);
             __syncthreads();
-            g2p_item<B, false>(a, qi, item, (float *)smem, nullptr);
+            g2p_item<B, false, false>(a, qi, item, (float *)smem, nullptr);
         }
     }
     if (threadIdx.x == 0) {

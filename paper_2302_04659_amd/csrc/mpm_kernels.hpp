@@ -33,6 +33,7 @@ struct StepArgs {
     int sur_box[3];           //   null = the whole grid (res^3 per scene, offset cap_off[s])
     float *out_mass;          // per scene: P2G mass the grid update found outside the box (added), or null
     const float *sdf;         // samples of the SDF-volume colliders (ColliderNow::sdf_off into it)
+    int contact;              // 0 grid-node projection, 1 particle penalty (in G2P), 2 both
     float *wrench;            // per collider (global index): [6] impulse and angular impulse about its centre
                               //   received from the material, summed over grid updates (or null)
 };

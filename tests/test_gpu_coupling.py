@@ -145,3 +145,55 @@ def test_sdf_volume_collider_matches_oracle(mpm, orc, model):
     assert err <= 1e-3
     assert wmax > 0.0, "the material never touched the beaker"
     sim.close()
+
+
+def _approach_scene(seed, model):
+    """A box starting 2 mm off a blob's +x face, moving into it at 1 m/s."""
+    sc = scenes.small_scene(500 + seed, n=3000, res=32, model=model, n_ctrl=2, dt=1e-4)
+    box = scenes.ColliderShape(scenes.BOX, (0.08, 0.12, 0.12), friction=0.5)
+    c0 = np.array([float(sc.x[:, 0].max()) + 0.08 + 0.002, 0.5, 0.5])
+    vel = np.array([-1.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+    poses = np.zeros((2, 1, 7), np.float32)
+    vels = np.zeros((2, 1, 6), np.float32)
+    for k in range(2):
+        poses[k, 0, :3] = c0 + vel[:3] * 25 * k * sc.dt
+        poses[k, 0, 3] = 1.0
+        vels[k, 0] = vel
+    return replace(sc, colliders=[box], ctrl_poses=poses, ctrl_vels=vels)
+
+
+@pytest.mark.parametrize("contact,graph", [(1, 0), (2, 1)])
+def test_penalty_contact_matches_oracle(mpm, orc, contact, graph):
+    """Particle penalty contact (alone, and with the grid-node projection):
+    positions after two control steps (1e-3 dx) and the wrenches per control
+    step against the oracle, a box pressing into Hencky and fluid blobs."""
+    batch = [_approach_scene(0, scenes.HENCKY_VM), _approach_scene(1, scenes.FLUID)]
+    announce("penalty contact", contact, "graph", graph)
+    sim = mpm.Sim(batch)
+    sim.set_option(mpm.OPT_CONTACT, contact)
+    sim.set_option(mpm.OPT_GRAPH, graph)
+    assert sim.get_option(mpm.OPT_CONTACT) == contact
+    orcs = [orc.Oracle(sc, wrench=True, contact=contact) for sc in batch]
+    wmax = 0.0
+    for k in range(2):
+        sim.set_colliders_ctrl(k)
+        sim.step(25)
+        assert sim.sync() == mpm.OK
+        W = sim.collider_wrenches()
+        for s, (sc, o) in enumerate(zip(batch, orcs)):
+            o.set_colliders(sc.ctrl_poses[k], sc.ctrl_vels[k])
+            o.step(25)
+            r = o.take_wrench()[0]
+            g = W[s, 0].astype(np.float64)
+            wmax = max(wmax, np.abs(r).max())
+            print("contact", contact, "step", k, "scene", s, "wrench gpu", g[:3], "oracle", r[:3])
+            assert (np.abs(g - r) <= 2e-3 * np.abs(r).max() + 1e-4 * wmax).all(), (k, s, g, r)
+    for s, (sc, o) in enumerate(zip(batch, orcs)):
+        x, _, _, _ = sim.get_state(s)
+        err = np.abs(x - o.x).max() / sc.dx
+        print("contact", contact, "scene", s, "max |dx| / dx", err)
+        assert err <= 1e-3
+    assert wmax > 0.0, "the box never reached the blobs"
+    with pytest.raises(mpm.MPMError):
+        sim.set_option(mpm.OPT_CONTACT, 3)
+    sim.close()
