@@ -149,7 +149,9 @@ mpm_status mpm_set_colliders(mpm_ctx ctx, const float *poses, const float *veloc
  * substep is minus the momentum its projection gives the material,
  * -sum_i m_i (v_i after - v_i before) over the nodes it touches, and its
  * angular impulse about its own centre (at that substep's pose) is
- * -sum_i (x_i - c_k) x m_i (v_i after - v_i before).  out
+ * -sum_i (x_i - c_k) x m_i (v_i after - v_i before); with particle penalty
+ * contact (MPM_OPT_CONTACT 1 or 2) the particles inside it add -m_p dv_p and
+ * -(x_p - c_k) x m_p dv_p in the same way.  out
  * [n_scenes][max_colliders][6] = impulse xyz (N s), angular impulse xyz
  * (N m s), summed over every substep since the previous call (or since
  * mpm_create); entries past a scene's own collider count are zero.  Divide
