@@ -176,6 +176,18 @@ mpm_status mpm_sync(mpm_ctx ctx);
  * order.  x: [n][3]; v: [n][3] or NULL; F: [n][3][3] or NULL. */
 mpm_status mpm_get_particles(mpm_ctx ctx, int scene, float *x, float *v, float *F, int on_device);
 
+/* Zero-copy view of the particle positions for a consumer on the same GPU (a
+ * renderer: App. C.2 hands the particles over on the GPU rather than through
+ * the host).  *x, *y, *z receive device pointers to the current x, y and z
+ * coordinates in the library's internal order (sorted by grid block, not
+ * creation order); scene s holds slots [slot_begin[s], slot_begin[s + 1])
+ * when slot_begin (host, n_scenes + 1 ints) is not NULL.  Read-only, and
+ * valid only until the next call that steps or changes the state (mpm_step,
+ * mpm_sur_block, mpm_set_state, mpm_autotune): a re-sort moves the
+ * particles to the other buffer.  Synchronise the context stream before
+ * reading. */
+mpm_status mpm_particle_view(mpm_ctx ctx, const float **x, const float **y, const float **z, int *slot_begin);
+
 /* Full particle state (checkpoint / teacher forcing): x, v [n][3]; affine
  * velocity C and deformation gradient F [n][3][3] of one scene or all
  * (scene = -1).  mpm_set_state replaces that state (all four arrays are

@@ -885,6 +885,21 @@ mpm_status mpm_get_particles(mpm_ctx ctx, int scene, float *x, float *v, float *
     return mpm_get_state(ctx, scene, x, v, nullptr, F, on_device);
 }
 
+mpm_status mpm_particle_view(mpm_ctx ctx, const float **x, const float **y, const float **z, int *slot_begin)
+{
+    ARGCHK(ctx, "null context");
+    ARGCHK(x && y && z, "x, y and z must not be NULL");
+    const float *P = ctx->d_P[ctx->cur];
+    *x = P + (long long)X0 * ctx->pstride;
+    *y = P + (long long)X1 * ctx->pstride;
+    *z = P + (long long)X2 * ctx->pstride;
+    if (slot_begin) {
+        for (int s = 0; s < ctx->n_scenes; s++) slot_begin[s] = ctx->h_scenes[s].p_begin;
+        slot_begin[ctx->n_scenes] = ctx->n_scenes ? ctx->h_scenes[ctx->n_scenes - 1].p_end : 0;
+    }
+    return MPM_OK;
+}
+
 mpm_status mpm_set_state(mpm_ctx ctx, int scene, const float *x, const float *v, const float *C, const float *F,
                          int on_device)
 {

@@ -66,6 +66,7 @@ def lib():
         L.mpm_destroy.argtypes = [vp]
         L.mpm_set_colliders.argtypes = [vp, vp, vp, ct.c_int]
         L.mpm_get_collider_wrenches.argtypes = [vp, vp, ct.c_int]
+        L.mpm_particle_view.argtypes = [vp, ct.POINTER(vp), ct.POINTER(vp), ct.POINTER(vp), ct.POINTER(ct.c_int)]
         L.mpm_step.argtypes = [vp, ct.c_int]
         L.mpm_sync.argtypes = [vp]
         L.mpm_get_particles.argtypes = [vp, ct.c_int, vp, vp, vp, ct.c_int]
@@ -201,6 +202,15 @@ class Sim:
         P = _f32(poses, (self.n_scenes, self.max_col, 7))
         V = _f32(vels, (self.n_scenes, self.max_col, 6))
         return self._check(self.L.mpm_set_colliders(self.h, P.ctypes.data, V.ctypes.data, 0), "set_colliders")
+
+    def particle_view(self):
+        """Device pointers (ints) of the x, y, z position arrays in internal
+        order, and the per-scene slot ranges [n_scenes + 1]."""
+        px, py, pz = ct.c_void_p(), ct.c_void_p(), ct.c_void_p()
+        begin = (ct.c_int * (self.n_scenes + 1))()
+        self._check(self.L.mpm_particle_view(self.h, ct.byref(px), ct.byref(py), ct.byref(pz), begin),
+                    "particle_view")
+        return px.value, py.value, pz.value, np.array(begin[:], np.int64)
 
     def collider_wrenches(self):
         """[n_scenes][max_colliders][6]: impulse and angular impulse (about

@@ -197,3 +197,35 @@ def test_penalty_contact_matches_oracle(mpm, orc, contact, graph):
     with pytest.raises(mpm.MPMError):
         sim.set_option(mpm.OPT_CONTACT, 3)
     sim.close()
+
+
+def test_particle_view_is_the_state(mpm):
+    """The zero-copy position view (internal order) holds, scene by scene, the
+    same positions as the creation-order read-out, after a control step with
+    re-sorts."""
+    import ctypes as ct
+    batch = _batch()
+    announce("particle view", len(batch))
+    sim = mpm.Sim(batch)
+    sim.set_option(mpm.OPT_SORT_EVERY, 7)
+    sim.set_colliders_ctrl(0)
+    sim.step(25)
+    assert sim.sync() == mpm.OK
+    px, py, pz, begin = sim.particle_view()
+    assert begin[0] == 0 and begin[-1] == sum(sc.n for sc in batch)
+    hip = ct.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_int]
+    n = int(begin[-1])
+    view = np.zeros((3, n), np.float32)
+    for a, p in enumerate((px, py, pz)):
+        assert hip.hipMemcpy(view[a].ctypes.data, p, 4 * n, 2) == 0    # device to host
+    x_all, _, _, _ = sim.get_state(-1)
+    off = 0
+    for s, sc in enumerate(batch):
+        mine = view[:, begin[s]: begin[s + 1]].T
+        ref = x_all[off: off + sc.n]
+        off += sc.n
+        assert mine.shape == ref.shape
+        order = lambda a: a[np.lexsort((a[:, 2], a[:, 1], a[:, 0]))]
+        assert np.array_equal(order(mine), order(ref)), s
+    sim.close()
