@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
         bool ok[4];
 #pragma unroll
         for (int f = 0; f < 4; f++) {
-            int sz, sy, sx;
+            int sz = 0, sy = 0, sx = 0;
             ok[f] = vok[f] && tap_source(a.kind, vz[f], vy[f], vx[f], ta, tb, tc, a.id, a.ih, a.iw, sz, sy, sx);
             src[f] = ok[f] ? ((((long long)vn[f] * a.id + sz) * a.ih + sy) * a.iw + sx) * a.cx + a.x_off + kq : 0;
         }
@@ -587,7 +587,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
             q /= a.oh;
             int z = (int)(q % a.od);
             int nn = (int)(q / a.od);
-            int sz, sy, sx;
+            int sz = 0, sy = 0, sx = 0;
             ok[r] = ok[r] && tap_source(a.kind, z, y, x, ta, tb, tc, a.id, a.ih, a.iw, sz, sy, sx);
             src[r] = ((((long long)nn * a.id + sz) * a.ih + sy) * a.iw + sx) * a.cx + a.x_off;
             dst[r] = v * a.cg + a.g_off;
