@@ -98,3 +98,27 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=300, cwd=root)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr), r.stdout + r.stderr
+
+
+def test_traffic_summaries_match_current_kernel_sources():
+    """The committed HBM-traffic summaries were taken on the kernel sources in
+    the tree (else the benchmark reports their traffic as null), and each
+    summary's byte total follows from its own counter readings and copy
+    calibration."""
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    for kernel in ("g2p", "p2g", "grid"):
+        total = bench.kernel_traffic(kernel, "cfg3")
+        assert total is not None, f"{kernel}: summary missing or taken on other kernel sources"
+        vals = {}
+        for line in open(os.path.join(root, "profiles", f"{kernel}_cfg3_traffic.txt")):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = float(v.split("#")[0]) if k.strip() not in ("kernel", "workload",
+                                                                             "kernel_source_sha256_16") else v
+        rd = vals["fetch_size_kib_per_dispatch"] * 1024 / vals["copy_probe_fetch_factor"]
+        wr = vals["write_size_kib_per_dispatch"] * 1024 / vals["copy_probe_write_factor"]
+        assert abs(rd + wr - total) <= 1e-3 * total, (kernel, rd + wr, total)
