@@ -110,15 +110,15 @@ def test_traffic_summaries_match_current_kernel_sources():
     spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
     bench = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(bench)
-    for kernel in ("g2p", "p2g", "grid"):
-        total = bench.kernel_traffic(kernel, "cfg3")
-        assert total is not None, f"{kernel}: summary missing or taken on other kernel sources"
+    for kernel, wl in [(k, w) for w in ("cfg3", "cfg4") for k in ("g2p", "p2g", "grid")]:
+        total = bench.kernel_traffic(kernel, wl)
+        assert total is not None, f"{kernel} {wl}: summary missing or taken on other kernel sources"
         vals = {}
-        for line in open(os.path.join(root, "profiles", f"{kernel}_cfg3_traffic.txt")):
+        for line in open(os.path.join(root, "profiles", f"{kernel}_{wl}_traffic.txt")):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = float(v.split("#")[0]) if k.strip() not in ("kernel", "workload",
                                                                              "kernel_source_sha256_16") else v
         rd = vals["fetch_size_kib_per_dispatch"] * 1024 / vals["copy_probe_fetch_factor"]
         wr = vals["write_size_kib_per_dispatch"] * 1024 / vals["copy_probe_write_factor"]
-        assert abs(rd + wr - total) <= 1e-3 * total, (kernel, rd + wr, total)
+        assert abs(rd + wr - total) <= 1e-3 * total, (kernel, wl, rd + wr, total)
