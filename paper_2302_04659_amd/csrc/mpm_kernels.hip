@@ -315,7 +315,10 @@ __global__ __launch_bounds__(WG) void k_item_bounds(SortArgs a)
         b = wave_max(b);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
         __syncthreads();
-        if (threadIdx.x == 0) a.L.ibound[it] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        if (threadIdx.x == 0) {
+            a.L.ibound[it] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+            a.L.icell[it] = 0;   // per-cell counts unknown: the next P2G counts
+        }
         __syncthreads();
     }
 }
@@ -412,16 +415,28 @@ __device__ void write_colliders_now(const StepArgs &a, const SceneDev &S)
 constexpr float RND = 12582912.0f;
 constexpr unsigned long long RND_PAIR = 0x4B4000004B400000ull;   // RND's bits in both halves
 
+// Base cells a particle of a P2G tile can have: (B + 2)^3 (tile coordinates 0 .. B + 1).
+template <int B> constexpr int p2g_cells() { return (B + 2) * (B + 2) * (B + 2); }
+
+// Items with more particles than this count their particles per base cell
+// before scattering (below it the per-term limit already sets the scale).
+constexpr int P2G_COUNT_MIN = 256;
+
 template <int B>
-__device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
+__device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile, int *cells)
 {
-    constexpr int T = B + 4, T3 = T * T * T;
+    constexpr int T = B + 4, T3 = T * T * T, NC = p2g_cells<B>();
     const int t = threadIdx.x;
     const int s = item.scene;
     const SceneDev &S = a.scenes[s];
     const int nb = S.nb;
     const int bx = item.block / (nb * nb), by = (item.block / nb) % nb, bz = item.block % nb;
     const int org[3] = {bx * B - 1, by * B - 1, bz * B - 1};
+    const SceneK K = scene_k(S);
+    // largest particle count of a base cell, left by the G2P that moved the
+    // particles (0 after a re-sort or a surrogate step: count here)
+    const int known = item.count > P2G_COUNT_MIN ? a.L.icell[it] : 0;
+    const bool count_cells = item.count > P2G_COUNT_MIN && known <= 0;
 
     // LDS tile: per node two 64-bit sums, (p_x, m) and (p_y, p_z) as (hi, lo),
     // each the exact sum of 32-bit fixed-point terms packed as hi * 2^32 + lo
@@ -429,17 +444,55 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile)
     // 32 bits)
     long long *t64 = (long long *)tile;
     for (int n = t; n < 2 * T3; n += WG) t64[n] = 0;
+    if (count_cells) {
+        for (int n = t; n < NC + 1; n += WG) cells[n] = 0;   // cells[NC]: the maximum
+    }
     // bound of this item's particles, left by the previous G2P (or the sort)
     const float bmax = a.L.ibound[it];
     if (it == a.L.scene_item_begin[s]) write_colliders_now(a, S);
     __syncthreads();
     if (t == 0 && !a.keep_bound) a.L.ibound[it] = 0.0f;   // this substep's G2P accumulates the next bound
 
+    // Node sums of weights: a node receives w <= 0.5, 0.75, 0.5 per axis from
+    // particles whose base cell is 0, 1, 2 cells below it, so the weights
+    // reaching one node add up to at most 1.75^3 = 5.359375 times the largest
+    // number of particles sharing a base cell (and never more than
+    // 0.421875 * count).  Large items count their particles per base cell
+    // first (the same in-tile test as the scatter below).
+    float wsum = 0.421875f * (float)item.count;
+    if (count_cells) {
+        for (int base = 0; base < item.count; base += WG) {
+            const int li = base + t;
+            if (li >= item.count) break;
+            const unsigned jo = (unsigned)(item.start + li) << 2;
+            int cl = 0, in = 1, c = 0;
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                int bp;
+                float f;
+                particle_base(K, pload(a.P, a.pstride, X0 + d, jo), bp, f, cl);
+                const int tb = bp - org[d];
+                in &= (tb >= 0) & (tb <= B + 1);
+                c = c * (B + 2) + tb;
+            }
+            if (in && !cl) atomicAdd(cells + c, 1);
+        }
+        __syncthreads();
+        int mx = 0;
+        for (int n = t; n < NC; n += WG) mx = max(mx, cells[n]);
+        mx = wave_max_i(mx);
+        if ((t & 63) == 0) atomicMax(cells + NC, mx);
+        __syncthreads();
+        wsum = fminf(wsum, 5.359375f * (float)max(cells[NC], 1));
+    } else if (known > 0) {
+        wsum = fminf(wsum, 5.359375f * (float)known);
+    }
+
     // Power-of-two fixed-point scales keeping every node sum below 2^30:
-    // |contribution| <= w * bound, w <= 0.421875, at most item.count particles;
-    // and every single term within 2^22 (rounded by the RND addition below).
-    const SceneK K = scene_k(S);
-    const float lim = fminf(1073741824.0f / (0.421875f * (float)item.count), 4194304.0f / 0.421875f);
+    // |contribution| <= w * bound with the weights of a node summing to at
+    // most wsum; and every single term within 2^22 (w <= 0.421875; rounded by
+    // the RND addition below).
+    const float lim = fminf(1073741824.0f / wsum, 4194304.0f / 0.421875f);
     int em = ilogbf(lim / K.mass);
     em = min(max(em, -120), 120);
     int ep = bmax > 0.0f ? ilogbf(lim / bmax) : 120;
@@ -536,6 +589,7 @@ __global__ __launch_bounds__(WG) void k_p2g(StepArgs a)
 {
     constexpr int T = B + 4, T3 = T * T * T;
     __shared__ __align__(16) int tile[4 * T3];
+    __shared__ int cells[p2g_cells<B>() + 1];
     const int n_items = *a.L.n_items;
     const int G = active_wgs(n_items);
     if ((int)blockIdx.x >= G) return;
@@ -545,7 +599,7 @@ __global__ __launch_bounds__(WG) void k_p2g(StepArgs a)
         const int it = n_items - 1 - r;
         Item item = a.L.items[it];
         if (!a.active[item.scene]) continue;
-        p2g_item<B>(a, it, item, tile);
+        p2g_item<B>(a, it, item, tile, cells);
     }
 }
 
@@ -674,10 +728,13 @@ __global__ __launch_bounds__(WG, (B == 8 && !EXTRA) ? 7 : 1) void k_grid(StepArg
 
 // ---------------------------------------------------------------- G2P + integration
 // PEN: particle penalty contact after the position update (MPM_OPT_CONTACT 1 or 2).
+// cells: LDS of p2g_cells<B>() + 1 ints; the item's particles are counted per
+// base cell of their new position (as the next P2G's tile sees them) and the
+// largest count is left in L.icell[it] for that P2G's fixed-point scale.
 template <int B, bool PF, bool PEN>
-__device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt, float *pf)
+__device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt, float *pf, int *cells)
 {
-    constexpr int T = B + 4, T3 = T * T * T;
+    constexpr int T = B + 4, T3 = T * T * T, NC = p2g_cells<B>();
     const int t = threadIdx.x;
     const int s = item.scene;
     const SceneDev &S = a.scenes[s];
@@ -691,6 +748,7 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
     // the compiler, which would reload them after each one)
     const Material mat = material_of(S);
     const SceneK K = scene_k(S);
+    for (int n = t; n < NC + 1; n += WG) cells[n] = 0;
     if (PF) {
         const int res = uniform_i(S.res);
         const SceneDev Sg = {0, 0, res, uniform_i(S.nb), uniform_ll(S.grid_off)};
@@ -831,6 +889,20 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
             for (int e = 0; e < 3; e++) C[3 * c + e] = Dd * fmaf(-vp[c], f[e], So[c][e]);
 #pragma unroll
         for (int d = 0; d < 3; d++) x[d] = fmaf(K.dt, vp[d], x[d]);
+        {
+            // base cell of the new position in this item's P2G tile
+            int c = 0, inn = 1, cln = 0;
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                int bn;
+                float fn;
+                particle_base(K, x[d], bn, fn, cln);
+                const int tb = bn - org[d];
+                inn &= (tb >= 0) & (tb <= B + 1);
+                c = c * (B + 2) + tb;
+            }
+            if (inn && !cln) atomicAdd(cells + c, 1);
+        }
         if (PEN) {
             // inside collider c at the new position: v += -phi n / (4 dt), a spring of stiffness
             // m / (4 dt^2) along the outward normal (the stored v, hence the next scatter bound,
@@ -923,6 +995,12 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
     if (bad_any) atomicOr(a.flags + s, (int)FLAG_NONFINITE);
     if (cl_any) atomicOr(a.flags + s, (int)FLAG_CLAMPED);
     __syncthreads();
+    int mx = 0;
+    for (int n = t; n < NC; n += WG) mx = max(mx, cells[n]);
+    mx = wave_max_i(mx);
+    if ((t & 63) == 0) atomicMax(cells + NC, mx);
+    __syncthreads();
+    if (t == 0) a.L.icell[it] = cells[NC];
 }
 
 template <int B, bool PEN>
@@ -931,6 +1009,7 @@ __global__ __launch_bounds__(WG, 4) void k_g2p(StepArgs a)
     constexpr int T = B + 4, T3 = T * T * T;
     __shared__ float vt[3 * T3];
     __shared__ float pf[(WG / 64) * PF_COMPS * 64];
+    __shared__ int cells[p2g_cells<B>() + 1];
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(a.L.n_ovf, 0);   // grid update has consumed the list
     const int n_items = *a.L.n_items;
     const int G = active_wgs(n_items);
@@ -938,7 +1017,7 @@ __global__ __launch_bounds__(WG, 4) void k_g2p(StepArgs a)
     for (int it = xcd_remap(blockIdx.x, G); it < n_items; it += G) {
         Item item = a.L.items[it];
         if (!a.active[item.scene]) continue;
-        g2p_item<B, true, PEN>(a, it, item, vt, pf);
+        g2p_item<B, true, PEN>(a, it, item, vt, pf, cells);
     }
 }
 
@@ -1008,6 +1087,7 @@ __global__ __launch_bounds__(WG) void k_substep_persistent(StepArgs a)
 {
     constexpr int T = B + 4, T3 = T * T * T;
     __shared__ __align__(16) int smem[4 * T3];
+    __shared__ int cells[p2g_cells<B>() + 1];
     __shared__ int s_q;
     __shared__ ColliderNow cls[WG / 64][MAX_COLLIDERS_PER_SCENE];
     const int n_items = *a.L.n_items;
@@ -1026,7 +1106,7 @@ __global__ __launch_bounds__(WG) void k_substep_persistent(StepArgs a)
         if (q >= total) break;
         if (q < n_items) {
             Item item = a.L.items[q];
-            p2g_item<B>(a, q, item, smem);
+            p2g_item<B>(a, q, item, smem, cells);
             if (threadIdx.x == 0) {
                 __threadfence();
                 atomicAdd(&p2g_done[item.scene], 1);
@@ -1064,7 +1144,7 @@ __global__ __launch_bounds__(WG) void k_substep_persistent(StepArgs a)
             if (threadIdx.x == 0)
                 wait_counter(&grid_done[s], a.L.scene_gitem_begin[s + 1] - a.L.scene_gitem_begin[s] + 1, a.flags + s);
             __syncthreads();
-            g2p_item<B, false, false>(a, qi, item, (float *)smem, nullptr);
+            g2p_item<B, false, false>(a, qi, item, (float *)smem, nullptr, cells);
         }
     }
     if (threadIdx.x == 0) {

@@ -75,6 +75,7 @@ struct Lists {
     int *n_ovf;               // [1]
     int ovf_cap;
     float *ibound;            // per item: max over its particles of m|v_c| + 1.5 dx sum_e |A_ce| (P2G scale)
+    int *icell;               // per item: most particles sharing a base cell (P2G scale), 0 = not known
     unsigned char *touched;   // per block (all scenes, linear order): 1 = received mass in this substep's P2G
 };
 

@@ -297,6 +297,7 @@ __device__ void sur_advance_item(const StepArgs &a, int it, const Item &item, fl
     }
     bnd = wave_max(bnd);
     if ((t & 63) == 0 && bnd > 0.0f) atomicMax((int *)(a.L.ibound + it), __float_as_int(bnd));
+    if (t == 0) a.L.icell[it] = 0;   // the particles moved a whole control step: the next P2G counts
     if (bad_any) atomicOr(a.flags + s, (int)FLAG_NONFINITE);
     if (cl_any) atomicOr(a.flags + s, (int)FLAG_CLAMPED);
     __syncthreads();

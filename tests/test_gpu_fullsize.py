@@ -2,24 +2,31 @@
 benchmark times (block, chunk and re-sort cadence the autotuner picks on
 the MI355X), against the FP64 oracle on what the oracle can afford:
 
-  * cfg3, all 256 scenes (7.7 M particles) stepped together, one control
-    step (25 substeps, replayed from a captured hipGraph as the benchmark
-    runs it) with block 8, chunk 8192: sampled scenes (the first,
-    the last, the largest, the smallest) against the oracle run on each
-    alone (the scenes are independent), 1e-3 dx; every scene's state stays
-    finite and inside its grid;
+  * cfg3, all 256 scenes (7.7 M particles) stepped together with block 8,
+    chunk 8192, re-sort every 50 substeps:
+      - positions after 100 substeps (four 25-substep control steps, each
+        replayed from a captured hipGraph as the benchmark runs them) of
+        sampled scenes (the first, the last, the largest, the smallest)
+        against the oracle run on each alone (the scenes are independent),
+        1e-3 dx; every scene's state stays finite and inside its grid;
+      - the per-substep grid-momentum bar (1e-5) on 16 sampled scenes at
+        substep 1 (a handed-in state with seeded C, F) and at substep 25
+        (the state the GPU reached, read back for the oracle);
   * cfg4, the 1,048,576-particle heap on a 128^3 grid with 3 colliders,
-    one control step (25 substeps, graph replay) with block 4, chunk 8192,
-    re-sort every 10 (three sorts in the run): every particle against the
-    oracle, 1e-3 dx.
+    block 4, chunk 8192, re-sort every 10: every particle after 100
+    substeps (graph replay, ten sorts in the run) against the oracle,
+    1e-3 dx; grid momentum at substeps 1 and 25.
 """
 import numpy as np
 import pytest
 
-from gpu_util import announce
+from gpu_util import announce, momentum_floor, random_state, rel_l2
 from paper_2302_04659_amd import scenes
 
 pytestmark = pytest.mark.gpu
+
+CFG3_LAUNCH = dict(block=8, chunk=8192, sort_every=50)
+CFG4_LAUNCH = dict(block=4, chunk=8192, sort_every=10)
 
 
 @pytest.fixture(scope="module")
@@ -31,27 +38,68 @@ def mpm():
     return m
 
 
-def test_cfg3_full_batch_sampled_scenes(mpm, orc):
-    batch = scenes.cfg3(n_ctrl=2)
-    counts = np.array([sc.n for sc in batch])
-    announce("full-size cfg3", len(batch), "scenes", int(counts.sum()), "particles")
+def _sim(mpm, batch, launch, graph=1, capture=0):
     sim = mpm.Sim(batch)
-    sim.set_option(mpm.OPT_BLOCK, 8)
-    sim.set_option(mpm.OPT_CHUNK, 8192)
-    sim.set_option(mpm.OPT_SORT_EVERY, 50)
-    sim.set_option(mpm.OPT_GRAPH, 1)
+    sim.set_option(mpm.OPT_BLOCK, launch["block"])
+    sim.set_option(mpm.OPT_CHUNK, launch["chunk"])
+    sim.set_option(mpm.OPT_SORT_EVERY, launch["sort_every"])
+    sim.set_option(mpm.OPT_GRAPH, graph)
+    sim.set_option(mpm.OPT_CAPTURE_GRID, capture)
+    return sim
+
+
+def _grid_momentum(sim, orc, batch, sample, states, what):
+    worst = 0.0
+    for s in sample:
+        sc = batch[s]
+        x, v, C, F = states[s]
+        om, op = orc.Oracle(sc, x=x, v=v, C=C, F=F).p2g()
+        gm, gp = sim.get_grid(s)
+        assert rel_l2(gm, om) <= 1e-6, (what, s)
+        worst = max(worst, rel_l2(gp, op, momentum_floor(sc, om.sum())))
+    print(what, "worst grid momentum rel err", worst)
+    assert worst <= 1e-5, (what, worst)
+
+
+def _c18_at_1_and_25(mpm, orc, batch, sample, launch):
+    sim = _sim(mpm, batch, launch, graph=0, capture=1)
+    states = {}
+    xs, vs, Cs, Fs = [], [], [], []
+    for s, sc in enumerate(batch):
+        C, F = random_state(sc, 500 + s, c_scale=2.0, f_scale=0.05)
+        xs.append(sc.x), vs.append(sc.v), Cs.append(C), Fs.append(F)
+        if s in sample:
+            states[s] = (sc.x, sc.v, C, F)
+    sim.set_state(np.concatenate(xs), np.concatenate(vs), np.concatenate(Cs), np.concatenate(Fs))
     sim.set_colliders_ctrl(0)
-    sim.step(25)
+    sim.step(1)
+    assert sim.sync() == mpm.OK
+    _grid_momentum(sim, orc, batch, sample, states, "substep 1")
+    sim.step(23)
+    assert sim.sync() == mpm.OK
+    states = {s: sim.get_state(s) for s in sample}
+    sim.step(1)
+    assert sim.sync() == mpm.OK
+    _grid_momentum(sim, orc, batch, sample, states, "substep 25")
+    sim.close()
+
+
+def test_cfg3_full_batch_100_substeps(mpm, orc):
+    batch = scenes.cfg3(n_ctrl=4)
+    counts = np.array([sc.n for sc in batch])
+    announce("full-size cfg3, 100 substeps", len(batch), "scenes", int(counts.sum()), "particles")
+    sim = _sim(mpm, batch, CFG3_LAUNCH)
+    sim.run_schedule(4)
     assert sim.sync() == mpm.OK
     sample = sorted({0, len(batch) - 1, int(counts.argmax()), int(counts.argmin())})
     for s in sample:
         sc = batch[s]
         o = orc.Oracle(sc)
-        o.set_colliders(sc.ctrl_poses[0], sc.ctrl_vels[0])
-        o.step(25)
+        o.run_schedule(4)
         x, v, C, F = sim.get_state(s)
         err = np.abs(x - o.x).max() / sc.dx
-        print("cfg3 scene", s, "n", sc.n, "max |dx| / dx", err)
+        print("cfg3 scene", s, "n", sc.n, "max |dx| / dx after 100 substeps", err,
+              "rms", np.sqrt(((x - o.x) ** 2).sum(1).mean()) / sc.dx)
         assert err <= 1e-3
     x_all, *_ = sim.get_state(-1)
     assert np.all(np.isfinite(x_all))
@@ -60,22 +108,30 @@ def test_cfg3_full_batch_sampled_scenes(mpm, orc):
     sim.close()
 
 
-def test_cfg4_full_scene(mpm, orc):
-    sc = scenes.cfg4(n_ctrl=2)
-    announce("full-size cfg4", sc.n, "particles")
-    sim = mpm.Sim([sc])
-    sim.set_option(mpm.OPT_BLOCK, 4)
-    sim.set_option(mpm.OPT_CHUNK, 8192)
-    sim.set_option(mpm.OPT_SORT_EVERY, 10)
-    sim.set_option(mpm.OPT_GRAPH, 1)
-    sim.set_colliders_ctrl(0)
-    sim.step(25)
+def test_cfg3_full_batch_grid_momentum(mpm, orc):
+    batch = scenes.cfg3(n_ctrl=2)
+    counts = np.array([sc.n for sc in batch])
+    announce("full-size cfg3, grid momentum", len(batch), "scenes", int(counts.sum()), "particles")
+    sample = sorted(set(range(0, 256, 17)) | {int(counts.argmax())})
+    _c18_at_1_and_25(mpm, orc, batch, sample, CFG3_LAUNCH)
+
+
+def test_cfg4_full_scene_100_substeps(mpm, orc):
+    sc = scenes.cfg4(n_ctrl=4)
+    announce("full-size cfg4, 100 substeps", sc.n, "particles")
+    sim = _sim(mpm, [sc], CFG4_LAUNCH)
+    sim.run_schedule(4)
     assert sim.sync() == mpm.OK
     o = orc.Oracle(sc)
-    o.set_colliders(sc.ctrl_poses[0], sc.ctrl_vels[0])
-    o.step(25)
+    o.run_schedule(4)
     x, v, C, F = sim.get_state(0)
     err = np.abs(x - o.x).max() / sc.dx
-    print("cfg4 max |dx| / dx after 25 substeps:", err, "rms", np.sqrt(((x - o.x) ** 2).sum(1).mean()) / sc.dx)
+    print("cfg4 max |dx| / dx after 100 substeps:", err, "rms", np.sqrt(((x - o.x) ** 2).sum(1).mean()) / sc.dx)
     assert err <= 1e-3
     sim.close()
+
+
+def test_cfg4_full_scene_grid_momentum(mpm, orc):
+    sc = scenes.cfg4(n_ctrl=2)
+    announce("full-size cfg4, grid momentum", sc.n, "particles")
+    _c18_at_1_and_25(mpm, orc, [sc], [0], CFG4_LAUNCH)

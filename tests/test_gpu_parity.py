@@ -69,6 +69,60 @@ def test_teacher_forced_p2g_and_substep(mpm, orc, name, idx, block):
     sim.close()
 
 
+def _c18_batch(which):
+    if which == "cfg2":
+        return [scenes.cfg2(n_ctrl=2)]
+    return scenes.cfg3(n_scenes=16, n_ctrl=2)      # the first 16 scenes of the batched workload
+
+
+def _c18_check(sim, orc, batch, states, what):
+    """Grid momentum of the last P2G of every scene against the oracle's P2G
+    of the same particle state (c18 bar)."""
+    worst = 0.0
+    for s, sc in enumerate(batch):
+        x, v, C, F = states[s]
+        o = orc.Oracle(sc, x=x, v=v, C=C, F=F)
+        om, op = o.p2g()
+        gm, gp = sim.get_grid(s)
+        assert rel_l2(gm, om) <= 1e-6, (what, s)
+        err = rel_l2(gp, op, momentum_floor(sc, om.sum()))
+        worst = max(worst, err)
+    print(what, "worst grid momentum rel err", worst)
+    assert worst <= 1e-5, (what, worst)
+
+
+@pytest.mark.parametrize("which", ["cfg2", "cfg3x16"])
+@pytest.mark.parametrize("block,chunk", [(4, 512), (4, 2048), (4, 8192), (8, 512), (8, 2048), (8, 8192)])
+def test_grid_momentum_every_launch_config(mpm, orc, which, block, chunk):
+    """The per-substep grid-momentum bar at every block edge and chunk size
+    the autotuner can pick (the fixed-point scale of P2G depends on the
+    work item's particle count): the first P2G after a re-sort, from a
+    handed-in state (seeded C, F; scale bound from the sort), and the P2G of
+    the next substep (scale bound from the G2P that wrote the state, which is
+    read back for the oracle)."""
+    batch = _c18_batch(which)
+    announce("grid momentum", which, "B", block, "chunk", chunk, "n", sum(sc.n for sc in batch))
+    sim = mpm.Sim(batch)
+    sim.set_option(mpm.OPT_BLOCK, block)
+    sim.set_option(mpm.OPT_CHUNK, chunk)
+    sim.set_option(mpm.OPT_CAPTURE_GRID, 1)
+    states = []
+    for s, sc in enumerate(batch):
+        C, F = random_state(sc, 70 + s, c_scale=2.0, f_scale=0.05)
+        states.append((sc.x, sc.v, C, F))
+    sim.set_state(np.concatenate([st[0] for st in states]), np.concatenate([st[1] for st in states]),
+                  np.concatenate([st[2] for st in states]), np.concatenate([st[3] for st in states]))
+    sim.set_colliders_ctrl(0)
+    sim.step(1)
+    assert sim.sync() == mpm.OK
+    _c18_check(sim, orc, batch, states, "after sort")
+    states = [sim.get_state(s) for s in range(len(batch))]
+    sim.step(1)
+    assert sim.sync() == mpm.OK
+    _c18_check(sim, orc, batch, states, "bound from G2P")
+    sim.close()
+
+
 @pytest.mark.parametrize("name", ["cfg1", "cfg1b", "cfg2", "small-hencky", "small-sticky", "small-fluid"])
 def test_free_running_100(mpm, orc, name):
     if name == "small-hencky":
