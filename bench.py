@@ -1,15 +1,19 @@
 """Throughput of the MLS-MPM substep on one MI355X.
 
-A step is one full substep (re-sort when due, P2G, grid update, G2P with
-the return map) of every scene of the workload; collider poses and
-velocities are handed over every 25 substeps (one control step), as the
-workload prescribes.  Inputs are seeded synthetic scenes already resident in
-HBM when the timed region starts.
+A step is one control step of every scene of the workload: its collider
+poses and velocities are handed over, then 25 substeps run (each a re-sort
+when due, P2G, grid update and G2P with the return map), replayed from a
+captured hipGraph by default.  The timed window therefore holds whole
+control steps and the re-sorts that fall in them; the library's own
+counters report how many substeps, graph replays, host launches and
+re-sorts it actually queued.  Inputs are seeded synthetic scenes already
+resident in HBM when the timed region starts.
 
 Prints ONE JSON line: particle-substeps/s, the HBM roofline fraction of the
 dominant kernel (its average duration measured with HIP events on the
-library's stream over the timed region), and the FP64 CPU oracle timed on a
-bounded sample of the same workload on the host cores.
+library's stream over a second, host-launched window of the same length),
+and the FP64 CPU oracle timed on a bounded sample of the same workload on
+the host cores, single-threaded and on all cores.
 """
 import argparse
 import hashlib
@@ -74,30 +78,51 @@ def kernel_traffic(kernel, wl):
         return None
 
 
-def cpu_baseline(scene_list, n_scenes, substeps):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(scene_list, n_scenes, substeps, n_scenes_1t, substeps_1t):
+    """The FP64 oracle on the host cores: all cores on n_scenes x substeps,
+    one thread on n_scenes_1t x substeps_1t (each scene set up with its
+    first control step's collider poses; set-up not timed)."""
     import oracle
     oracle.build(force=False)
-    sample = scene_list[:n_scenes]
-    orcs = [oracle.Oracle(sc) for sc in sample]
-    for o, sc in zip(orcs, sample):
-        if sc.n_colliders:
-            o.set_colliders(sc.ctrl_poses[0], sc.ctrl_vels[0])
-    t0 = time.perf_counter()
-    for o in orcs:
-        o.step(substeps)
-    dt = time.perf_counter() - t0
-    n = sum(sc.n for sc in sample)
-    return {"value": n * substeps / dt, "unit": "particle-substeps/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"{n_scenes} scenes of the workload ({n} particles) x {substeps} substeps, FP64, "
-                      f"{dt:.1f} s wall"}
+    all_cores = len(os.sched_getaffinity(0))
+
+    def timed(count, steps, threads):
+        oracle.set_threads(threads)
+        sample = scene_list[:count]
+        orcs = [oracle.Oracle(sc) for sc in sample]
+        for o, sc in zip(orcs, sample):
+            if sc.n_colliders:
+                o.set_colliders(sc.ctrl_poses[0], sc.ctrl_vels[0])
+        t0 = time.perf_counter()
+        for o in orcs:
+            o.step(steps)
+        dt = time.perf_counter() - t0
+        n = sum(sc.n for sc in sample)
+        return n * steps / dt, f"{count} scenes of the workload ({n} particles) x {steps} substeps, FP64, {dt:.1f} s wall"
+
+    v_all, s_all = timed(n_scenes, substeps, all_cores)
+    v_one, s_one = timed(n_scenes_1t, substeps_1t, 1)
+    oracle.set_threads(all_cores)
+    return {"value": v_all, "unit": "particle-substeps/s", "cores": all_cores, "kind": "oracle",
+            "sample": s_all, "cpu_model": cpu_model(),
+            "single_thread": {"value": v_one, "cores": 1, "sample": s_one}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=25)
+    ap.add_argument("--steps", type=int, default=20, help="timed control steps (25 substeps each)")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed control steps before the window")
     ap.add_argument("--workload", default="cfg3")
     ap.add_argument("--block", type=int, default=0, help="grid block edge (0 = library default / autotuned)")
     ap.add_argument("--chunk", type=int, default=0)
@@ -111,6 +136,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-scenes", type=int, default=64)
     ap.add_argument("--cpu-substeps", type=int, default=50)
+    ap.add_argument("--cpu-scenes-1t", type=int, default=8)
+    ap.add_argument("--cpu-substeps-1t", type=int, default=25)
     ap.add_argument("--train-steps", type=int, default=3000, help="cfg5: surrogate training steps")
     ap.add_argument("--eval-scenes", type=int, default=256, help="cfg5: held-out scenes timed")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -150,34 +177,32 @@ def main():
         if args.workload == "cfg4":
             sim.set_option(mpm.OPT_SORT_EVERY, 10)   # the workload fixes its re-sort cadence
 
+    SUB = 25                      # substeps per control step (one step of the benchmark)
+    n_ctrl_avail = max(scene_list[0].n_ctrl, 1)
     ctrl = [0]
 
-    def run(n):
-        # hand over poses / velocities at every control-step boundary
-        done = 0
-        while done < n:
-            k = min(25 - run.phase, n - done)
-            if run.phase == 0:
-                sim.set_colliders_ctrl(ctrl[0] % scene_list[0].n_ctrl if scene_list[0].n_ctrl else 0)
-                ctrl[0] += 1
-            sim.step(k)
-            done += k
-            run.phase = (run.phase + k) % 25
-    run.phase = 0
+    def run(n_steps):
+        # one control step: hand over poses / velocities, then 25 substeps
+        for _ in range(n_steps):
+            sim.set_colliders_ctrl(ctrl[0] % n_ctrl_avail)
+            ctrl[0] += 1
+            sim.step(SUB)
 
     run(args.warmup)
     st = sim.sync()
     use_graph = sim.get_option(mpm.OPT_GRAPH) == 1
     # Timed region.  Per-kernel HIP events (library stream) bracket every
-    # launch of the region; with graph replay they cannot, so the kernels are
-    # then timed over a second region of the same length right after it.
+    # launch of a host-launched run; graph replays cannot be bracketed, so
+    # the kernels are then timed over a second region of the same length.
     sim.set_option(mpm.OPT_TIMING, 0 if use_graph else 1)
     sim.timing(reset=True)
+    sim.counters(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run(args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    window = sim.counters(reset=True)
     st = sim.sync()
     if use_graph:
         sim.set_option(mpm.OPT_TIMING, 1)
@@ -189,11 +214,16 @@ def main():
     if st < 0:
         raise SystemExit(f"simulation reported status {st}")
 
-    value = N * args.steps / elapsed
+    substeps = window["substeps"]
+    assert substeps == SUB * args.steps, window
+    value = N * substeps / elapsed
+    per_launch = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
     dom = max(("p2g", "g2p", "grid", "sort"), key=lambda k: kt[k][0])
-    dom_ms = kt[dom][0] / max(kt[dom][1], 1)
+    dom_ms = per_launch[dom]
     bytes_launch = ALG_BYTES[dom] * N
     achieved = bytes_launch / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
+    window["sort_ms_per_launch"] = round(per_launch["sort"], 5)
+    window["sort_share"] = window["sorts"] * per_launch["sort"] / (elapsed * 1e3)
     out = {
         "metric": "MPM particle-substeps/s at 1 GPU",
         "value": value,
@@ -207,11 +237,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": desc, "scenes": len(scene_list), "particles": N,
+        "config": {"workload": desc, "scenes": len(scene_list), "particles": N, "substeps_per_step": SUB,
                    "block": sim.get_option(mpm.OPT_BLOCK), "chunk": sim.get_option(mpm.OPT_CHUNK),
                    "sort_every": sim.get_option(mpm.OPT_SORT_EVERY),
                    "graph": sim.get_option(mpm.OPT_GRAPH), "persistent": sim.get_option(mpm.OPT_PERSISTENT)},
-        "kernels_ms_per_launch": {k: round(v[0] / max(v[1], 1), 5) for k, v in kt.items()},
+        "window": window,
+        "kernels_ms_per_launch": {k: round(v, 5) for k, v in per_launch.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": kernel_traffic(dom, args.workload)},
@@ -229,7 +260,8 @@ def main():
         torch.cuda.synchronize()
         print(f"copy probe: 3 x {nb} bytes device-to-device", file=sys.stderr)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(scene_list, min(args.cpu_scenes, len(scene_list)), args.cpu_substeps)
+        out["cpu_baseline"] = cpu_baseline(scene_list, min(args.cpu_scenes, len(scene_list)), args.cpu_substeps,
+                                           min(args.cpu_scenes_1t, len(scene_list)), args.cpu_substeps_1t)
     print(json.dumps(out), flush=True)
     sim.close()
 

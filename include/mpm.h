@@ -241,6 +241,22 @@ mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_l
  * for the timed work.  reset = 1 clears the accumulators. */
 mpm_status mpm_get_timing(mpm_ctx ctx, double *ms_total, long long *launches, int reset);
 
+/* Work queued on the context stream since mpm_create or the last reset,
+ * out[MPM_NCOUNTERS] (host):
+ *   MPM_CNT_SUBSTEPS        substeps of every scene (plain; a surrogate
+ *                           control step counts only its fallback substeps)
+ *   MPM_CNT_GRAPH_LAUNCHES  25-substep control steps replayed from a
+ *                           captured hipGraph
+ *   MPM_CNT_HOST_SUBSTEPS   substeps whose kernels were launched one by one
+ *                           from the host
+ *   MPM_CNT_SORTS           particle re-sorts (those inside replayed graphs
+ *                           included)
+ * Autotuning trials are counted too.  reset = 1 zeroes the counters after
+ * reading them.  Never waits. */
+enum { MPM_CNT_SUBSTEPS = 0, MPM_CNT_GRAPH_LAUNCHES = 1, MPM_CNT_HOST_SUBSTEPS = 2, MPM_CNT_SORTS = 3,
+       MPM_NCOUNTERS = 4 };
+mpm_status mpm_get_counters(mpm_ctx ctx, long long *out, int reset);
+
 /* Internal particle order (debugging and tests): pid_out[slot] = creation
  * index of the particle held in internal slot `slot`, for all particles
  * (length mpm_num_particles(ctx, -1)); host pointer; blocks.  Inside each

@@ -43,6 +43,7 @@ struct GraphKey {
 struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     int end_parity = 0, end_since_sort = 0;
+    long long n_sorts = 0;   // re-sorts the captured control step contains
 };
 
 constexpr int GRAPH_BLOCK = 25;
@@ -114,6 +115,8 @@ struct mpm_ctx_s {
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
     double kt_ms[MPM_KCLASSES] = {};
     long long kt_n[MPM_KCLASSES] = {};
+    // work queued since the last reset (mpm_get_counters)
+    long long cnt[MPM_NCOUNTERS] = {};
 
     // io
     float *d_io = nullptr;
@@ -388,6 +391,7 @@ mpm_status do_sort(mpm_ctx ctx)
 {
     KTimer kt(ctx, MPM_K_SORT);
     HIPCHK(launch_sort(sort_args(ctx), ctx->stream));
+    ctx->cnt[MPM_CNT_SORTS]++;
     ctx->cur = 1 - ctx->cur;
     ctx->since_sort = 0;
     return MPM_OK;
@@ -415,6 +419,8 @@ mpm_status queue_plain(mpm_ctx ctx, int n)
             KTimer kt(ctx, MPM_K_PERSISTENT);
             HIPCHK(launch_persistent(a, ctx->CH, ctx->cus * 4, ctx->stream));
             ctx->since_sort++;
+            ctx->cnt[MPM_CNT_SUBSTEPS]++;
+            ctx->cnt[MPM_CNT_HOST_SUBSTEPS]++;
             continue;
         }
         {
@@ -430,6 +436,8 @@ mpm_status queue_plain(mpm_ctx ctx, int n)
             HIPCHK(launch_g2p(a, substep_wgs(ctx), ctx->stream));
         }
         ctx->since_sort++;
+        ctx->cnt[MPM_CNT_SUBSTEPS]++;
+        ctx->cnt[MPM_CNT_HOST_SUBSTEPS]++;
     }
     HIPCHK(launch_collider_advance(ctx->d_cols, (int)ctx->h_cols.size(), ctx->d_col_scene, ctx->d_scenes, n,
                                    ctx->stream));
@@ -444,11 +452,15 @@ mpm_status queue_graph_block(mpm_ctx ctx)
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
         const int cur0 = ctx->cur, ss0 = ctx->since_sort;
+        long long cnt0[MPM_NCOUNTERS];
+        std::copy(ctx->cnt, ctx->cnt + MPM_NCOUNTERS, cnt0);
         ctx->since_sort = key.since_sort;
         HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
         mpm_status st = queue_plain(ctx, GRAPH_BLOCK);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+        const long long captured_sorts = ctx->cnt[MPM_CNT_SORTS] - cnt0[MPM_CNT_SORTS];
+        std::copy(cnt0, cnt0 + MPM_NCOUNTERS, ctx->cnt);   // captured, not run
         if (st != MPM_OK || e != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
             ctx->cur = cur0;
@@ -466,10 +478,14 @@ mpm_status queue_graph_block(mpm_ctx ctx)
         }
         ent.end_parity = ctx->cur;
         ent.end_since_sort = ctx->since_sort;
+        ent.n_sorts = captured_sorts;
         ctx->cur = cur0;
         it = ctx->graphs.emplace(key, ent).first;
     }
     HIPCHK(hipGraphLaunch(it->second.exec, ctx->stream));
+    ctx->cnt[MPM_CNT_GRAPH_LAUNCHES]++;
+    ctx->cnt[MPM_CNT_SUBSTEPS] += GRAPH_BLOCK;
+    ctx->cnt[MPM_CNT_SORTS] += it->second.n_sorts;
     ctx->cur = it->second.end_parity;
     ctx->since_sort = it->second.end_since_sort;
     return MPM_OK;
@@ -529,7 +545,7 @@ void release(mpm_ctx ctx)
     void *bufs[] = {ctx->d_scenes, ctx->d_psc, ctx->d_P[0], ctx->d_P[1], ctx->d_grid, ctx->d_cols, ctx->d_colnow,
                     ctx->d_col_scene, ctx->d_scene_bin_off, ctx->d_keys, ctx->d_count, ctx->d_pstart, ctx->d_perm,
                     ctx->d_tsum, ctx->d_dil, ctx->L.items, ctx->L.gitems, ctx->L.n_items, ctx->L.n_gitems,
-                    ctx->L.scene_item_begin, ctx->L.scene_gitem_begin, ctx->L.bflag, ctx->L.ovf, ctx->L.n_ovf, ctx->L.ibound, ctx->L.touched,
+                    ctx->L.scene_item_begin, ctx->L.scene_gitem_begin, ctx->L.bflag, ctx->L.ovf, ctx->L.n_ovf, ctx->L.ibound, ctx->L.icell, ctx->L.touched,
                     ctx->d_flags, ctx->d_queue, ctx->d_scene_done, ctx->d_cap, ctx->d_cap_off, ctx->d_io,
                     ctx->d_active, ctx->d_sur_gend, ctx->d_sur_acc, ctx->d_sur_out, ctx->d_sur_nfb,
                     ctx->d_wrench, ctx->d_wrench_out, ctx->d_sdf};
@@ -621,6 +637,7 @@ mpm_status create_impl(mpm_ctx ctx, const mpm_scene_desc *scenes, int n_scenes)
     HIPCHK(dalloc(&ctx->d_dil, T4));
     HIPCHK(dalloc(&ctx->L.items, ctx->items_cap));
     HIPCHK(dalloc(&ctx->L.ibound, ctx->items_cap));
+    HIPCHK(dalloc(&ctx->L.icell, ctx->items_cap));
     HIPCHK(dalloc(&ctx->L.gitems, T4));
     HIPCHK(dalloc(&ctx->L.n_items, 1));
     HIPCHK(dalloc(&ctx->L.n_gitems, 1));
@@ -1045,6 +1062,14 @@ mpm_status mpm_get_timing(mpm_ctx ctx, double *ms_total, long long *launches, in
             ctx->kt_n[k] = 0;
         }
     }
+    return MPM_OK;
+}
+
+mpm_status mpm_get_counters(mpm_ctx ctx, long long *out, int reset)
+{
+    ARGCHK(ctx && out, "null argument");
+    std::copy(ctx->cnt, ctx->cnt + MPM_NCOUNTERS, out);
+    if (reset) std::fill(ctx->cnt, ctx->cnt + MPM_NCOUNTERS, 0LL);
     return MPM_OK;
 }
 

@@ -78,6 +78,7 @@ def lib():
         L.mpm_autotune.argtypes = [vp, ct.c_int, ct.c_char_p, ct.c_size_t]
         L.mpm_get_order.argtypes = [vp, vp]
         L.mpm_get_timing.argtypes = [vp, vp, vp, ct.c_int]
+        L.mpm_get_counters.argtypes = [vp, vp, ct.c_int]
         L.mpm_set_scene_mask.argtypes = [vp, vp]
         L.mpm_sur_bbox.argtypes = [vp, vp]
         L.mpm_sur_features.argtypes = [vp, vp, ct.c_int, vp, vp, ct.c_int, ct.c_int, ct.c_int]
@@ -339,6 +340,12 @@ class Sim:
         n = np.zeros(len(KERNEL_CLASSES), np.int64)
         self._check(self.L.mpm_get_timing(self.h, ms.ctypes.data, n.ctypes.data, int(reset)), "get_timing")
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def counters(self, reset: bool = True):
+        """Work queued since the last reset: substeps, graph launches, host-launched substeps, re-sorts."""
+        c = np.zeros(4, np.int64)
+        self._check(self.L.mpm_get_counters(self.h, c.ctypes.data, int(reset)), "get_counters")
+        return {"substeps": int(c[0]), "graph_launches": int(c[1]), "host_substeps": int(c[2]), "sorts": int(c[3])}
 
     def autotune(self, substeps: int = 10) -> str:
         buf = ct.create_string_buffer(4096)
