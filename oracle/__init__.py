@@ -97,9 +97,12 @@ def lib():
         L.orc_g2p.argtypes = [sp, dp]
         L.orc_g2p.restype = ct.c_int
         L.orc_advance_colliders.argtypes = [sp]
+        L.orc_sur_advance.argtypes = [sp, dp, dp, ct.c_int, ct.c_int]
+        L.orc_sur_advance.restype = ct.c_int
         L.orc_step.argtypes = [sp, ct.c_int, dp, dp, dp]
         L.orc_step.restype = ct.c_int
         L.orc_threads.restype = ct.c_int
+        L.orc_set_threads.argtypes = [ct.c_int]
         _lib = L
     return _lib
 
@@ -198,6 +201,17 @@ class Oracle:
         if e:
             raise OracleError(f"step failed ({e}): particle stencil outside the grid")
 
+    def sur_advance(self, vs, dv, n_sub: int = 25, mode: int = 1):
+        """Surrogate control step from a grid prediction: vs, dv [res^3][3]
+        (start P2G velocity, predicted change), particles advanced in place
+        (mode 1: they take the predicted change; mode 0: the end field)."""
+        vs = np.ascontiguousarray(vs, np.float64).reshape(-1, 3)
+        dv = np.ascontiguousarray(dv, np.float64).reshape(-1, 3)
+        assert vs.shape[0] == self.res ** 3 and dv.shape[0] == self.res ** 3
+        e = lib().orc_sur_advance(ct.byref(self.s), _dp(vs), _dp(dv), int(n_sub), int(mode))
+        if e:
+            raise OracleError(f"sur_advance failed ({e}): particle stencil outside the grid")
+
     def affine(self):
         A = np.zeros((self.scene.n, 3, 3))
         lib().orc_affine(ct.byref(self.s), _dp(A))
@@ -210,6 +224,50 @@ class Oracle:
             if sc.n_colliders:
                 self.set_colliders(sc.ctrl_poses[k], sc.ctrl_vels[k])
             self.step(substeps)
+
+
+# -- surrogate residual ------------------------------------------------------
+# Reference velocity of the momentum term: the speed that carries a particle
+# across the per-block error bar (2e-2 dx) in one control step.
+SUR_ERR_BAR_DX = 2e-2
+
+
+def sur_residual(scene, m_s, v_s, dm, dv, m_r, p_r, n_sub: int = 25):
+    """Self-consistency residual of a surrogate control step, in FP64.
+
+    m_s [res^3], v_s [res^3][3]: mass and P2G velocity at the start of the
+    step; dm, dv: the predicted changes; m_r, p_r: a P2G of the particles the
+    prediction advanced.  Over the nodes holding material before or after,
+        r_m = sum |m_r - (m_s + dm)| / sum m_s,
+        r_p = sum |p_r - (m_s + dm) (v_s + dv)|_1 / (sum m_s * u_ref),
+    u_ref = SUR_ERR_BAR_DX dx / (n_sub dt); returns (max(r_m, r_p), r_m, r_p).
+    """
+    m_s = np.asarray(m_s, np.float64).reshape(-1)
+    v_s = np.asarray(v_s, np.float64).reshape(-1, 3)
+    dm = np.asarray(dm, np.float64).reshape(-1)
+    dv = np.asarray(dv, np.float64).reshape(-1, 3)
+    m_r = np.asarray(m_r, np.float64).reshape(-1)
+    p_r = np.asarray(p_r, np.float64).reshape(-1, 3)
+    sel = (m_s > 0) | (m_r > 0)
+    m_pred = m_s + dm
+    v_end = v_s + dv
+    total = m_s.sum()
+    if total <= 0:
+        return 0.0, 0.0, 0.0
+    u_ref = SUR_ERR_BAR_DX * scene.dx / (n_sub * scene.dt)
+    r_m = np.abs(m_r - m_pred)[sel].sum() / total
+    r_p = np.abs(p_r - m_pred[:, None] * v_end)[sel].sum() / (total * u_ref)
+    return max(r_m, r_p), r_m, r_p
+
+
+def p2g_velocity(m, p):
+    """Grid velocity p / m of a P2G output (0 where the mass is 0)."""
+    m = np.asarray(m, np.float64).reshape(-1)
+    p = np.asarray(p, np.float64).reshape(-1, 3)
+    v = np.zeros_like(p)
+    nz = m > 0
+    v[nz] = p[nz] / m[nz, None]
+    return v
 
 
 # -- single-matrix helpers (pinned by the tests) ----------------------------
@@ -280,3 +338,8 @@ def collide(collider, xi, v):
 
 def threads() -> int:
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from here on (timing)."""
+    lib().orc_set_threads(int(n))

@@ -100,6 +100,16 @@ int orc_threads(void)
 #endif
 }
 
+/* Threads of the parallel loops that follow (n >= 1); timing only. */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n < 1 ? 1 : n);
+#else
+    (void)n;
+#endif
+}
+
 static void lame(const orc_scene *s, double *mu, double *la)
 {
     *mu = s->E / (2.0 * (1.0 + s->nu));
@@ -601,6 +611,77 @@ int orc_g2p(orc_scene *s, const double *vg)
             for (int i = 0; i < 9; i++) F[i] = i % 4 == 0 ? c : 0.0;
         } else {
             orc_return_map(s, F);
+        }
+    }
+    return err;
+}
+
+/* Surrogate control step from a grid prediction (the paper has no learned
+ * part; a grid model stands in for one control step of n_sub substeps).
+ * vs [res^3][3]: the start grid velocity (P2G momentum / mass of the current
+ * state, 0 where the mass is 0); dv [res^3][3]: the predicted change of that
+ * velocity over the step.  With T = n_sub dt, mid field u = vs + dv / 2 and
+ * end field e = vs + dv, every particle, with its weights at its start
+ * position:
+ *   v_mid = sum w u_i,   C_mid = (4/dx^2) sum w u_i (x_i - x_p)^T,
+ *   x    <- x + T v_mid,
+ *   F    <- (I + T C_mid) F, then the return map (or the fluid's volume-only
+ *           projection), as after a plain substep;
+ *   mode 1: v <- v + sum w dv_i,  C <- C + (4/dx^2) sum w dv_i (x_i - x_p)^T
+ *           (the particles take the predicted change: the surrogate's
+ *           particle update);
+ *   mode 0: v <- sum w e_i,  C <- (4/dx^2) sum w e_i (x_i - x_p)^T
+ *           (the particles take the end field; kept to measure how far this
+ *           simpler form lands from a plain control step).
+ * Returns -2 when a stencil leaves the grid. */
+int orc_sur_advance(orc_scene *s, const double *vs, const double *dv, int n_sub, int mode)
+{
+    int err = 0;
+    double D = 4.0 / (s->dx * s->dx), T = n_sub * s->dt;
+#pragma omp parallel for schedule(static) reduction(min : err)
+    for (int p = 0; p < s->n; p++) {
+        int base[3];
+        double f[3], w[3][3];
+        double *x = s->x + 3 * p, *v = s->v + 3 * p, *C = s->C + 9 * p, *F = s->F + 9 * p;
+        if (particle_base(s, x, base, f)) { err = -2; continue; }
+        for (int a = 0; a < 3; a++) orc_weights(f[a], w[a]);
+        double vm[3] = {0, 0, 0}, ve[3] = {0, 0, 0}, vd[3] = {0, 0, 0};
+        double Bm[9] = {0}, Be[9] = {0}, Bd[9] = {0};
+        for (int ox = 0; ox < 3; ox++)
+            for (int oy = 0; oy < 3; oy++)
+                for (int oz = 0; oz < 3; oz++) {
+                    double wt = w[0][ox] * w[1][oy] * w[2][oz];
+                    double d[3] = {(ox - f[0]) * s->dx, (oy - f[1]) * s->dx, (oz - f[2]) * s->dx};
+                    size_t idx = ((size_t)(base[0] + ox) * s->res + (base[1] + oy)) * s->res + (base[2] + oz);
+                    for (int i = 0; i < 3; i++) {
+                        double u = vs[3 * idx + i] + 0.5 * dv[3 * idx + i];
+                        double e = vs[3 * idx + i] + dv[3 * idx + i];
+                        vm[i] += wt * u;
+                        ve[i] += wt * e;
+                        vd[i] += wt * dv[3 * idx + i];
+                        for (int j = 0; j < 3; j++) {
+                            Bm[3 * i + j] += wt * u * d[j];
+                            Be[3 * i + j] += wt * e * d[j];
+                            Bd[3 * i + j] += wt * dv[3 * idx + i] * d[j];
+                        }
+                    }
+                }
+        for (int i = 0; i < 3; i++) x[i] += T * vm[i];
+        double M[9];
+        for (int i = 0; i < 9; i++) M[i] = (i % 4 == 0 ? 1.0 : 0.0) + T * D * Bm[i];
+        matmul(M, F, F);
+        if (s->model == 2) {
+            double c = cbrt(det3(F));
+            for (int i = 0; i < 9; i++) F[i] = i % 4 == 0 ? c : 0.0;
+        } else {
+            orc_return_map(s, F);
+        }
+        if (mode == 0) {
+            for (int i = 0; i < 3; i++) v[i] = ve[i];
+            for (int i = 0; i < 9; i++) C[i] = D * Be[i];
+        } else {
+            for (int i = 0; i < 3; i++) v[i] += vd[i];
+            for (int i = 0; i < 9; i++) C[i] += D * Bd[i];
         }
     }
     return err;
