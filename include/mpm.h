@@ -2,7 +2,7 @@
  * mpm.h -- C ABI of the MI355X MLS-MPM soft-body library (libmpm_hip.so).
  *
  * The calls follow the paper's statement of the soft-body problem
- * (Sec. 3 "Rigid-soft Coupling" and Algorithm 1 in App. C.1):
+ * (Sec. 3 "Rigid-soft Coupling" and Algorithm 1 in App. D.1):
  *   - create a soft scene and copy the rigid collision shapes into it
  *     (Algorithm 1: "copy rigid body shapes ... to soft scene")      -> mpm_create
  *   - after each rigid step copy rigid poses and velocities into it
@@ -10,14 +10,14 @@
  *   - run the soft steps: particle-to-grid, grid velocity, grid-to-particle,
  *     integrate (Algorithm 1, inner loop)                             -> mpm_step
  *   - hand particle positions to the consumer, ideally by one device-to-device
- *     copy (App. C.2)                                                  -> mpm_get_particles
+ *     copy (App. D.2)                                                  -> mpm_get_particles
  *   - read out the forces the soft body exerts on the rigid bodies
  *     (Algorithm 1 accumulates them for the rigid step)               -> mpm_get_collider_wrenches
  * The method of a substep is MLS-MPM with APIC transfers and quadratic
  * B-splines (Sec. 3 names MLS-MPM); colliders are analytic box / capsule
  * SDFs applied on grid nodes (Sec. 3: the grid-node variant the simulator
  * also supports), material is neo-Hookean or Hencky elasticity with a von
- * Mises return map (App. C.3, Table "tab:mpm_param": Young's modulus,
+ * Mises return map (App. D.3, Table "tab:mpm_param": Young's modulus,
  * Poisson ratio, yield stress).
  *
  * Conventions shared by every call:
@@ -62,7 +62,7 @@ typedef enum {
     MPM_ERR_STATE = -5        /* call not valid in the current state */
 } mpm_status;
 
-/* Materials (App. C.3 gives E, nu and the yield stress of the elastoplastic
+/* Materials (App. D.3 gives E, nu and the yield stress of the elastoplastic
  * bodies; the liquid of the Pour task (Sec. 2.1 "Heterogeneous Task Families",
  * and the soft-body task table of the appendix) has no printed law):
  *   MPM_NEO_HOOKEAN           tau = mu (F F^T - I) + lambda ln(J) I
@@ -177,7 +177,7 @@ mpm_status mpm_sync(mpm_ctx ctx);
 mpm_status mpm_get_particles(mpm_ctx ctx, int scene, float *x, float *v, float *F, int on_device);
 
 /* Zero-copy view of the particle positions for a consumer on the same GPU (a
- * renderer: App. C.2 hands the particles over on the GPU rather than through
+ * renderer: App. D.2 hands the particles over on the GPU rather than through
  * the host).  *x, *y, *z receive device pointers to the current x, y and z
  * coordinates in the library's internal order (sorted by grid block, not
  * creation order); scene s holds slots [slot_begin[s], slot_begin[s + 1])
@@ -274,7 +274,7 @@ mpm_status mpm_set_scene_mask(mpm_ctx ctx, const int *active);
 
 /* ---- Grid surrogate for one control step ------------------------------
  * The paper has no learned component; these calls let a grid network stand
- * in for one control step of 25 substeps (App. D.3: 25 physics steps per
+ * in for one control step of 25 substeps (App. E.3: 25 physics steps per
  * control step), with the plain substeps above as the per-scene fallback.
  * All scenes must share one grid resolution R; every pointer is a device
  * pointer on the context's device; work is queued on the context stream.
@@ -310,14 +310,15 @@ mpm_status mpm_sur_features(mpm_ctx ctx, float *feat, int cf, float *grid0, cons
  * step, at the nodes of grid0 (from mpm_sur_features on this state, same
  * box; the prediction is zero outside the box).
  * Particles advance with T = 25 dt: x += T v_mid, F <- (I + T C_mid) F
- * then the return map, v and C from v_end = v_start + dv (v_mid the mean of
- * start and end), and a P2G of the advanced particles (m_r, v_r = p_r / m_r)
- * is compared with the prediction over the nodes holding material before or
- * after:
- *   r = max(|m_r - m_pred|_1 / sum m, |m_r v_r - m_pred v_end|_1 /
- *           max(|m v_start|_1, sum m |g| T)),
- * per scene (re-splat mass outside the box counts in full in the first
- * term).  Scenes with r > threshold (or non-finite state) are put back
+ * then the return map (v_mid the mean of the start field and the end field
+ * v_end = v_start + dv, C_mid its APIC gradient at the particle), and take
+ * the predicted change: v += the interpolated dv, C += its APIC gradient.
+ * A P2G of the advanced particles (m_r, p_r) is compared with the
+ * prediction over the nodes holding material before or after:
+ *   r = max(|m_r - m_pred|_1 / sum m, |p_r - m_pred v_end|_1 / (sum m u_ref)),
+ * per scene, with u_ref = 0.02 dx / T, the speed that carries a particle
+ * across the per-block error bar (2e-2 dx) in one control step (re-splat
+ * mass outside the box counts in full in the first term).  Scenes with r > threshold (or non-finite state) are put back
  * to their state at the start of the step and run the 25 plain substeps
  * instead (flag MPM_SUR_NO_FALLBACK keeps every scene on the surrogate and
  * only reports r).  residual [n_scenes] (nullable) receives r; n_fallback

@@ -11,6 +11,10 @@ constexpr int WG = 256;
 constexpr float SUR_VEL = 0.2f;   // velocity unit of the surrogate's inputs and outputs (m/s)
 constexpr float SUR_DM = 1.0f / 32.0f;   // unit of the predicted mass change, in rho dx^3 (a change over one
                                          // control step is ~1e-3 rho dx^3; this unit brings it to O(1e-2))
+// Per-block position error bar of the surrogate, in cells: the residual's
+// momentum term is measured against the speed that crosses it in one
+// control step, SUR_ERR_BAR dx / (n_sub dt).
+constexpr float SUR_ERR_BAR = 0.02f;
 
 __device__ __forceinline__ int xcd_remap(int b, int G)
 {

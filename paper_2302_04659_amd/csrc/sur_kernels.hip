@@ -14,8 +14,8 @@ namespace mpm {
 // distance to the nearest collider and that collider's velocity; its output
 // is the change of the node mass and of the P2G velocity p / m over the
 // control step.  The particles then advance with the mean of the start and
-// end grid velocities, take their velocity and APIC matrix from the end
-// velocity, and a P2G of the advanced particles checks the prediction
+// end grid velocities, add the predicted change to their velocity and APIC
+// matrix, and a P2G of the advanced particles checks the prediction
 // (residual gate).
 
 // Collider poses of every scene at substep a.substep (for the dense pass).
@@ -172,8 +172,10 @@ __device__ __forceinline__ void sur_node(const float *grid0, const float *pred, 
 }
 
 // Advance the particles of one item over the control step from the predicted
-// grid: x += T v_mid, F <- (I + T C_mid) F (+ return map), v and C from the
-// end velocity, and the affine momentum A for the next substep's P2G.
+// grid: x += T v_mid, F <- (I + T C_mid) F (+ return map), v += the change
+// interpolated to the particle, C += its APIC gradient, and the affine
+// momentum A for the next substep's P2G (the stored A = m C - k tau(F) takes
+// m dC and the change of the stress term).
 template <int B>
 __device__ void sur_advance_item(const StepArgs &a, int it, const Item &item, float *vt, const float *grid0,
                                  const float *pred, int cp, int n_sub)
@@ -194,7 +196,7 @@ __device__ void sur_advance_item(const StepArgs &a, int it, const Item &item, fl
         }
         for (int d = 0; d < 3; d++) {
             vt[d * T3 + n] = fmaf(0.5f, dv[d], vs[d]);
-            vt[(3 + d) * T3 + n] = vs[d] + dv[d];
+            vt[(3 + d) * T3 + n] = dv[d];
         }
     }
     __syncthreads();
@@ -207,8 +209,10 @@ __device__ void sur_advance_item(const StepArgs &a, int it, const Item &item, fl
     float bnd = 0.0f;
     for (int li = t; li < item.count; li += WG) {
         const unsigned jo = (unsigned)(item.start + li) << 2;
-        float x[3], G[9];
+        float x[3], G[9], v[3], A[9];
         for (int d = 0; d < 3; d++) x[d] = pload(a.P, ps, X0 + d, jo);
+        for (int d = 0; d < 3; d++) v[d] = pload(a.P, ps, V0 + d, jo);
+        for (int e = 0; e < 9; e++) A[e] = pload(a.P, ps, A00 + e, jo);
         for (int e = 0; e < 9; e++) G[e] = pload(a.P, ps, G00 + e, jo);
         int b[3], cl = 0, in = 1;
         float f[3];
@@ -240,7 +244,7 @@ __device__ void sur_advance_item(const StepArgs &a, int it, const Item &item, fl
                         if (c >= 0) sur_node(grid0, pred, cp, c, vs, dv);
                         for (int d = 0; d < 3; d++) {
                             um[d] = fmaf(0.5f, dv[d], vs[d]);
-                            ue[d] = vs[d] + dv[d];
+                            ue[d] = dv[d];
                         }
                     }
                     const float o[3] = {(float)ox, (float)oy, (float)oz};
@@ -253,7 +257,7 @@ __device__ void sur_advance_item(const StepArgs &a, int it, const Item &item, fl
                         }
                     }
                 }
-        // C = (4/dx^2) sum w v (x_i - x_p)^T = (4/dx) (S - v f^T)
+        // C = (4/dx^2) sum w v (x_i - x_p)^T = (4/dx) (S - v f^T); "e" sums hold the change
         float Cm[9], Ce[9];
         for (int c = 0; c < 3; c++)
             for (int e = 0; e < 3; e++) {
@@ -268,8 +272,11 @@ __device__ void sur_advance_item(const StepArgs &a, int it, const Item &item, fl
                 for (int e = 0; e < 3; e++) acc = fmaf(Cm[3 * i + e], G[3 * e + k], acc);
                 Gt[3 * i + k] = fmaf(Tb, acc, G[3 * i + k]);
             }
-        float tau[9], Gn[9];
+        // stress of the start F (the stored A holds m C - k tau(F))
+        float tau0[9];
         int bad = 0;
+        stress_of(G, mat, tau0, bad);
+        float tau[9], Gn[9];
         if (mat.model == 0) {
             tau_neo_hookean(Gt, mat.mu, mat.la, tau, bad);
             for (int e = 0; e < 9; e++) Gn[e] = Gt[e];
@@ -280,18 +287,21 @@ __device__ void sur_advance_item(const StepArgs &a, int it, const Item &item, fl
         }
         bad |= !(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]));
         bad_any |= bad;
+        float vn[3];
         for (int d = 0; d < 3; d++) {
+            vn[d] = v[d] + ve[d];
             pstore(a.P, ps, X0 + d, jo, x[d]);
-            pstore(a.P, ps, V0 + d, jo, ve[d]);
+            pstore(a.P, ps, V0 + d, jo, vn[d]);
         }
         float An[9];
         for (int e = 0; e < 9; e++) {
-            An[e] = fmaf(K.mass, Ce[e], -K.kstress * tau[e]);
+            // m (C + dC) - k tau(F_new) = A + k (tau(F) - tau(F_new)) + m dC
+            An[e] = fmaf(K.mass, Ce[e], fmaf(K.kstress, tau0[e] - tau[e], A[e]));
             pstore(a.P, ps, A00 + e, jo, An[e]);
             pstore(a.P, ps, G00 + e, jo, Gn[e]);
         }
         // a non-finite v or A: flagged, so that the scene falls back
-        const float sb = scatter_bound(K.mass, K.dx, ve, An);
+        const float sb = scatter_bound(K.mass, K.dx, vn, An);
         bad_any |= !(sb <= 3.0e38f);
         bnd = fmaxf(bnd, sb);
     }
@@ -382,8 +392,10 @@ hipError_t launch_sur_residual(const StepArgs &a, int res, const float *grid0, c
     return hipGetLastError();
 }
 
-// Residual per scene r = max(sum|dm| / sum m, sum|dp| / max(sum|p|, sum m |g| T))
-// and the fallback decision r > threshold (a non-finite r falls back too).
+// Residual per scene r = max(sum|dm| / sum m, sum|dp| / (sum m u_ref)), with
+// u_ref = SUR_ERR_BAR dx / T the speed that crosses the per-block error bar in
+// one control step, and the fallback decision r > threshold (a non-finite r
+// falls back too).
 __global__ void k_sur_decide(StepArgs a, const float *acc, int n_sub, float threshold, int fallback, float *residual,
                              int *active, int *n_fallback)
 {
@@ -393,9 +405,8 @@ __global__ void k_sur_decide(StepArgs a, const float *acc, int n_sub, float thre
     const float *q = acc + 4 * s;
     float r = 0.0f;
     if (q[2] > 0.0f) {
-        const float gn = sqrtf(S.g[0] * S.g[0] + S.g[1] * S.g[1] + S.g[2] * S.g[2]);
-        const float pref = fmaxf(q[3], q[2] * gn * (float)n_sub * S.dt);
-        r = fmaxf(q[0] / q[2], pref > 0.0f ? q[1] / pref : 0.0f);
+        const float u_ref = SUR_ERR_BAR * S.dx / ((float)n_sub * S.dt);
+        r = fmaxf(q[0] / q[2], q[1] / (q[2] * u_ref));
     }
     if (!isfinite(r) || (a.flags[s] & FLAG_NONFINITE)) r = INFINITY;
     if (residual) residual[s] = r;

@@ -7,11 +7,11 @@ and the per-scene stepping mask, through the C ABI.
     against the oracle's P2G (the P2G bars, 1e-6 / 1e-5), collider
     channels against the oracle's SDF and the collider velocity;
   * particle advance: closed form on a linear velocity field (APIC
-    reproduces it exactly, so x, v, C and F follow in closed form);
+    reproduces it exactly, so x, v, C and F follow in closed form), and the
+    whole control step (advance and residual) against the oracle's on a
+    seeded non-affine prediction, for each material;
   * residual gate: scenes over the threshold are put back and run the plain
     substeps (oracle bar); scenes under it are untouched by the fallback;
-    the residual itself equals the one recomputed from the oracle's P2G of
-    the advanced particles;
   * per-scene boxes: the stencil box of the particles, features, start grid,
     particle advance and residual on a box agree with the whole-grid calls;
     mass outside a box that cuts the material counts in the residual;
@@ -309,14 +309,17 @@ def test_advance_reproduces_linear_field(env, u):
     sim.close()
 
 
-def test_residual_matches_oracle_resplat(env, orc):
-    """The gate's residual (c22 reading) recomputed on the CPU: the oracle's
-    P2G of the particles the GPU advanced, against the start grid and the
-    prediction, r = max(sum|m_r - m_pred| / sum m, sum|p_r - m_pred v_end| /
-    max(sum m |v|, sum m |g| T)) over nodes with material before or after."""
+@pytest.mark.parametrize("model", [scenes.HENCKY_VM, scenes.NEO_HOOKEAN, scenes.FLUID])
+def test_control_step_matches_oracle(env, orc, model):
+    """One surrogate control step from a seeded non-affine prediction (noise
+    on every node), against the oracle's control step from the same particle
+    state and prediction: the oracle's own P2G gives its start grid, its
+    advance moves its particles (they take the predicted change), its P2G of
+    them and its residual judge them.  Particles element by element (x to
+    1e-5 dx; v, C, F - I to 1e-5 relative L2), residual to 1e-3 relative."""
     torch, mpm = env
-    batch = _batch()
-    announce("surrogate residual vs oracle re-splat", len(batch))
+    batch = [scenes.small_scene(70 + s, n=3000, res=32, model=model, n_ctrl=1, dt=1e-4) for s in range(3)]
+    announce("surrogate control step vs oracle, model", model)
     S, R = len(batch), batch[0].res
     ts = _new_stream(torch)
     sim, = _state_sims(mpm, batch, ts, 1)
@@ -331,25 +334,24 @@ def test_residual_matches_oracle_resplat(env, orc):
         sim.sur_block(pred, grid0, threshold=1e-3, fallback=False, residual=residual)
     torch.cuda.synchronize()
     assert sim.sync() >= 0
-    g = grid0.cpu().numpy().astype(np.float64)
     r_gpu = residual.cpu().numpy()
     for s, sc in enumerate(batch):
-        x, v, C, F = sim.get_state(s)
-        o = orc.Oracle(sc, x=x, v=v, C=C, F=F)
-        o.set_colliders(sc.ctrl_poses[0], sc.ctrl_vels[0])
+        C0, F0 = random_state(sc, 90 + s, c_scale=2.0, f_scale=0.03)
+        o = orc.Oracle(sc, x=sc.x, v=sc.v, C=C0, F=F0)
+        m_s, p_s = (a.reshape(-1, *a.shape[3:]).copy() for a in o.p2g())
+        v_s = orc.p2g_velocity(m_s, p_s)
+        dv = pred_h[s, ..., 0:3].reshape(-1, 3).astype(np.float64) * VEL
+        dm = pred_h[s, ..., 3].reshape(-1).astype(np.float64) * (sc.rho * sc.dx ** 3 / 32.0)
+        o.sur_advance(v_s, dv, 25, 1)
         m_r, p_r = o.p2g()
-        mu = sc.rho * sc.dx ** 3 / 32.0
-        m0, v0 = g[s, ..., 0], g[s, ..., 1:4]
-        mp = m0 + pred_h[s, ..., 3].astype(np.float64) * mu
-        ve = v0 + pred_h[s, ..., 0:3].astype(np.float64) * VEL
-        on = (m0 > 0) | (m_r > 0)
-        sm = np.abs(m_r - mp)[on].sum()
-        sp = np.abs(p_r - mp[..., None] * ve)[on].sum()
-        T = 25 * sc.dt
-        pref = max((m0[..., None] * np.abs(v0)).sum(), m0.sum() * float(np.linalg.norm(sc.gravity)) * T)
-        r = max(sm / m0.sum(), sp / pref)
-        print("scene", s, "gpu", r_gpu[s], "oracle re-splat", r)
-        assert abs(r_gpu[s] - r) <= 1e-4 * r
+        r, r_m, r_p = orc.sur_residual(sc, m_s, v_s, dm, dv, m_r, p_r, 25)
+        x, v, C, F = sim.get_state(s)
+        ex = np.abs(x - o.x).max() / sc.dx
+        ev, eC, eF = rel_l2(v, o.v), rel_l2(C, o.C), rel_l2(F - np.eye(3), o.F - np.eye(3))
+        print("scene", s, "x", ex, "v", ev, "C", eC, "F-I", eF, "| residual gpu", r_gpu[s], "oracle", r,
+              "(mass", r_m, "momentum", r_p, ")")
+        assert ex <= 1e-5 and ev <= 1e-5 and eC <= 1e-5 and eF <= 1e-5
+        assert abs(r_gpu[s] - r) <= 1e-3 * r
     sim.close()
 
 
