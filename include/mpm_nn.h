@@ -3,7 +3,7 @@
  *
  * The paper has no learned component; these kernels serve the surrogate
  * this library adds in front of the MLS-MPM substep (the network stands in
- * for a 25-substep control step, App. D.3 gives 25 physics steps per control
+ * for a 25-substep control step, App. E.3 gives 25 physics steps per control
  * step, and the plain MPM stays its fallback).  They are the training and
  * inference primitives the Python driver composes into the U-Net:
  * convolution forward / adjoint (BF16 MFMA, FP32 accumulate), weight and

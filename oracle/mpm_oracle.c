@@ -7,13 +7,13 @@
  * shares no code, header, table or helper with the HIP sources.
  *
  * What it computes (the paper, Sec. 3 "Rigid-soft Coupling" and Algorithm 1
- * in App. C.1): the soft step is MLS-MPM (moving least squares MPM with APIC
+ * in App. D.1): the soft step is MLS-MPM (moving least squares MPM with APIC
  * transfers, the method the paper says its solver follows) with
  *   particle-to-grid transfer of mass and momentum including the stress term,
  *   a grid velocity update,
  *   grid-to-particle transfer of velocity and its gradient,
  *   particle integration (position, deformation gradient),
- * for elastoplastic material (App. C.3, Table "tab:mpm_param": Young's
+ * for elastoplastic material (App. D.3, Table "tab:mpm_param": Young's
  * modulus, Poisson ratio, yield stress), pushed by kinematic rigid shapes
  * given as analytic signed distance functions (Sec. 3: boxes and capsules,
  * applied on grid nodes, the PlasticineLab-style variant the paper also

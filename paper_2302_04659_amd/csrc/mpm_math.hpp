@@ -2,7 +2,7 @@
 //
 // Quadratic B-spline weights and APIC transfer (MLS-MPM, the method the
 // paper's soft-body solver follows, Sec. 3), neo-Hookean and Hencky
-// elasticity with a von Mises return map (App. C.3, Table "tab:mpm_param"),
+// elasticity with a von Mises return map (App. D.3, Table "tab:mpm_param"),
 // analytic box / capsule SDFs (Sec. 3).
 //
 // Numerical design: the deformation gradient is carried as G = F - I and the

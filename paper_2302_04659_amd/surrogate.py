@@ -3,7 +3,7 @@ MLS-MPM, with the residual gate and per-scene plain-MPM fallback.
 
 The paper has no learned component; this module adds one in front of the
 substep loop of its soft-body simulator (Algorithm 1 runs 25 substeps per
-control step, App. D.3).  Everything that computes runs in libmpm_hip.so:
+control step, App. E.3).  Everything that computes runs in libmpm_hip.so:
 feature extraction, the network (BF16 MFMA kernels), the particle advance,
 the re-splat residual and the fallback (include/mpm.h, include/mpm_nn.h).
 PyTorch only provides device buffers and the stream, and assembles training

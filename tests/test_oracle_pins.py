@@ -1,7 +1,7 @@
 """Pins of the FP64 oracle against closed forms, invariants, library routines
 and brute force (no GPU).
 
-The paper prints no worked numerical example for its MPM (Sec. 3 and App. C
+The paper prints no worked numerical example for its MPM (Sec. 3 and App. D
 give only Algorithm 1 and a parameter table), so every pin here is one of:
 a closed form the MLS-MPM / APIC mathematics fixes, a conservation law,
 a library routine (numpy SVD, scipy rotations) or brute force on tiny
