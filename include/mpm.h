@@ -54,7 +54,7 @@ typedef struct mpm_ctx_s *mpm_ctx;
 typedef enum {
     MPM_OK = 0,
     MPM_WARN_CLAMPED = 1,     /* a particle stencil touched the grid edge and was clamped */
-    MPM_WARN_FALLBACK = 2,    /* reserved */
+    MPM_WARN_FALLBACK = 2,    /* mpm_step_blocks: at least one scene fell back to the plain substeps */
     MPM_ERR_ARG = -1,         /* invalid argument; nothing was changed */
     MPM_ERR_HIP = -2,         /* HIP runtime error; detail via mpm_last_error */
     MPM_ERR_OOM = -3,         /* device allocation failed */
@@ -328,6 +328,43 @@ mpm_status mpm_sur_features(mpm_ctx ctx, float *feat, int cf, float *grid0, cons
 enum { MPM_SUR_NO_FALLBACK = 1, MPM_SUR_SYNC = 2 };
 mpm_status mpm_sur_block(mpm_ctx ctx, const float *pred, int cp, const float *grid0, const int *origin, int D, int H,
                          int W, float threshold, int flags, float *residual, int *n_fallback);
+
+/* Library-owned surrogate (Algorithm 1's inner soft-step loop, one control
+ * step of 25 substeps at a time, App. E.3, with the network in front of it).
+ *
+ * mpm_surrogate_load: copy a trained grid U-Net into the context (replacing
+ * one loaded before).  weights: host blob of `bytes` bytes, little-endian:
+ *   int32 header[8] = {0x554E504D, 1, cin, cout, width, 15, 0, 0}
+ *   then for each of the 15 layers in order (e1a, e1b, d1, e2a, e2b, d2,
+ *   e3a, e3b, u2, c2a, c2b, u1, c1a, c1b, head): FP32 weights
+ *   [taps][ci][co] (taps 27 for 3^3 and upsampling layers, 8 for the
+ *   stride-2 layers, 1 for the head; z-major) and FP32 bias [co].
+ * Channels (ci -> co) at width 1: e1a ceil16(cin) -> 32 (weights of the
+ * padding channels ignored), e1b 32 -> 32, d1 32 -> 64, e2a/e2b 64 -> 64,
+ * d2 64 -> 128, e3a/e3b 128 -> 128, u2 128 -> 64, c2a 128 -> 64, c2b 64 -> 64,
+ * u1 64 -> 32, c1a 64 -> 32, c1b 32 -> 32, head 32 -> cout; width 2 halves
+ * every count but cin and cout.  cin <= 8 (the feature channels of
+ * mpm_sur_features), cout a multiple of 4 (channels 0-3 as in mpm_sur_block).
+ * The blob is borrowed for the call.  MPM_ERR_ARG for a malformed blob or a
+ * batch without one common grid resolution.
+ *
+ * mpm_step_blocks: run n_blocks control steps of every scene.  use_surrogate
+ * = 0: 25 plain substeps each (as mpm_step(ctx, 25 n_blocks)).
+ * use_surrogate = 1: per block, the box of the material (mpm_sur_bbox, read
+ * back to the host: the call waits once per block), the features on it, the
+ * network's prediction, and mpm_sur_block's control step with its residual
+ * gate at residual_threshold: scenes over it are put back and run the 25
+ * plain substeps.  *fallback_count (host, nullable) receives the number of
+ * scene-blocks that fell back; the call returns MPM_WARN_FALLBACK when any
+ * did.  MPM_ERR_STATE when no network is loaded.  Colliders advance by 25
+ * substeps per block either way. */
+mpm_status mpm_surrogate_load(mpm_ctx ctx, const void *weights, size_t bytes);
+mpm_status mpm_step_blocks(mpm_ctx ctx, int n_blocks, int use_surrogate, float residual_threshold,
+                           int *fallback_count);
+
+/* Residual of every scene in the last block mpm_step_blocks ran with the
+ * surrogate: out [n_scenes] (host).  MPM_ERR_STATE before any such block. */
+mpm_status mpm_surrogate_residuals(mpm_ctx ctx, float *out);
 
 /* Training targets between the start grids g0, g1 of two consecutive
  * control steps (both from mpm_sur_features on the whole grid): target

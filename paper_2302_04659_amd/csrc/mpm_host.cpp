@@ -18,8 +18,10 @@
 #include <vector>
 
 #include "../../include/mpm.h"
+#include "../../include/mpm_nn.h"
 #include "mpm_kernels.hpp"
 #include "mpm_types.hpp"
+#include "sur_net.hpp"
 
 static_assert(MPM_MAX_COLLIDERS == mpm::MAX_COLLIDERS_PER_SCENE, "grid kernel LDS collider slots");
 
@@ -98,6 +100,14 @@ struct mpm_ctx_s {
     int *d_sur_nfb = nullptr;
     float *d_wrench = nullptr;       // per collider: [6] impulse and angular impulse received, summed
     float *d_wrench_out = nullptr;   // [n_scenes][max_col][6] staging for mpm_get_collider_wrenches
+
+    // library-owned surrogate (mpm_surrogate_load / mpm_step_blocks): network and per-block arrays
+    mpm::SurNet *net = nullptr;
+    int *d_sb_box = nullptr, *d_sb_origin = nullptr;
+    float *d_sb_feat = nullptr, *d_sb_grid0 = nullptr, *d_sb_pred = nullptr, *d_sb_res = nullptr;
+    long long sb_nodes = 0;          // box nodes the per-block arrays hold
+    std::vector<int> h_sb_box;
+    std::vector<float> h_sb_res;     // residuals of the last surrogate block
 
     // debug capture of the P2G grid
     int capture = 0;
@@ -537,6 +547,7 @@ void release(mpm_ctx ctx)
     hipSetDevice(ctx->dev);
     if (ctx->stream) hipStreamSynchronize(ctx->stream);
     clear_graphs(ctx);
+    surnet_destroy(ctx->net);
     for (auto &p : ctx->ev_pending) {
         ctx->ev_pool.push_back(p.second.first);
         ctx->ev_pool.push_back(p.second.second);
@@ -548,7 +559,8 @@ void release(mpm_ctx ctx)
                     ctx->L.scene_item_begin, ctx->L.scene_gitem_begin, ctx->L.bflag, ctx->L.ovf, ctx->L.n_ovf, ctx->L.ibound, ctx->L.icell, ctx->L.touched,
                     ctx->d_flags, ctx->d_queue, ctx->d_scene_done, ctx->d_cap, ctx->d_cap_off, ctx->d_io,
                     ctx->d_active, ctx->d_sur_gend, ctx->d_sur_acc, ctx->d_sur_out, ctx->d_sur_nfb,
-                    ctx->d_wrench, ctx->d_wrench_out, ctx->d_sdf};
+                    ctx->d_wrench, ctx->d_wrench_out, ctx->d_sdf, ctx->d_sb_box, ctx->d_sb_origin, ctx->d_sb_feat,
+                    ctx->d_sb_grid0, ctx->d_sb_pred, ctx->d_sb_res};
     for (void *p : bufs)
         if (p) hipFree(p);
     for (int i = 0; i < STAGE_RING; i++) {
@@ -1160,10 +1172,13 @@ mpm_status mpm_sur_features(mpm_ctx ctx, float *feat, int cf, float *grid0, cons
     return MPM_OK;
 }
 
-mpm_status mpm_sur_block(mpm_ctx ctx, const float *pred, int cp, const float *grid0, const int *origin, int D, int H,
-                         int W, float threshold, int flags, float *residual, int *n_fallback)
+namespace {
+
+// One surrogate control step (mpm_sur_block); with MPM_SUR_SYNC, *host_fb (when
+// not NULL) receives the number of scenes that fell back.
+mpm_status sur_block_impl(mpm_ctx ctx, const float *pred, int cp, const float *grid0, const int *origin, int D, int H,
+                          int W, float threshold, int flags, float *residual, int *n_fallback, int *host_fb)
 {
-    ARGCHK(ctx, "null context");
     ARGCHK(pred && grid0, "pred and grid0 must not be NULL");
     ARGCHK(cp >= 4 && cp % 4 == 0, "cp must be a multiple of 4 and >= 4");
     ARGCHK(threshold >= 0.0f, "threshold must be >= 0");
@@ -1215,11 +1230,12 @@ mpm_status mpm_sur_block(mpm_ctx ctx, const float *pred, int cp, const float *gr
     if (n_fallback)
         HIPCHK(hipMemcpyAsync(n_fallback, ctx->d_sur_nfb, sizeof(int), hipMemcpyDeviceToDevice, ctx->stream));
     bool run_plain = fallback;
-    if (fallback && (flags & MPM_SUR_SYNC)) {
+    if (flags & MPM_SUR_SYNC) {
         int h = 0;
         HIPCHK(hipMemcpyAsync(&h, ctx->d_sur_nfb, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
-        run_plain = h > 0;
+        run_plain = fallback && h > 0;
+        if (host_fb) *host_fb = h;
     }
     if (run_plain) {
         // scenes over the threshold: back to the snapshot, then plain substeps on those scenes only
@@ -1234,6 +1250,140 @@ mpm_status mpm_sur_block(mpm_ctx ctx, const float *pred, int cp, const float *gr
                                        ctx->stream));
         ctx->since_sort += nsub;
     }
+    return MPM_OK;
+}
+
+}  // namespace
+
+mpm_status mpm_sur_block(mpm_ctx ctx, const float *pred, int cp, const float *grid0, const int *origin, int D, int H,
+                         int W, float threshold, int flags, float *residual, int *n_fallback)
+{
+    ARGCHK(ctx, "null context");
+    return sur_block_impl(ctx, pred, cp, grid0, origin, D, H, W, threshold, flags, residual, n_fallback, nullptr);
+}
+
+mpm_status mpm_surrogate_load(mpm_ctx ctx, const void *weights, size_t bytes)
+{
+    ARGCHK(ctx, "null context");
+    ARGCHK(weights, "weights must not be NULL");
+    ARGCHK(common_res(ctx) > 0, "the surrogate needs one grid resolution for all scenes");
+    hipSetDevice(ctx->dev);
+    std::string err;
+    int code = 0;
+    mpm::SurNet *net = mpm::surnet_load(weights, bytes, ctx->stream, &err, &code);
+    if (!net) {
+        ctx->last_error = err;
+        return code == -1 ? MPM_ERR_ARG : (code == -3 ? MPM_ERR_OOM : MPM_ERR_HIP);
+    }
+    if (mpm::surnet_cin(net) > 8 || mpm::surnet_cout(net) % 4) {
+        mpm::surnet_destroy(net);
+        ctx->last_error = "the surrogate network must read at most the 8 feature channels and give a multiple of 4 "
+                          "output channels";
+        return MPM_ERR_ARG;
+    }
+    mpm::surnet_destroy(ctx->net);
+    ctx->net = net;
+    return MPM_OK;
+}
+
+namespace {
+
+// Box of one surrogate block: the largest stencil extent of the batch plus a
+// margin of SB_MARGIN nodes on each side, rounded up to a multiple of 8 (the
+// network halves it twice) and at most the grid.
+constexpr int SB_MARGIN = 4;
+
+void block_box(const std::vector<int> &box, int n, int R, int dims[3])
+{
+    for (int d = 0; d < 3; d++) {
+        int ext = 0;
+        for (int s = 0; s < n; s++) ext = std::max(ext, box[6 * s + 3 + d] - box[6 * s + d]);
+        ext += 2 * SB_MARGIN;
+        ext = (ext + 7) / 8 * 8;
+        dims[d] = std::min(R, std::max(8, ext));
+    }
+}
+
+}  // namespace
+
+mpm_status mpm_step_blocks(mpm_ctx ctx, int n_blocks, int use_surrogate, float residual_threshold,
+                           int *fallback_count)
+{
+    ARGCHK(ctx, "null context");
+    ARGCHK(n_blocks >= 0, "n_blocks must be >= 0");
+    ARGCHK(residual_threshold >= 0.0f, "residual_threshold must be >= 0");
+    hipSetDevice(ctx->dev);
+    if (fallback_count) *fallback_count = 0;
+    if (!use_surrogate) return queue_substeps(ctx, GRAPH_BLOCK * n_blocks);
+    if (!ctx->net) {
+        ctx->last_error = "no surrogate loaded (mpm_surrogate_load)";
+        return MPM_ERR_STATE;
+    }
+    const int R = common_res(ctx);
+    ARGCHK(R > 0, "the surrogate needs one grid resolution for all scenes");
+    const int S = ctx->n_scenes;
+    if (S == 0 || n_blocks == 0) return MPM_OK;
+    if (!ctx->d_sb_box) HIPCHK(dalloc(&ctx->d_sb_box, (size_t)6 * S));
+    if (!ctx->d_sb_origin) HIPCHK(dalloc(&ctx->d_sb_origin, (size_t)3 * S));
+    if (!ctx->d_sb_res) HIPCHK(dalloc(&ctx->d_sb_res, (size_t)S));
+    ctx->h_sb_box.resize((size_t)6 * S);
+    const int cout = mpm::surnet_cout(ctx->net);
+    int total = 0;
+    for (int b = 0; b < n_blocks; b++) {
+        mpm_status st = mpm_sur_bbox(ctx, ctx->d_sb_box);
+        if (st != MPM_OK) return st;
+        HIPCHK(hipMemcpyAsync(ctx->h_sb_box.data(), ctx->d_sb_box, sizeof(int) * 6 * S, hipMemcpyDeviceToHost,
+                              ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        int dims[3];
+        block_box(ctx->h_sb_box, S, R, dims);
+        const long long nodes = (long long)S * dims[0] * dims[1] * dims[2];
+        if (nodes > ctx->sb_nodes) {
+            for (float **p : {&ctx->d_sb_feat, &ctx->d_sb_grid0, &ctx->d_sb_pred})
+                if (*p) {
+                    (void)hipFree(*p);
+                    *p = nullptr;
+                }
+            ctx->sb_nodes = 0;
+            HIPCHK(dalloc(&ctx->d_sb_feat, (size_t)8 * nodes));
+            HIPCHK(dalloc(&ctx->d_sb_grid0, (size_t)4 * nodes));
+            HIPCHK(dalloc(&ctx->d_sb_pred, (size_t)cout * nodes));
+            ctx->sb_nodes = nodes;
+        }
+        if (mpm_nn_crop_origin(ctx->d_sb_box, S, R, dims[0], dims[1], dims[2], ctx->d_sb_origin, ctx->stream) != 0) {
+            ctx->last_error = "surrogate box origin failed";
+            return MPM_ERR_HIP;
+        }
+        st = mpm_sur_features(ctx, ctx->d_sb_feat, 8, ctx->d_sb_grid0, ctx->d_sb_origin, dims[0], dims[1], dims[2]);
+        if (st != MPM_OK) return st;
+        std::string err;
+        const int r = mpm::surnet_forward(ctx->net, ctx->d_sb_feat, 8, S, dims[0], dims[1], dims[2], ctx->d_sb_pred,
+                                          ctx->stream, &err);
+        if (r != 0) {
+            ctx->last_error = err;
+            return r == -3 ? MPM_ERR_OOM : (r == -1 ? MPM_ERR_ARG : MPM_ERR_HIP);
+        }
+        int fb = 0;
+        st = sur_block_impl(ctx, ctx->d_sb_pred, cout, ctx->d_sb_grid0, ctx->d_sb_origin, dims[0], dims[1], dims[2],
+                            residual_threshold, MPM_SUR_SYNC, ctx->d_sb_res, nullptr, &fb);
+        if (st != MPM_OK) return st;
+        total += fb;
+    }
+    ctx->h_sb_res.resize(S);
+    HIPCHK(hipMemcpyAsync(ctx->h_sb_res.data(), ctx->d_sb_res, sizeof(float) * S, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (fallback_count) *fallback_count = total;
+    return total > 0 ? MPM_WARN_FALLBACK : MPM_OK;
+}
+
+mpm_status mpm_surrogate_residuals(mpm_ctx ctx, float *out)
+{
+    ARGCHK(ctx && out, "null argument");
+    if ((int)ctx->h_sb_res.size() != ctx->n_scenes) {
+        ctx->last_error = "no surrogate block has run (mpm_step_blocks)";
+        return MPM_ERR_STATE;
+    }
+    std::copy(ctx->h_sb_res.begin(), ctx->h_sb_res.end(), out);
     return MPM_OK;
 }
 

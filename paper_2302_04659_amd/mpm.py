@@ -85,6 +85,9 @@ def lib():
         L.mpm_sur_block.argtypes = [vp, vp, ct.c_int, vp, vp, ct.c_int, ct.c_int, ct.c_int, ct.c_float, ct.c_int, vp,
                                     vp]
         L.mpm_sur_targets.argtypes = [vp, vp, vp, vp, ct.c_int, vp]
+        L.mpm_surrogate_load.argtypes = [vp, ct.c_char_p, ct.c_size_t]
+        L.mpm_step_blocks.argtypes = [vp, ct.c_int, ct.c_int, ct.c_float, vp]
+        L.mpm_surrogate_residuals.argtypes = [vp, vp]
         for name in ("mpm_num_scenes", "mpm_max_colliders"):
             getattr(L, name).argtypes = [vp]
         L.mpm_num_particles.argtypes = [vp, ct.c_int]
@@ -267,6 +270,25 @@ class Sim:
     def sur_targets(self, g0, g1, target, mask):
         return self._check(self.L.mpm_sur_targets(self.h, _ptr(g0), _ptr(g1), _ptr(target), int(target.shape[-1]),
                                                   _ptr(mask)), "sur_targets")
+
+    def surrogate_load(self, blob: bytes):
+        """Hand the library a trained surrogate network (UNet.export_weights())."""
+        self._check(self.L.mpm_surrogate_load(self.h, blob, len(blob)), "surrogate_load")
+
+    def step_blocks(self, n_blocks: int = 1, use_surrogate: bool = True, threshold: float = 1e-3) -> int:
+        """n_blocks control steps (25 substeps each), through the loaded surrogate
+        with its residual gate when use_surrogate; returns the number of
+        scene-blocks that fell back to the plain substeps."""
+        fb = ct.c_int(0)
+        self._check(self.L.mpm_step_blocks(self.h, int(n_blocks), int(bool(use_surrogate)), float(threshold),
+                                           ct.byref(fb)), "step_blocks")
+        return int(fb.value)
+
+    def surrogate_residuals(self) -> np.ndarray:
+        """Per-scene residuals of the last surrogate block of step_blocks."""
+        r = np.zeros(self.n_scenes, np.float32)
+        self._check(self.L.mpm_surrogate_residuals(self.h, r.ctypes.data), "surrogate_residuals")
+        return r
 
     def sync(self):
         return self._check(self.L.mpm_sync(self.h), "sync")

@@ -154,6 +154,17 @@ class UNet:
             _chk(self.L.mpm_nn_pack(w.data_ptr(), KIND[kind], ci, co, 1, bw.data_ptr(), self.stream), "pack")
             self.packs[name] = (fw, bw)
 
+    def export_weights(self) -> bytes:
+        """The weight blob of mpm_surrogate_load (include/mpm.h): an int32
+        header, then every layer's FP32 weights [taps][ci][co] and bias in
+        network order."""
+        hdr = np.array([0x554E504D, 1, self.cin, self.cout, self.width, len(self.layers), 0, 0], "<i4")
+        parts = [hdr.tobytes()]
+        for name, kind, ci, co, _ in self.layers:
+            parts.append(np.ascontiguousarray(self.params[name + ".w"].detach().cpu().numpy(), "<f4").tobytes())
+            parts.append(np.ascontiguousarray(self.params[name + ".b"].detach().cpu().numpy(), "<f4").tobytes())
+        return b"".join(parts)
+
     def state_dict(self):
         return {k: v.detach().cpu().numpy() for k, v in self.params.items()}
 

@@ -427,3 +427,64 @@ def test_targets_definition(env):
         assert np.allclose(th[s, ..., 3], (b[s, ..., 0] - a[s, ..., 0]) / mu, rtol=1e-5, atol=3e-2)
         assert np.array_equal(mh[s], ((a[s, ..., 0] > 0) | (b[s, ..., 0] > 0)).astype(np.float32))
     sim.close()
+
+
+def test_step_blocks_matches_python_composition(env, orc):
+    """The library-owned control step (mpm_surrogate_load + mpm_step_blocks)
+    against the same step composed from the separate calls in Python
+    (surrogate.GridSurrogate), with one seeded network: no scene over a
+    huge threshold (particles and residuals agree up to the order of the
+    feature P2G's float flushes), every scene over a zero threshold (all
+    fall back: plain substeps, oracle bar), use_surrogate = 0 (plain
+    substeps); and the errors: no network loaded, a malformed blob."""
+    torch, mpm = env
+    from paper_2302_04659_amd import surrogate, unet
+    batch = [scenes.cfg2(seed=2000 + s, n_ctrl=2) for s in range(3)]
+    announce("step_blocks vs python composition", len(batch))
+    S = len(batch)
+    net = unet.UNet(cin=surrogate.CIN, cout=surrogate.COUT, width=2, seed=5)
+    blob = net.export_weights()
+    out = {}
+    for thr in (1e6, 0.0):
+        py = surrogate.make_sim(batch)
+        py.set_colliders_ctrl(0)
+        gs = surrogate.GridSurrogate(py, net, threshold=thr)
+        gs.block(fallback=True, sync=True)
+        torch.cuda.synchronize()
+        r_py, fb_py = gs.residual.cpu().numpy(), int(gs.n_fallback.item())
+        lib = mpm.Sim(batch)
+        lib.surrogate_load(blob)
+        lib.set_colliders_ctrl(0)
+        fb = lib.step_blocks(1, True, thr)
+        r_lib = lib.surrogate_residuals()
+        assert lib.sync() >= 0 and py.sync() >= 0
+        print("threshold", thr, "residuals python", r_py, "library", r_lib, "fallbacks", fb_py, fb)
+        assert fb == fb_py == (S if thr == 0.0 else 0)
+        assert np.allclose(r_lib, r_py, rtol=1e-3, atol=0.0)
+        for s, sc in enumerate(batch):
+            a, b = py.get_state(s), lib.get_state(s)
+            assert np.abs(a[0] - b[0]).max() <= 1e-4 * sc.dx
+            for u, w in zip(a[1:], b[1:]):
+                assert rel_l2(w, u) <= 1e-3
+        out[thr] = lib
+        py.close()
+    for s, sc in enumerate(batch):       # everything fell back: the plain control step
+        o = orc.Oracle(sc)
+        o.set_colliders(sc.ctrl_poses[0], sc.ctrl_vels[0])
+        o.step(25)
+        x, *_ = out[0.0].get_state(s)
+        assert np.abs(x - o.x).max() <= 1e-3 * sc.dx
+    plain = mpm.Sim(batch)
+    plain.set_colliders_ctrl(0)
+    assert plain.step_blocks(1, False) == 0
+    x_p, *_ = plain.get_state(-1)
+    x_f, *_ = out[0.0].get_state(-1)
+    assert np.abs(x_p - x_f).max() <= 1e-5 * batch[0].dx
+    with pytest.raises(mpm.MPMError) as e:
+        plain.step_blocks(1, True, 1e-3)
+    assert e.value.status == mpm.ERR_STATE
+    with pytest.raises(mpm.MPMError) as e:
+        plain.surrogate_load(blob[:-4])
+    assert e.value.status == mpm.ERR_ARG
+    for sim in (plain, *out.values()):
+        sim.close()
