@@ -138,8 +138,14 @@ def main():
     ap.add_argument("--cpu-substeps", type=int, default=50)
     ap.add_argument("--cpu-scenes-1t", type=int, default=8)
     ap.add_argument("--cpu-substeps-1t", type=int, default=25)
-    ap.add_argument("--train-steps", type=int, default=3000, help="cfg5: surrogate training steps")
-    ap.add_argument("--eval-scenes", type=int, default=256, help="cfg5: held-out scenes timed")
+    ap.add_argument("--train-steps", type=int, default=4000, help="surrogate: training steps")
+    ap.add_argument("--train-seeds", type=int, default=128, help="surrogate: cfg2 rollouts generated for training")
+    ap.add_argument("--train-blocks", type=int, default=20, help="surrogate: control steps per training rollout")
+    ap.add_argument("--eval-scenes", type=int, default=256, help="surrogate: held-out scenes timed")
+    ap.add_argument("--error-scenes", type=int, default=16, help="surrogate: held-out scenes judged by the oracle")
+    ap.add_argument("--error-blocks", type=int, default=2, help="surrogate: control steps judged per scene")
+    ap.add_argument("--gate", type=float, default=1e-3, help="surrogate: residual threshold of the fallback")
+    ap.add_argument("--no-surrogate", action="store_true", help="leave the surrogate section out of the default run")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed region, run a plain device-to-device copy of this many MiB three "
                          "times (the reference kernel for scaling HBM byte counters)")
@@ -262,8 +268,11 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(scene_list, min(args.cpu_scenes, len(scene_list)), args.cpu_substeps,
                                            min(args.cpu_scenes_1t, len(scene_list)), args.cpu_substeps_1t)
-    print(json.dumps(out), flush=True)
     sim.close()
+    if args.workload == "cfg3" and not args.no_surrogate and not args.no_cpu:
+        torch.cuda.empty_cache()
+        out["surrogate"] = surrogate_section(args)
+    print(json.dumps(out), flush=True)
 
 
 def unet_forward_flop(shape, cin: int = 8, cout: int = 4, width: int = 1) -> float:
@@ -280,114 +289,210 @@ def unet_forward_flop(shape, cin: int = 8, cout: int = 4, width: int = 1) -> flo
     return flop
 
 
-def bench_surrogate(args):
-    """cfg5: the grid U-Net surrogate with residual gate and fallback against
-    plain batched MPM on held-out slab-pushing scenes, one control step
-    (25 substeps) at a time."""
+def cpu_baseline_surrogate(ev, n_blocks):
+    """CPU-baseline leg of the surrogate section: the FP64 oracle run on the
+    held-out scenes for n_blocks control steps, timed; returns the timing and
+    each block's start state (FP32) and end positions, against which the GPU
+    runs are then measured (per-block error, each block from the oracle's
+    state)."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    orcs = [oracle.Oracle(sc) for sc in ev]
+    starts, ends = [], []
+    t = 0.0
+    for b in range(n_blocks):
+        st = []
+        for o, sc in zip(orcs, ev):
+            o.set_colliders(sc.ctrl_poses[b], sc.ctrl_vels[b])
+            st.append([a.astype(np.float32).copy() for a in (o.x, o.v, o.C, o.F)])
+        t0 = time.perf_counter()
+        for o in orcs:
+            o.step(25)
+        t += time.perf_counter() - t0
+        starts.append(st)
+        ends.append([o.x.copy() for o in orcs])
+    n = sum(sc.n for sc in ev)
+    timing = {"value": n * 25 * n_blocks / t, "unit": "particle-substeps/s", "cores": oracle.threads(),
+              "kind": "oracle", "sample": f"{len(ev)} held-out scenes ({n} particles) x {n_blocks} control steps "
+                                          f"of 25 substeps, FP64, {t:.1f} s wall"}
+    return timing, starts, ends
+
+
+def surrogate_section(args):
+    """The grid U-Net surrogate with its residual gate and plain-MPM fallback,
+    through the library's own control step (mpm_surrogate_load +
+    mpm_step_blocks), against plain batched MPM on held-out slab-pushing
+    scenes: training on rollouts the MPM generates, the speedup over plain
+    MPM at the residual gate and without it, the fallback fraction, and the
+    per-block position error judged by the FP64 oracle (from the oracle's
+    state at the start of every block) beside the predictors without a
+    network."""
     import numpy as np
     import torch
     from paper_2302_04659_amd import mpm, scenes, surrogate, unet
     t_start = time.perf_counter()
-    train_scenes = [scenes.cfg2(seed=s) for s in range(16)]
-    data = surrogate.RolloutData(train_scenes, n_blocks=8)
+    gate = args.gate
+    train_scenes = [scenes.cfg2(seed=s, n_ctrl=args.train_blocks + 1) for s in range(args.train_seeds)]
+    t0 = time.perf_counter()
+    data = surrogate.RolloutData(train_scenes, n_blocks=args.train_blocks)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
     train_shape = data.shape
     net = unet.UNet(cin=surrogate.CIN, cout=surrogate.COUT, width=1, seed=0)
     t0 = time.perf_counter()
-    log = surrogate.train(net, data, steps=args.train_steps, batch=8, lr=1e-3, log_every=max(args.train_steps // 4, 1))
+    log = surrogate.train(net, data, steps=args.train_steps, batch=8, lr=1e-3, lr_final=5e-5,
+                          log_every=max(args.train_steps // 4, 1))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    n_samples = data.n_samples
     del data
-    ev = [scenes.cfg2(seed=2000 + s) for s in range(args.eval_scenes)]
+    torch.cuda.empty_cache()
+    blob = net.export_weights()
+
+    ev = [scenes.cfg2(seed=2000 + s, n_ctrl=8) for s in range(args.eval_scenes)]
     n_blocks = 4
-    # plain batched MPM (graph replay of 25-substep blocks)
     plain = mpm.Sim(ev)
     plain.autotune(10)            # both sides run the tuned substep configuration
     tuned = {o: plain.get_option(o) for o in (mpm.OPT_BLOCK, mpm.OPT_CHUNK, mpm.OPT_SORT_EVERY)}
-    plain.set_option(mpm.OPT_GRAPH, 1)
-    plain.set_colliders_ctrl(0)
-    plain.step(25)
-    plain.sync()
-    t0 = time.perf_counter()
-    for b in range(1, n_blocks + 1):
-        plain.set_colliders_ctrl(b)
-        plain.step(25)
-    plain.sync()
-    t_plain = (time.perf_counter() - t0) / n_blocks
-    plain.close()
 
-    def run_surrogate(threshold, fallback=True):
-        sim = surrogate.make_sim(ev)
-        for o, v in tuned.items():
-            sim.set_option(o, v)
-        sim.set_option(mpm.OPT_GRAPH, 1)
-        gs = surrogate.GridSurrogate(sim, net, threshold=threshold)
+    def run(sim, use_surrogate, threshold):
         sim.set_colliders_ctrl(0)
-        gs.block(fallback=fallback)
-        torch.cuda.synchronize()
+        sim.step_blocks(1, use_surrogate, threshold)     # warm-up (graph capture, buffers)
+        sim.sync()
         fb, res = 0, []
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for b in range(1, n_blocks + 1):
             sim.set_colliders_ctrl(b)
-            gs.block(fallback=fallback)
-            fb += int(gs.n_fallback.item())
-            res.append(gs.residual.cpu().numpy())
+            fb += sim.step_blocks(1, use_surrogate, threshold)
+            if use_surrogate:
+                res.append(sim.surrogate_residuals())
+        st = sim.sync()
         torch.cuda.synchronize()
         t = (time.perf_counter() - t0) / n_blocks
-        st = sim.sync()
-        return sim, gs, t, fb / (n_blocks * len(ev)), np.concatenate(res), st
+        if st < 0:
+            raise SystemExit(f"simulation reported status {st}")
+        return t, fb / (n_blocks * len(ev)), (np.concatenate(res) if res else None)
 
-    sim, gs, t_sur, fb_frac, res, st = run_surrogate(1e-3)
-    # the network alone on the last crop, timed with events on its stream
-    _, fc, _, pc = gs._cbuf
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(gs.ts):
-        ev0.record()
-        for i in range(0, len(ev), gs.chunk):
-            j = min(len(ev), i + gs.chunk)
-            net.forward(fc[i:j], out=pc[i:j])
-        ev1.record()
+    plain.set_option(mpm.OPT_GRAPH, 1)
+    t_plain, _, _ = run(plain, False, 0.0)
+    plain.close()
+    out = {}
+    for name, thr in (("gate", gate), ("no_fallback", float("inf"))):
+        sim = mpm.Sim(ev)
+        for o, v in tuned.items():
+            sim.set_option(o, v)
+        sim.set_option(mpm.OPT_GRAPH, 1)
+        sim.surrogate_load(blob)
+        out[name] = run(sim, True, thr)
+        sim.close()
+    t_sur, fb_frac, res = out["gate"]
+    t_nofb = out["no_fallback"][0]
+
+    # per-block error against the oracle on a subset of the held-out scenes
+    sub = ev[: args.error_scenes]
+    cpu, starts, ends = cpu_baseline_surrogate(sub, args.error_blocks)
+    R, T = sub[0].res, 25 * sub[0].dt
+    err = {k: [] for k in ("surrogate", "surrogate_gated", "no_network", "gravity_only", "zero_update")}
+    sim = surrogate.make_sim(sub)
+    for o, v in tuned.items():
+        sim.set_option(o, v)
+    sim.surrogate_load(blob)
+    with torch.cuda.stream(sim.torch_stream):
+        keep = torch.zeros((len(sub), R, R, R, 4), dtype=torch.float32, device="cuda")
+        grav = torch.zeros_like(keep)
+        grav[..., 1] = -9.8 * T / 0.2
     torch.cuda.synchronize()
-    t_net = ev0.elapsed_time(ev1) * 1e-3
-    crop = gs.crop_shape
-    flop = unet_forward_flop(crop) * len(ev)
+    gs = surrogate.GridSurrogate(sim, net)
+    for b in range(args.error_blocks):
+        for name in err:
+            for s in range(len(sub)):
+                sim.set_state(*starts[b][s], scene=s)
+            sim.set_colliders_ctrl(b)
+            if name == "surrogate":
+                sim.step_blocks(1, True, float("inf"))
+            elif name == "surrogate_gated":
+                sim.step_blocks(1, True, gate)
+            elif name == "no_network":
+                gs.block_with(keep, fallback=False)
+            elif name == "gravity_only":
+                gs.block_with(grav, fallback=False)
+            torch.cuda.synchronize()
+            if sim.sync() < 0:
+                raise SystemExit("simulation error in the error run")
+            for s, sc in enumerate(sub):
+                x = starts[b][s][0] if name == "zero_update" else sim.get_state(s)[0]
+                e = np.linalg.norm(x.astype(np.float64) - ends[b][s], axis=1) / sc.dx
+                err[name].append((float(e.max()), float(np.sqrt((e ** 2).mean()))))
     sim.close()
-    sim, gs, t_sur2, fb_frac2, _, _ = run_surrogate(1e-2)
-    sim.close()
-    sim, gs, t_nofb, _, _, _ = run_surrogate(1e-3, fallback=False)
-    sim.close()
+    per_block = {k: {"max": max(a for a, _ in v), "rms": float(np.sqrt(np.mean([c * c for _, c in v])))}
+                 for k, v in err.items()}
+    # the network alone (the same kernels) on the training crop, batch = the timed scenes, event-timed
+    D, H, W = train_shape
+    with torch.cuda.stream(torch.cuda.Stream()):
+        x = torch.zeros((len(ev), D, H, W, surrogate.CIN), dtype=torch.float32, device="cuda")
+        y = torch.zeros((len(ev), D, H, W, surrogate.COUT), dtype=torch.float32, device="cuda")
+        net.forward(x, out=y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            net.forward(x, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        t_net = e0.elapsed_time(e1) * 1e-3 / 3
+    del x, y
+    flop = unet_forward_flop(train_shape) * len(ev)
+    return {
+        "speedup_at_gate": t_plain / t_sur,
+        "gate": gate,
+        "fallback_fraction_at_gate": fb_frac,
+        "speedup_without_fallback": t_plain / t_nofb,
+        "plain_ms_per_control_step": t_plain * 1e3,
+        "surrogate_ms_per_control_step": t_sur * 1e3,
+        "surrogate_no_fallback_ms_per_control_step": t_nofb * 1e3,
+        "residual": {"median": float(np.median(res)), "p10": float(np.percentile(res, 10)),
+                     "p90": float(np.percentile(res, 90)), "max": float(res.max())},
+        "per_block_error_dx": per_block,
+        "per_block_error_bar_dx": 2e-2,
+        "error_sample": f"{len(sub)} held-out scenes x {args.error_blocks} control steps, each started from the "
+                        f"oracle's state; max and RMS over particles of |x - x_oracle| / dx",
+        "cpu_baseline": cpu,
+        "workload": f"cfg5: grid U-Net (3 levels, 32/64/128, 3^3 convs) on a box around the material; trained "
+                    f"{args.train_steps} steps (Adam, batch 8, lr 1e-3 cosine to 5e-5) on {n_samples} samples = "
+                    f"{args.train_seeds} cfg2 rollouts x {args.train_blocks} control steps made on the GPU; timed on "
+                    f"{len(ev)} held-out cfg2 scenes (65,536 particles, 64^3 each), library control step "
+                    f"(mpm_step_blocks), residual gate {gate}",
+        "scenes": len(ev), "particles": int(sum(sc.n for sc in ev)), "train_crop": list(train_shape),
+        "unet_forward": {"bound": "mfma", "achieved": flop / t_net / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                         "frac": flop / t_net / 1e12 / 2500.0, "ms": t_net * 1e3,
+                         "shape": [len(ev), D, H, W]},
+        "train": {"steps": args.train_steps, "seconds": t_train, "data_seconds": t_data, "log": log},
+        "substep_config": {"block": tuned[mpm.OPT_BLOCK], "chunk": tuned[mpm.OPT_CHUNK],
+                           "sort_every": tuned[mpm.OPT_SORT_EVERY]},
+        "wall_s": time.perf_counter() - t_start,
+    }
+
+
+def bench_surrogate(args):
+    """cfg5 alone: one JSON line with the surrogate's speedup as the value."""
+    sec = surrogate_section(args)
     out = {
         "metric": "surrogate+fallback speedup over plain batched MPM (one control step)",
-        "value": t_plain / t_sur,
+        "value": sec["speedup_at_gate"],
         "unit": "x",
         "n_gpus": 1,
-        "steps": n_blocks * 25,
-        "warmup": 25,
-        "ms_per_step": t_sur * 1e3 / 25,
+        "steps": 4,
+        "warmup": 1,
+        "ms_per_step": sec["surrogate_ms_per_control_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": f"cfg5: grid U-Net (3 levels, 32/64/128, 3^3 convs) on a box around the material, "
-                               f"trained {args.train_steps} steps on 16 cfg2 rollouts x 8 control steps; timed on "
-                               f"{len(ev)} held-out cfg2 scenes (65,536 particles, 64^3 each), residual gate 1e-3",
-                   "scenes": len(ev), "particles": int(sum(sc.n for sc in ev)), "crop": list(crop),
-                   "train_crop": list(train_shape), "block": tuned[mpm.OPT_BLOCK], "chunk": tuned[mpm.OPT_CHUNK],
-                   "sort_every": tuned[mpm.OPT_SORT_EVERY]},
-        "plain_ms_per_control_step": t_plain * 1e3,
-        "surrogate_ms_per_control_step": t_sur * 1e3,
-        "fallback_fraction": fb_frac,
-        "residual": {"median": float(np.median(res)), "p10": float(np.percentile(res, 10)),
-                     "p90": float(np.percentile(res, 90))},
-        "at_threshold_1e-2": {"speedup": t_plain / t_sur2, "fallback_fraction": fb_frac2,
-                              "surrogate_ms_per_control_step": t_sur2 * 1e3},
-        "without_fallback": {"speedup": t_plain / t_nofb, "surrogate_ms_per_control_step": t_nofb * 1e3},
-        "status": int(st),
-        "train": {"steps": args.train_steps, "seconds": t_train, "log": log},
-        "roofline": {"bound": "mfma", "kernel": "U-Net forward (all convolutions, BF16)",
-                     "achieved": flop / t_net / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
-                     "frac": flop / t_net / 1e12 / 2500.0, "traffic": None},
-        "wall_s": time.perf_counter() - t_start,
+        "config": {"workload": sec["workload"], "scenes": sec["scenes"], "particles": sec["particles"]},
+        "surrogate": sec,
+        "cpu_baseline": sec["cpu_baseline"],
     }
     print(json.dumps(out), flush=True)
 

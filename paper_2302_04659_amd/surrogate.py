@@ -168,65 +168,107 @@ class GridSurrogate:
 
 # ---------------------------------------------------------------------- data
 class RolloutData:
-    """Start grids and features of consecutive control steps of plain MPM
-    rollouts, and the targets between them (all on the device)."""
+    """Features of the start of consecutive control steps of plain MPM
+    rollouts and the targets (grid change over the step) after them, on the
+    device, cropped to one box shape around each sample's material.
 
-    def __init__(self, scene_list: Sequence, n_blocks: int, crop: bool = True, margin: int = 4):
+    The rollouts run in chunks of `chunk` scenes: a first pass records the
+    stencil box of every scene at every control-step boundary (the box shape
+    covers the material at the start and the end of every step, plus
+    `margin` nodes), a second pass reruns them and keeps the crops, so only
+    one chunk of whole-grid arrays is held at a time."""
+
+    def __init__(self, scene_list: Sequence, n_blocks: int, crop: bool = True, margin: int = 4, chunk: int = 32):
         torch = _torch()
-        sim = make_sim(scene_list)
-        S, R = sim.n_scenes, scene_list[0].res
+        S, R = len(scene_list), scene_list[0].res
         self.S, self.R, self.n_blocks = S, R, n_blocks
+        chunk = max(1, min(int(chunk), S))
+        shape = (R, R, R)
+        if crop:
+            boxes = []
+            for c0 in range(0, S, chunk):
+                boxes.append(self._boxes(scene_list[c0:c0 + chunk], n_blocks))
+            bb = np.concatenate(boxes)
+            shape = crop_shape(bb, margin, R)
+        self.shape = shape
+        D, H, W = shape
+        with torch.cuda.device(0):
+            self.feat = torch.zeros((n_blocks, S, D, H, W, CIN), dtype=torch.float32, device="cuda")
+            self.target = torch.zeros((n_blocks, S, D, H, W, COUT), dtype=torch.float32, device="cuda")
+            self.mask = torch.zeros((n_blocks, S, D, H, W), dtype=torch.float32, device="cuda")
+        for c0 in range(0, S, chunk):
+            self._fill(scene_list[c0:c0 + chunk], c0, n_blocks, crop)
+
+    @staticmethod
+    def _boxes(scenes_c, n_blocks):
+        """[n][6] stencil boxes (inclusive) of every scene over every step of its rollout."""
+        torch = _torch()
+        sim = make_sim(scenes_c)
+        n = len(scenes_c)
+        out = np.zeros((n, 6), np.int64)
+        out[:, :3], out[:, 3:] = 1 << 30, -1
         with torch.cuda.stream(sim.torch_stream):
-            self.feat = torch.zeros((n_blocks, S, R, R, R, CIN), dtype=torch.float32, device="cuda")
-            self.target = torch.zeros((n_blocks, S, R, R, R, COUT), dtype=torch.float32, device="cuda")
-            self.mask = torch.zeros((n_blocks, S, R, R, R), dtype=torch.float32, device="cuda")
-            g_prev = torch.zeros((S, R, R, R, 4), dtype=torch.float32, device="cuda")
-            g_next = torch.zeros_like(g_prev)
-            f_next = torch.zeros((S, R, R, R, CIN), dtype=torch.float32, device="cuda")
-            sim.set_colliders_ctrl(0)
-            sim.sur_features(self.feat[0], g_prev)
-            for b in range(n_blocks):
-                sim.step(SUBSTEPS)
-                k = min(b + 1, scene_list[0].n_ctrl - 1)
+            box = torch.zeros((n, 6), dtype=torch.int32, device="cuda")
+            for b in range(n_blocks + 1):
+                if b:
+                    sim.step(SUBSTEPS)
+                k = min(b, scenes_c[0].n_ctrl - 1)
                 sim.set_colliders_ctrl(k)
-                dst = self.feat[b + 1] if b + 1 < n_blocks else f_next
-                sim.sur_features(dst, g_next)
-                sim.sur_targets(g_prev, g_next, self.target[b], self.mask[b])
-                g_prev, g_next = g_next, g_prev
+                sim.sur_bbox(box)
+                h = box.cpu().numpy()
+                out[:, :3] = np.minimum(out[:, :3], h[:, :3])
+                out[:, 3:] = np.maximum(out[:, 3:], h[:, 3:] + 1)   # one node past the stencil
         st = sim.sync()
-        torch.cuda.synchronize()
+        sim.close()
         if st < 0:
             raise RuntimeError(f"rollout failed ({st})")
-        sim.close()
-        self.shape = (R, R, R)
-        if crop:
-            self._crop(margin)
+        return out
 
-    def _crop(self, margin: int):
-        """Keep a box around each sample's material (start or end of the
-        step): the network trains on the same kind of crop it runs on."""
+    def _fill(self, scenes_c, s0, n_blocks, crop):
         torch = _torch()
-        L = _unet_lib()
-        n, R = self.n_blocks * self.S, self.R
-        s = torch.cuda.current_stream().cuda_stream
-        box = torch.zeros((n, 6), dtype=torch.int32, device="cuda")
-        origin = torch.zeros((n, 3), dtype=torch.int32, device="cuda")
-        if L.mpm_nn_bbox(self.mask.data_ptr(), 1, n, R, box.data_ptr(), s) != 0:
-            raise RuntimeError("mpm_nn_bbox failed")
-        shape = crop_shape(box.cpu().numpy(), margin, R)
-        D, H, W = shape
-        if L.mpm_nn_crop_origin(box.data_ptr(), n, R, D, H, W, origin.data_ptr(), s) != 0:
-            raise RuntimeError("mpm_nn_crop_origin failed")
-        out = []
-        for src, c in ((self.feat, CIN), (self.target, COUT), (self.mask, 1)):
-            dst = torch.zeros((n, D, H, W, c), dtype=torch.float32, device="cuda")
-            _crop_all(L, s, src, c, n, R, origin, shape, dst)
-            out.append(dst)
+        n, R = len(scenes_c), self.R
+        sim = make_sim(scenes_c)
+        with torch.cuda.stream(sim.torch_stream):
+            feat = torch.zeros((n_blocks, n, R, R, R, CIN), dtype=torch.float32, device="cuda")
+            target = torch.zeros((n_blocks, n, R, R, R, COUT), dtype=torch.float32, device="cuda")
+            mask = torch.zeros((n_blocks, n, R, R, R), dtype=torch.float32, device="cuda")
+            g_prev = torch.zeros((n, R, R, R, 4), dtype=torch.float32, device="cuda")
+            g_next = torch.zeros_like(g_prev)
+            f_next = torch.zeros((n, R, R, R, CIN), dtype=torch.float32, device="cuda")
+            sim.set_colliders_ctrl(0)
+            sim.sur_features(feat[0], g_prev)
+            for b in range(n_blocks):
+                sim.step(SUBSTEPS)
+                k = min(b + 1, scenes_c[0].n_ctrl - 1)
+                sim.set_colliders_ctrl(k)
+                dst = feat[b + 1] if b + 1 < n_blocks else f_next
+                sim.sur_features(dst, g_next)
+                sim.sur_targets(g_prev, g_next, target[b], mask[b])
+                g_prev, g_next = g_next, g_prev
+            if not crop:
+                self.feat[:, s0:s0 + n] = feat
+                self.target[:, s0:s0 + n] = target
+                self.mask[:, s0:s0 + n] = mask
+            else:
+                L = _unet_lib()
+                st_ = sim.torch_stream.cuda_stream
+                m = n_blocks * n
+                box = torch.zeros((m, 6), dtype=torch.int32, device="cuda")
+                origin = torch.zeros((m, 3), dtype=torch.int32, device="cuda")
+                if L.mpm_nn_bbox(mask.data_ptr(), 1, m, R, box.data_ptr(), st_) != 0:
+                    raise RuntimeError("mpm_nn_bbox failed")
+                D, H, W = self.shape
+                if L.mpm_nn_crop_origin(box.data_ptr(), m, R, D, H, W, origin.data_ptr(), st_) != 0:
+                    raise RuntimeError("mpm_nn_crop_origin failed")
+                for src, c, dst in ((feat, CIN, self.feat), (target, COUT, self.target), (mask, 1, self.mask)):
+                    tmp = torch.zeros((m, D, H, W, c), dtype=torch.float32, device="cuda")
+                    _crop_all(L, st_, src, c, m, R, origin, self.shape, tmp)
+                    dst[:, s0:s0 + n] = tmp.view((n_blocks, n, D, H, W) + ((c,) if dst.dim() == 6 else ()))
+        st = sim.sync()
         torch.cuda.synchronize()
-        self.feat = out[0].view(self.n_blocks, self.S, D, H, W, CIN)
-        self.target = out[1].view(self.n_blocks, self.S, D, H, W, COUT)
-        self.mask = out[2].view(self.n_blocks, self.S, D, H, W)
-        self.shape = shape
+        sim.close()
+        if st < 0:
+            raise RuntimeError(f"rollout failed ({st})")
 
     @property
     def n_samples(self):
@@ -241,8 +283,10 @@ class RolloutData:
 
 
 def train(net: UNet, data: RolloutData, steps: int, batch: int = 8, lr: float = 3e-4, seed: int = 0,
-          log_every: int = 50, holdout: Optional[RolloutData] = None) -> List[Dict]:
-    """Adam on the masked MSE of the targets; returns a loss log."""
+          log_every: int = 50, holdout: Optional[RolloutData] = None, lr_final: Optional[float] = None) -> List[Dict]:
+    """Adam on the masked MSE of the targets; returns a loss log.  With
+    lr_final the step size falls from lr to lr_final on a cosine over the
+    run."""
     torch = _torch()
     sh = tuple(data.shape)
     rng = np.random.default_rng(seed)
@@ -254,7 +298,10 @@ def train(net: UNet, data: RolloutData, steps: int, batch: int = 8, lr: float = 
     for it in range(1, steps + 1):
         idx = rng.choice(data.n_samples, size=batch, replace=False)
         data.batch(idx, xb, tb, mb)
-        loss = net.train_step(xb, tb.view(-1, COUT), mb.view(-1), lr=lr)
+        lr_t = lr
+        if lr_final is not None:
+            lr_t = lr_final + 0.5 * (lr - lr_final) * (1.0 + np.cos(np.pi * (it - 1) / max(steps - 1, 1)))
+        loss = net.train_step(xb, tb.view(-1, COUT), mb.view(-1), lr=lr_t)
         if it % log_every == 0 or it == steps:
             rec = {"step": it, "loss": loss.value(), "s": time.perf_counter() - t0}
             if holdout is not None:

@@ -1,17 +1,23 @@
 """What the trained surrogate gains over having no network.
 
 A small U-Net (half width) is trained on plain-MPM rollouts of seeded
-slab-pushing scenes, then judged per control step (25 substeps) against the
-FP64 oracle on held-out scenes: every block starts from the oracle's state
-rounded to FP32, and the error is the distance of each particle from the
-oracle's position after the block (max and RMS, in grid cells).
+slab-pushing scenes, handed to the library (mpm_surrogate_load) and run
+through its control step (mpm_step_blocks, no fallback), then judged per
+control step (25 substeps) against the FP64 oracle on held-out scenes:
+every block starts from the oracle's state rounded to FP32, and the error is
+the distance of each particle from the oracle's position after the block
+(max and RMS, in grid cells).
 
-The gain criteria: the trained network's error is below both the
-zero-update predictor (particles frozen for the block) and the gravity-only
-predictor (every node's velocity changes by 25 dt g); it meets the 2e-2 dx
-per-block bar; and its re-splat residual is below the untrained network's
-for every scene and block, so at any gate threshold it falls back no more
-often.
+At these speeds every predictor below stays inside the 2e-2 dx per-block
+bar (particles move about 0.016 dx per block), so the bar itself shows no
+gain.  The gain criteria are comparisons: the trained network's error (max
+and RMS) is below that of
+  * the method without the network (no velocity change predicted: the
+    particles keep their velocities and move with the start field),
+  * the gravity-only predictor (every node's velocity changes by 25 dt g),
+  * the zero-update predictor (particles frozen for the block);
+and its re-splat residual is below the untrained network's for every scene
+and block, so at any gate threshold it falls back no more often.
 """
 import numpy as np
 import pytest
@@ -44,9 +50,12 @@ def test_trained_surrogate_beats_baselines(orc):
     with torch.cuda.stream(sim.torch_stream):
         g_pred = torch.zeros((N_EVAL, R, R, R, 4), dtype=torch.float32, device="cuda")
         g_pred[..., 1] = -9.8 * T / 0.2
+        keep = torch.zeros((N_EVAL, R, R, R, 4), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
-    err = {k: [] for k in ("trained", "gravity", "zero")}
+    blobs = {"trained": net.export_weights(), "untrained": untrained.export_weights()}
+    err = {k: [] for k in ("trained", "no_network", "gravity", "zero")}
     res = {k: [] for k in ("trained", "untrained")}
+    gs = surrogate.GridSurrogate(sim, net, chunk=N_EVAL)
     for b in range(N_BLOCKS_EVAL):
         start = []
         for o, sc in zip(orcs, ev):
@@ -54,19 +63,18 @@ def test_trained_surrogate_beats_baselines(orc):
             start.append([a.astype(np.float32).copy() for a in (o.x, o.v, o.C, o.F)])
         for o in orcs:
             o.step(25)
-        for name in ("trained", "untrained", "gravity"):
+        for name in ("trained", "untrained", "no_network", "gravity"):
             for s in range(N_EVAL):
                 sim.set_state(*start[s], scene=s)
             sim.set_colliders_ctrl(b)
-            gs = surrogate.GridSurrogate(sim, untrained if name == "untrained" else net, chunk=N_EVAL)
-            if name == "gravity":
-                gs.block_with(g_pred, fallback=False)
+            if name in blobs:
+                sim.surrogate_load(blobs[name])
+                sim.step_blocks(1, True, float("inf"))
+                res[name].append(sim.surrogate_residuals().astype(np.float64))
             else:
-                gs.block(fallback=False)
+                gs.block_with(g_pred if name == "gravity" else keep, fallback=False)
             torch.cuda.synchronize()
             assert sim.sync() >= 0
-            if name in res:
-                res[name].append(gs.residual.cpu().numpy().astype(np.float64))
             if name in err:
                 for s in range(N_EVAL):
                     x, *_ = sim.get_state(s)
@@ -79,8 +87,9 @@ def test_trained_surrogate_beats_baselines(orc):
     print("per-block error (mean of max, mean of rms) in dx:", summary)
     rt, ru = np.concatenate(res["trained"]), np.concatenate(res["untrained"])
     print("residual trained", rt, "untrained", ru)
-    assert max(a for a, _ in err["trained"]) <= 2e-2
-    for base in ("gravity", "zero"):
+    for name in err:
+        assert max(a for a, _ in err[name]) <= 2e-2, name
+    for base in ("no_network", "gravity", "zero"):
         assert summary["trained"][0] < summary[base][0], base
         assert summary["trained"][1] < summary[base][1], base
     assert np.all(rt < ru)
