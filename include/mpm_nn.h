@@ -58,6 +58,22 @@ int mpm_nn_wgrad(int kind, const uint16_t *x, int n, int id, int ih, int iw, int
                  const uint16_t *g, int cg, int g_off, int cout, long long chunk, float *partial, float *gw,
                  int accumulate, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * weight gradient as mpm_nn_wgrad with its partial sums kept in a scratch
+ * array the library holds on every GPU it runs on (MPM_NN_SCRATCH_BYTES,
+ * reserved from the first call on a device until the process ends).  The
+ * call allocates nothing.  Returns -3 when the partial sums,
+ * ceil(voxels / chunk) * taps * cin * cout floats, exceed the scratch (raise
+ * chunk); otherwise as mpm_nn_wgrad.  Every call on one GPU uses the same
+ * scratch, which keeps the last call's values (each call writes every
+ * partial it reads, so nothing needs clearing): calls that may run
+ * concurrently on one GPU (different streams, host threads) race. */
+#define MPM_NN_SCRATCH_BYTES (32LL << 20)
+int mpm_nn_wgrad_noalloc(int kind, const uint16_t *x, int n, int id, int ih, int iw, int cx, int x_off, int cin,
+                         const uint16_t *g, int cg, int g_off, int cout, long long chunk, float *gw, int accumulate,
+                         void *stream);
+
 /* gb[co] (+)= sum over voxels of g[voxel][g_off + co] (cout <= 128; the
  * partial sums are added with float atomics, so the summation order -- and
  * the last bit -- may differ between calls). */

@@ -1,6 +1,8 @@
 // C ABI of the surrogate kernels (argument checks + launches).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "../../include/mpm_nn.h"
 #include "nn_kernels.hpp"
 
@@ -17,6 +19,59 @@ void out_size(int kind, int id, int ih, int iw, int &od, int &oh, int &ow)
     if (kind == 1) { od = 2 * id; oh = 2 * ih; ow = 2 * iw; }
     else if (kind == 2) { od = id / 2; oh = ih / 2; ow = iw / 2; }
     else { od = id; oh = ih; ow = iw; }
+}
+
+// Partial sums of the allocation-free weight gradient (mpm_nn_wgrad_noalloc):
+// one array per GPU, held until the process ends.  Host code never passes
+// its name to a kernel: the device address comes from hipGetSymbolAddress,
+// once per device (scratch_of_device).
+constexpr long long NN_SCRATCH_FLOATS = MPM_NN_SCRATCH_BYTES / sizeof(float);
+static_assert(MPM_NN_SCRATCH_BYTES % 256 == 0, "scratch size");
+__device__ __align__(256) float scratch[NN_SCRATCH_FLOATS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+float *scratch_dev[MAX_DEVICES] = {};
+
+// Device address of the current device's scratch, looked up on first use.
+int scratch_of_device(float **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -2;
+    if (dev < 0 || dev >= MAX_DEVICES) return -1;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -2;
+        scratch_dev[dev] = (float *)p;
+    }
+    *out = scratch_dev[dev];
+    return 0;
+}
+
+// Weight gradient with its partial sums in `partial` (cap floats, or < 0:
+// the caller sized it).  -3 when the partial sums do not fit in cap.
+int wgrad_call(int kind, const uint16_t *x, int n, int id, int ih, int iw, int cx, int x_off, int cin,
+               const uint16_t *g, int cg, int g_off, int cout, long long chunk, float *partial, long long cap, float *gw,
+               int accumulate, void *stream)
+{
+    if (!kind_ok(kind) || !x || !g || !partial || !gw || n <= 0 || chunk < 16 || chunk % 16) return -1;
+    if (!c16(cin) || cin > 128 || cout <= 0 || cout > 128 || x_off + cin > cx || g_off + cout > cg) return -1;
+    if (id <= 0 || ih <= 0 || iw <= 0) return -1;
+    const int nf = (cout + 15) / 16;
+    if (nf != 1 && nf != 2 && nf != 4 && nf != 8) return -1;
+    nn::WgradArgs a{};
+    a.kind = kind;
+    a.x = x; a.n = n; a.id = id; a.ih = ih; a.iw = iw; a.cx = cx; a.x_off = x_off; a.cin = cin;
+    a.g = g; a.cg = cg; a.g_off = g_off; a.cout = cout;
+    out_size(kind, id, ih, iw, a.od, a.oh, a.ow);
+    a.chunk = chunk; a.partial = partial; a.gw = gw; a.accumulate = accumulate;
+    if (cap >= 0) {
+        const long long nvox = (long long)n * a.od * a.oh * a.ow;
+        const long long need = (nvox + chunk - 1) / chunk * taps_of(kind) * cin * cout;
+        if (need > cap) return -3;
+    }
+    return st_of(nn::wgrad(a, (hipStream_t)stream));
 }
 
 }  // namespace
@@ -58,17 +113,20 @@ int mpm_nn_wgrad(int kind, const uint16_t *x, int n, int id, int ih, int iw, int
                  const uint16_t *g, int cg, int g_off, int cout, long long chunk, float *partial, float *gw,
                  int accumulate, void *stream)
 {
-    if (!kind_ok(kind) || !x || !g || !partial || !gw || n <= 0 || chunk < 16 || chunk % 16) return -1;
-    if (!c16(cin) || cin > 128 || cout <= 0 || cout > 128 || x_off + cin > cx || g_off + cout > cg) return -1;
-    const int nf = (cout + 15) / 16;
-    if (nf != 1 && nf != 2 && nf != 4 && nf != 8) return -1;
-    nn::WgradArgs a{};
-    a.kind = kind;
-    a.x = x; a.n = n; a.id = id; a.ih = ih; a.iw = iw; a.cx = cx; a.x_off = x_off; a.cin = cin;
-    a.g = g; a.cg = cg; a.g_off = g_off; a.cout = cout;
-    out_size(kind, id, ih, iw, a.od, a.oh, a.ow);
-    a.chunk = chunk; a.partial = partial; a.gw = gw; a.accumulate = accumulate;
-    return st_of(nn::wgrad(a, (hipStream_t)stream));
+    if (!partial) return -1;
+    return wgrad_call(kind, x, n, id, ih, iw, cx, x_off, cin, g, cg, g_off, cout, chunk, partial, -1, gw, accumulate,
+                      stream);
+}
+
+int mpm_nn_wgrad_noalloc(int kind, const uint16_t *x, int n, int id, int ih, int iw, int cx, int x_off, int cin,
+                         const uint16_t *g, int cg, int g_off, int cout, long long chunk, float *gw, int accumulate,
+                         void *stream)
+{
+    float *ptr = nullptr;
+    const int r = scratch_of_device(&ptr);
+    if (r) return r;
+    return wgrad_call(kind, x, n, id, ih, iw, cx, x_off, cin, g, cg, g_off, cout, chunk, ptr, NN_SCRATCH_FLOATS, gw,
+                      accumulate, stream);
 }
 
 int mpm_nn_bias_grad(const uint16_t *g, long long voxels, int cg, int g_off, int cout, float *gb, int accumulate,
