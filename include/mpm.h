@@ -369,8 +369,10 @@ mpm_status mpm_surrogate_residuals(mpm_ctx ctx, float *out);
 /* Training targets between the start grids g0, g1 of two consecutive
  * control steps (both from mpm_sur_features on the whole grid): target
  * [n][R^3][ct] (ct >= 4)
- * = ((v1 - v0) in 0.2 m/s, (m1 - m0) in rho dx^3 / 32), mask [n][R^3] = 1
- * where m0 > 0 or m1 > 0, else 0. */
+ * = ((v1 - v0) in 0.2 m/s, (m1 - m0) in rho dx^3 / 32), and a loss weight
+ * mask [n][R^3] = min(1, max(m0, m1) / (rho dx^3)) where m0 > 0 or m1 > 0
+ * (positive there), else 0: the node's share of a filled cell's mass, as
+ * the residual gate weighs velocity errors by mass. */
 mpm_status mpm_sur_targets(mpm_ctx ctx, const float *g0, const float *g1, float *target, int ct, float *mask);
 
 /* Introspection. */

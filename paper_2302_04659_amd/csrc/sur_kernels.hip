@@ -443,7 +443,10 @@ hipError_t launch_sur_restore(const float *Psnap, float *P, long long pstride, c
 }
 
 // Training targets from the start grids of two consecutive control steps:
-// target = ((v1 - v0) / vel unit, (m1 - m0) / mass-change unit), mask = m0 > 0 or m1 > 0.
+// target = ((v1 - v0) / vel unit, (m1 - m0) / mass-change unit), and a loss
+// weight mask = min(1, max(m0, m1) / (rho dx^3)) where m0 > 0 or m1 > 0, else 0
+// (the node's share of a filled cell's mass: the residual gate weighs
+// velocity errors by mass).
 __global__ __launch_bounds__(WG) void k_sur_targets(StepArgs a, int res, const float *g0, const float *g1, int ct,
                                                     float *target, float *mask)
 {
@@ -458,7 +461,8 @@ __global__ __launch_bounds__(WG) void k_sur_targets(StepArgs a, int res, const f
         tp[1] = (w.z - u.z) * (1.0f / SUR_VEL);
         tp[2] = (w.w - u.w) * (1.0f / SUR_VEL);
         tp[3] = (w.x - u.x) * inv_mu;
-        mask[e] = (u.x > 0.0f || w.x > 0.0f) ? 1.0f : 0.0f;
+        const float mfill = fmaxf(u.x, w.x) * (S.vol / (S.mass * S.dx * S.dx * S.dx));
+        mask[e] = (u.x > 0.0f || w.x > 0.0f) ? fmaxf(fminf(mfill, 1.0f), 1e-30f) : 0.0f;
     }
 }
 
