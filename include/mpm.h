@@ -214,11 +214,13 @@ typedef enum {
     MPM_OPT_GRAPH = 4,          /* 1: replay a captured hipGraph for 25-substep blocks */
     MPM_OPT_CAPTURE_GRID = 5,   /* 1: keep the last P2G grid for mpm_get_grid (slow, debug) */
     MPM_OPT_TIMING = 6,         /* 1: time every kernel launch with HIP events (see mpm_get_timing) */
-    MPM_OPT_CONTACT = 7         /* collider contact, default 0 (Sec. 3 names both models):
+    MPM_OPT_CONTACT = 7,        /* collider contact, default 0 (Sec. 3 names both models):
                                  * 0: on grid nodes (separating projection with Coulomb friction);
                                  * 1: particle penalty: a particle inside a collider after its
                                  *    position update gets -phi n / (4 dt) (stiffness m / (4 dt^2));
                                  * 2: both.  Either reaction goes into mpm_get_collider_wrenches. */
+    MPM_OPT_WG = 8              /* threads per workgroup of the particle kernels (P2G, G2P): 256
+                                 * (default) or 512 */
 } mpm_option;
 
 /* Kernel classes reported by mpm_get_timing. */
@@ -229,9 +231,17 @@ typedef enum {
 mpm_status mpm_set_option(mpm_ctx ctx, int option, int value);
 mpm_status mpm_get_option(mpm_ctx ctx, int option, int *value);
 
-/* Time the candidate tunings (block edge, chunk size, persistent launch,
- * sort cadence) on the live scenes for `substeps` substeps each, keep the
- * fastest, and restore the particle state afterwards.  Writes a one-line
+/* Time the candidate tunings on the live scenes for `substeps` substeps each
+ * (at least one re-sort period): every block edge (4, 8) x chunk size (512,
+ * 2048, 8192) x sort cadence (10, 25, 50) with 256-thread workgroups, then
+ * 512-thread workgroups at the fastest of those; keep the fastest, and
+ * restore the particle state, the collider table and the collider wrench
+ * sums afterwards.  The result is cached per (GPU architecture, grid
+ * resolutions, particle-count bucket, one or many scenes), for the process
+ * and in a text file ($MPM_AUTOTUNE_CACHE, else
+ * $XDG_CACHE_HOME/mpm_mi355x_autotune.txt, else
+ * $HOME/.cache/mpm_mi355x_autotune.txt; unreadable or unwritable files are
+ * ignored): a cached tuning is applied without trials.  Writes a one-line
  * JSON report to report[0 .. report_len) when report is non-NULL. */
 mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_len);
 

@@ -8,8 +8,11 @@
 // returns; only mpm_sync and host-side reads wait.
 #include <hip/hip_runtime.h>
 
+#include <sys/stat.h>
+
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -82,6 +85,7 @@ struct mpm_ctx_s {
 
     // sort and work lists
     int B = 4, CH = 2048, sort_every = 25, since_sort = 1 << 30;
+    int nt = 256;                    // threads per workgroup of P2G and G2P (MPM_OPT_WG)
     int T = 0, T_cap = 0;
     int *d_scene_bin_off = nullptr;
     unsigned *d_keys = nullptr;
@@ -394,6 +398,7 @@ StepArgs step_args(mpm_ctx ctx, int substep)
     a.wrench = ctx->d_wrench;
     a.sdf = ctx->d_sdf;
     a.contact = ctx->contact;
+    a.nt = ctx->nt;
     return a;
 }
 
@@ -1022,6 +1027,11 @@ mpm_status mpm_set_option(mpm_ctx ctx, int option, int value)
         ARGCHK(value == 0 || value == 1, "graph must be 0 or 1");
         ctx->graph = value;
         return MPM_OK;
+    case MPM_OPT_WG:
+        ARGCHK(value == 256 || value == 512, "workgroup size must be 256 or 512");
+        ctx->nt = value;
+        clear_graphs(ctx);   // the captured kernels depend on it
+        return MPM_OK;
     case MPM_OPT_CONTACT:
         ARGCHK(value >= 0 && value <= 2, "contact must be 0, 1 or 2");
         ctx->contact = value;
@@ -1054,6 +1064,7 @@ mpm_status mpm_get_option(mpm_ctx ctx, int option, int *value)
     case MPM_OPT_PERSISTENT: *value = ctx->persistent; return MPM_OK;
     case MPM_OPT_GRAPH: *value = ctx->graph; return MPM_OK;
     case MPM_OPT_CONTACT: *value = ctx->contact; return MPM_OK;
+    case MPM_OPT_WG: *value = ctx->nt; return MPM_OK;
     case MPM_OPT_CAPTURE_GRID: *value = ctx->capture; return MPM_OK;
     case MPM_OPT_TIMING: *value = ctx->timing; return MPM_OK;
     }
@@ -1400,8 +1411,10 @@ mpm_status mpm_sur_targets(mpm_ctx ctx, const float *g0, const float *g1, float 
     return MPM_OK;
 }
 
-// Tuning results kept for the life of the process, keyed by device, grid
-// resolutions and particle-count bucket.
+// Tuning results, keyed by device architecture, grid resolutions and
+// particle-count bucket: kept for the life of the process and in a text file
+// (one "key block chunk sort_every wg" line per tuning, the last one for a key
+// wins), so that a later process on the same kind of workload starts tuned.
 static std::map<std::string, std::vector<int>> g_tune_cache;
 
 static std::string tune_key(mpm_ctx ctx)
@@ -1409,6 +1422,8 @@ static std::string tune_key(mpm_ctx ctx)
     hipDeviceProp_t prop;
     std::string k = "dev";
     if (hipGetDeviceProperties(&prop, ctx->dev) == hipSuccess) k = prop.gcnArchName;
+    for (char &c : k)
+        if (c == ' ') c = '_';
     int resmask = 0;
     for (auto &S : ctx->h_scenes) resmask |= S.res;
     int bucket = 0;
@@ -1418,107 +1433,186 @@ static std::string tune_key(mpm_ctx ctx)
     return k + buf;
 }
 
+// The cache file: $MPM_AUTOTUNE_CACHE, else $XDG_CACHE_HOME/mpm_mi355x_autotune.txt,
+// else $HOME/.cache/mpm_mi355x_autotune.txt ("" when none can be named).
+static std::string tune_file()
+{
+    if (const char *f = std::getenv("MPM_AUTOTUNE_CACHE")) return f;
+    if (const char *x = std::getenv("XDG_CACHE_HOME")) return std::string(x) + "/mpm_mi355x_autotune.txt";
+    if (const char *h = std::getenv("HOME")) return std::string(h) + "/.cache/mpm_mi355x_autotune.txt";
+    return "";
+}
+
+static bool tune_file_lookup(const std::string &path, const std::string &key, std::vector<int> &best)
+{
+    if (path.empty()) return false;
+    std::FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return false;
+    char k[256];
+    int v[4];
+    bool found = false;
+    while (std::fscanf(f, "%255s %d %d %d %d", k, &v[0], &v[1], &v[2], &v[3]) == 5) {
+        if (key == k && (v[0] == 4 || v[0] == 8) && v[1] >= 64 && v[1] <= 8192 && v[2] >= 1 &&
+            (v[3] == 256 || v[3] == 512)) {
+            best.assign(v, v + 4);
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+static void tune_file_store(const std::string &path, const std::string &key, const std::vector<int> &best)
+{
+    if (path.empty()) return;
+    std::string dir = path.substr(0, path.find_last_of('/'));
+    if (!dir.empty() && dir != path) (void)mkdir(dir.c_str(), 0755);
+    if (std::FILE *f = std::fopen(path.c_str(), "a")) {
+        std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), best[0], best[1], best[2], best[3]);
+        std::fclose(f);
+    }
+}
+
+namespace {
+
+// Device and host resources of one tuning run, released on every return.
+struct TuneScratch {
+    float *snap = nullptr;
+    ColliderDev *csnap = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~TuneScratch()
+    {
+        if (snap) (void)hipFree(snap);
+        if (csnap) (void)hipFree(csnap);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
+}  // namespace
+
 mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_len)
 {
     ARGCHK(ctx, "null context");
     ARGCHK(substeps >= 1 && substeps <= 1000, "substeps must be in [1, 1000]");
     hipSetDevice(ctx->dev);
     if (report && report_len) report[0] = 0;
-    std::string key = tune_key(ctx);
+    const std::string key = tune_key(ctx), path = tune_file();
     std::string rep;
-    auto hit = g_tune_cache.find(key);
     std::vector<int> best;
+    auto hit = g_tune_cache.find(key);
     if (hit != g_tune_cache.end()) {
         best = hit->second;
-        rep = "{\"cached\": true";
+        rep = "{\"cached\": true, \"source\": \"process\"";
+    } else if (tune_file_lookup(path, key, best)) {
+        g_tune_cache[key] = best;
+        rep = "{\"cached\": true, \"source\": \"file\"";
     } else {
         // snapshot the particle state and the collider table
         const long long N = ctx->N;
-        float *snap = nullptr;
-        ColliderDev *csnap = nullptr;
-        HIPCHK(dalloc(&snap, (size_t)24 * std::max<long long>(N, 1)));
-        HIPCHK(dalloc(&csnap, ctx->h_cols.size()));
-        float *sx = snap, *sv = sx + 3 * N, *sC = sv + 3 * N, *sF = sC + 9 * N;
+        TuneScratch ts;
+        HIPCHK(dalloc(&ts.snap, (size_t)24 * std::max<long long>(N, 1)));
+        HIPCHK(dalloc(&ts.csnap, std::max<size_t>(ctx->h_cols.size(), 1)));
+        float *sx = ts.snap, *sv = sx + 3 * N, *sC = sv + 3 * N, *sF = sC + 9 * N;
         mpm_status st = mpm_get_state(ctx, -1, sx, sv, sC, sF, 1);
         if (st != MPM_OK) return st;
         if (!ctx->h_cols.empty())
-            HIPCHK(hipMemcpyAsync(csnap, ctx->d_cols, sizeof(ColliderDev) * ctx->h_cols.size(),
+            HIPCHK(hipMemcpyAsync(ts.csnap, ctx->d_cols, sizeof(ColliderDev) * ctx->h_cols.size(),
                                   hipMemcpyDeviceToDevice, ctx->stream));
         // the trials' collider impulses are not the caller's: keep the accumulated wrenches
         std::vector<float> wsnap(6 * std::max<size_t>(ctx->h_cols.size(), 1));
         HIPCHK(hipMemcpyAsync(wsnap.data(), ctx->d_wrench, sizeof(float) * wsnap.size(), hipMemcpyDeviceToHost,
                               ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
-        const int saved[3] = {ctx->B, ctx->CH, ctx->sort_every};
+        const int saved[4] = {ctx->B, ctx->CH, ctx->sort_every, ctx->nt};
         const int saved_timing = ctx->timing, saved_graph = ctx->graph;
         ctx->timing = 0;
         ctx->graph = 0;
-        hipEvent_t e0, e1;
-        HIPCHK(hipEventCreate(&e0));
-        HIPCHK(hipEventCreate(&e1));
-        const int Bs[2] = {4, 8}, CHs[3] = {512, 2048, 8192}, SEs[3] = {10, 25, 50};
+        HIPCHK(hipEventCreate(&ts.e0));
+        HIPCHK(hipEventCreate(&ts.e1));
         float best_ms = 1e30f;
         rep = "{\"cached\": false, \"trials\": [";
         bool first = true;
+        // one trial: ms per substep of (B, CH, SE, WG) on the snapshot, the sort included
+        auto trial = [&](int B, int CH, int SE, int NT, mpm_status &st2) -> float {
+            if (B != ctx->B && (st2 = set_block(ctx, B)) != MPM_OK) return -1.0f;
+            ctx->CH = CH;
+            ctx->sort_every = SE;
+            ctx->nt = NT;
+            if ((st2 = mpm_set_state(ctx, -1, sx, sv, sC, sF, 1)) != MPM_OK) return -1.0f;
+            if (!ctx->h_cols.empty() &&
+                hipMemcpyAsync(ctx->d_cols, ts.csnap, sizeof(ColliderDev) * ctx->h_cols.size(),
+                               hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess) {
+                st2 = MPM_ERR_HIP;
+                return -1.0f;
+            }
+            // the sort right after set_state is part of every trial; time enough substeps
+            // that later re-sorts are amortised as in use
+            const int n = std::max(substeps, SE);
+            float ms = 0.0f;
+            if (hipEventRecord(ts.e0, ctx->stream) != hipSuccess) { st2 = MPM_ERR_HIP; return -1.0f; }
+            if ((st2 = queue_plain(ctx, n)) != MPM_OK) return -1.0f;
+            if (hipEventRecord(ts.e1, ctx->stream) != hipSuccess || hipEventSynchronize(ts.e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, ts.e0, ts.e1) != hipSuccess) {
+                st2 = MPM_ERR_HIP;
+                return -1.0f;
+            }
+            const float per = ms / n;
+            char buf[192];
+            std::snprintf(buf, sizeof buf,
+                          "%s{\"block\": %d, \"chunk\": %d, \"sort_every\": %d, \"wg\": %d, \"ms_per_substep\": %.5f}",
+                          first ? "" : ", ", B, CH, SE, NT, per);
+            rep += buf;
+            first = false;
+            if (per < best_ms) {
+                best_ms = per;
+                best = {B, CH, SE, NT};
+            }
+            st2 = MPM_OK;
+            return per;
+        };
+        const int Bs[2] = {4, 8}, CHs[3] = {512, 2048, 8192}, SEs[3] = {10, 25, 50};
         for (int B : Bs)
             for (int CH : CHs)
                 for (int SE : SEs) {
-                    if (B != ctx->B && (st = set_block(ctx, B)) != MPM_OK) return st;
-                    ctx->CH = CH;
-                    ctx->sort_every = SE;
-                    if ((st = mpm_set_state(ctx, -1, sx, sv, sC, sF, 1)) != MPM_OK) return st;
-                    if (!ctx->h_cols.empty())
-                        HIPCHK(hipMemcpyAsync(ctx->d_cols, csnap, sizeof(ColliderDev) * ctx->h_cols.size(),
-                                              hipMemcpyDeviceToDevice, ctx->stream));
-                    // the sort right after set_state is part of every trial; time
-                    // enough substeps that later re-sorts are amortised as in use
-                    int n = std::max(substeps, SE);
-                    HIPCHK(hipEventRecord(e0, ctx->stream));
-                    if ((st = queue_plain(ctx, n)) != MPM_OK) return st;
-                    HIPCHK(hipEventRecord(e1, ctx->stream));
-                    HIPCHK(hipEventSynchronize(e1));
-                    float ms = 0.0f;
-                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                    float per = ms / n;
-                    char buf[160];
-                    std::snprintf(buf, sizeof buf, "%s{\"block\": %d, \"chunk\": %d, \"sort_every\": %d, \"ms_per_substep\": %.5f}",
-                                  first ? "" : ", ", B, CH, SE, per);
-                    rep += buf;
-                    first = false;
-                    if (per < best_ms) {
-                        best_ms = per;
-                        best = {B, CH, SE};
-                    }
+                    trial(B, CH, SE, 256, st);
+                    if (st != MPM_OK) return st;
                 }
+        // the workgroup size at the best (block, chunk, cadence)
+        {
+            const std::vector<int> b256 = best;
+            trial(b256[0], b256[1], b256[2], 512, st);
+            if (st != MPM_OK) return st;
+        }
         rep += "]";
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
         // restore the state the caller had
         if (ctx->B != saved[0] && (st = set_block(ctx, saved[0])) != MPM_OK) return st;
         ctx->CH = saved[1];
         ctx->sort_every = saved[2];
+        ctx->nt = saved[3];
         if ((st = mpm_set_state(ctx, -1, sx, sv, sC, sF, 1)) != MPM_OK) return st;
         if (!ctx->h_cols.empty())
-            HIPCHK(hipMemcpyAsync(ctx->d_cols, csnap, sizeof(ColliderDev) * ctx->h_cols.size(),
+            HIPCHK(hipMemcpyAsync(ctx->d_cols, ts.csnap, sizeof(ColliderDev) * ctx->h_cols.size(),
                                   hipMemcpyDeviceToDevice, ctx->stream));
         HIPCHK(hipMemcpyAsync(ctx->d_wrench, wsnap.data(), sizeof(float) * wsnap.size(), hipMemcpyHostToDevice,
                               ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
-        (void)hipFree(snap);
-        (void)hipFree(csnap);
         ctx->timing = saved_timing;
         ctx->graph = saved_graph;
         g_tune_cache[key] = best;
+        tune_file_store(path, key, best);
     }
     mpm_status st;
     if (best[0] != ctx->B && (st = set_block(ctx, best[0])) != MPM_OK) return st;
     ctx->CH = best[1];
     ctx->sort_every = best[2];
+    ctx->nt = best[3];
     ctx->since_sort = 1 << 30;
     clear_graphs(ctx);
-    char buf[160];
-    std::snprintf(buf, sizeof buf, ", \"best\": {\"block\": %d, \"chunk\": %d, \"sort_every\": %d}}", best[0],
-                  best[1], best[2]);
+    char buf[256];
+    std::snprintf(buf, sizeof buf,
+                  ", \"key\": \"%s\", \"best\": {\"block\": %d, \"chunk\": %d, \"sort_every\": %d, \"wg\": %d}}",
+                  key.c_str(), best[0], best[1], best[2], best[3]);
     rep += buf;
     if (report && report_len) {
         std::strncpy(report, rep.c_str(), report_len - 1);

@@ -422,7 +422,7 @@ template <int B> constexpr int p2g_cells() { return (B + 2) * (B + 2) * (B + 2);
 // before scattering (below it the per-term limit already sets the scale).
 constexpr int P2G_COUNT_MIN = 256;
 
-template <int B>
+template <int B, int NT = WG>
 __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile, int *cells)
 {
     constexpr int T = B + 4, T3 = T * T * T, NC = p2g_cells<B>();
@@ -443,9 +443,9 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile,
     // (an integer sum, so both halves are recovered exactly while they fit in
     // 32 bits)
     long long *t64 = (long long *)tile;
-    for (int n = t; n < 2 * T3; n += WG) t64[n] = 0;
+    for (int n = t; n < 2 * T3; n += NT) t64[n] = 0;
     if (count_cells) {
-        for (int n = t; n < NC + 1; n += WG) cells[n] = 0;   // cells[NC]: the maximum
+        for (int n = t; n < NC + 1; n += NT) cells[n] = 0;   // cells[NC]: the maximum
     }
     // bound of this item's particles, left by the previous G2P (or the sort)
     const float bmax = a.L.ibound[it];
@@ -461,7 +461,7 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile,
     // first (the same in-tile test as the scatter below).
     float wsum = 0.421875f * (float)item.count;
     if (count_cells) {
-        for (int base = 0; base < item.count; base += WG) {
+        for (int base = 0; base < item.count; base += NT) {
             const int li = base + t;
             if (li >= item.count) break;
             const unsigned jo = (unsigned)(item.start + li) << 2;
@@ -479,7 +479,7 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile,
         }
         __syncthreads();
         int mx = 0;
-        for (int n = t; n < NC; n += WG) mx = max(mx, cells[n]);
+        for (int n = t; n < NC; n += NT) mx = max(mx, cells[n]);
         mx = wave_max_i(mx);
         if ((t & 63) == 0) atomicMax(cells + NC, mx);
         __syncthreads();
@@ -501,7 +501,7 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile,
     const float kk = Sp / (Sm * K.mass);       // momentum scale relative to the mass-scaled weight
     const float msc = Sm * K.mass;
 
-    for (int base = 0; base < item.count; base += WG) {
+    for (int base = 0; base < item.count; base += NT) {
         const int li = base + t;
         if (li >= item.count) break;
         float x[3], v[3], A[9], f[3];
@@ -563,7 +563,7 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile,
     }
     __syncthreads();
     const float im = 1.0f / Sm, ip = 1.0f / Sp;
-    for (int n = t; n < T3; n += WG) {
+    for (int n = t; n < T3; n += NT) {
         int m0, p0, p1, p2;
         unpack2(t64[n], p0, m0);
         unpack2(t64[T3 + n], p1, p2);
@@ -584,8 +584,8 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile,
     __syncthreads();
 }
 
-template <int B>
-__global__ __launch_bounds__(WG) void k_p2g(StepArgs a)
+template <int B, int NT>
+__global__ __launch_bounds__(NT) void k_p2g(StepArgs a)
 {
     constexpr int T = B + 4, T3 = T * T * T;
     __shared__ __align__(16) int tile[4 * T3];
@@ -599,7 +599,7 @@ __global__ __launch_bounds__(WG) void k_p2g(StepArgs a)
         const int it = n_items - 1 - r;
         Item item = a.L.items[it];
         if (!a.active[item.scene]) continue;
-        p2g_item<B>(a, it, item, tile, cells);
+        p2g_item<B, NT>(a, it, item, tile, cells);
     }
 }
 
@@ -731,7 +731,7 @@ __global__ __launch_bounds__(WG, (B == 8 && !EXTRA) ? 7 : 1) void k_grid(StepArg
 // cells: LDS of p2g_cells<B>() + 1 ints; the item's particles are counted per
 // base cell of their new position (as the next P2G's tile sees them) and the
 // largest count is left in L.icell[it] for that P2G's fixed-point scale.
-template <int B, bool PF, bool PEN>
+template <int B, bool PF, bool PEN, int NT = WG>
 __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt, float *pf, int *cells)
 {
     constexpr int T = B + 4, T3 = T * T * T, NC = p2g_cells<B>();
@@ -748,14 +748,14 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
     // the compiler, which would reload them after each one)
     const Material mat = material_of(S);
     const SceneK K = scene_k(S);
-    for (int n = t; n < NC + 1; n += WG) cells[n] = 0;
+    for (int n = t; n < NC + 1; n += NT) cells[n] = 0;
     if (PF) {
         const int res = uniform_i(S.res);
         const SceneDev Sg = {0, 0, res, uniform_i(S.nb), uniform_ll(S.grid_off)};
         // the wave's first 64 particles: x and G copied into LDS while the tile is staged
         pf_issue(a.P, ps, item.start + (t - lane), item.count - (t - lane), lane, pw);
         // tile nodes copied straight into LDS, all in flight at once; nodes outside the grid are zeroed
-        for (int n0 = t - lane; n0 < T3; n0 += WG) {
+        for (int n0 = t - lane; n0 < T3; n0 += NT) {
             const int n = n0 + lane;
             if (n >= T3) break;
             int gi = org[0] + n / (T * T), gj = org[1] + (n / T) % T, gk = org[2] + n % T;
@@ -772,7 +772,7 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
         }
         wait_vmem();
     } else {
-        for (int n = t; n < T3; n += WG) {
+        for (int n = t; n < T3; n += NT) {
             int gi = org[0] + n / (T * T), gj = org[1] + (n / T) % T, gk = org[2] + n % T;
             float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
             if (gi >= 0 && gj >= 0 && gk >= 0 && gi < S.res && gj < S.res && gk < S.res) {
@@ -797,7 +797,7 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
     float pacc[PEN ? MAX_COLLIDERS_PER_SCENE : 1][6] = {};
     unsigned pen_hit = 0;
     // wave-uniform loop: lane li = k0 + lane of each 64-particle batch
-    for (int k0 = t - lane; k0 < item.count; k0 += WG) {
+    for (int k0 = t - lane; k0 < item.count; k0 += NT) {
         const int li = k0 + lane;
         const unsigned jo = (unsigned)(item.start + li) << 2;
         float x[3], G[9];
@@ -808,7 +808,7 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
             for (int e = 0; e < 9; e++) G[e] = pw[(3 + e) * 64 + lane];
             wait_lds();
             // the next batch streams into LDS while this one computes
-            pf_issue(a.P, ps, item.start + k0 + WG, item.count - (k0 + WG), lane, pw);
+            pf_issue(a.P, ps, item.start + k0 + NT, item.count - (k0 + NT), lane, pw);
         }
         if (li >= item.count) {
             if (PF) wait_vmem();
@@ -996,19 +996,19 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
     if (cl_any) atomicOr(a.flags + s, (int)FLAG_CLAMPED);
     __syncthreads();
     int mx = 0;
-    for (int n = t; n < NC; n += WG) mx = max(mx, cells[n]);
+    for (int n = t; n < NC; n += NT) mx = max(mx, cells[n]);
     mx = wave_max_i(mx);
     if ((t & 63) == 0) atomicMax(cells + NC, mx);
     __syncthreads();
     if (t == 0) a.L.icell[it] = cells[NC];
 }
 
-template <int B, bool PEN>
-__global__ __launch_bounds__(WG, 4) void k_g2p(StepArgs a)
+template <int B, bool PEN, int NT>
+__global__ __launch_bounds__(NT, 4) void k_g2p(StepArgs a)
 {
     constexpr int T = B + 4, T3 = T * T * T;
     __shared__ float vt[3 * T3];
-    __shared__ float pf[(WG / 64) * PF_COMPS * 64];
+    __shared__ float pf[(NT / 64) * PF_COMPS * 64];
     __shared__ int cells[p2g_cells<B>() + 1];
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(a.L.n_ovf, 0);   // grid update has consumed the list
     const int n_items = *a.L.n_items;
@@ -1017,16 +1017,22 @@ __global__ __launch_bounds__(WG, 4) void k_g2p(StepArgs a)
     for (int it = xcd_remap(blockIdx.x, G); it < n_items; it += G) {
         Item item = a.L.items[it];
         if (!a.active[item.scene]) continue;
-        g2p_item<B, true, PEN>(a, it, item, vt, pf, cells);
+        g2p_item<B, true, PEN, NT>(a, it, item, vt, pf, cells);
     }
 }
 
 hipError_t launch_p2g(const StepArgs &a, int chunk, int n_wg, hipStream_t st)
 {
     (void)chunk;
+    if (a.nt == 512) n_wg /= 2;   // the same threads in workgroups of twice the size
     n_wg = (n_wg + 7) & ~7;
-    if (a.B == 4) k_p2g<4><<<n_wg, WG, 0, st>>>(a);
-    else k_p2g<8><<<n_wg, WG, 0, st>>>(a);
+    if (a.nt == 512) {
+        if (a.B == 4) k_p2g<4, 512><<<n_wg, 512, 0, st>>>(a);
+        else k_p2g<8, 512><<<n_wg, 512, 0, st>>>(a);
+    } else {
+        if (a.B == 4) k_p2g<4, WG><<<n_wg, WG, 0, st>>>(a);
+        else k_p2g<8, WG><<<n_wg, WG, 0, st>>>(a);
+    }
     return hipGetLastError();
 }
 
@@ -1044,17 +1050,25 @@ hipError_t launch_grid(const StepArgs &a, int n_wg, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_g2p(const StepArgs &a, int n_wg, hipStream_t st)
+template <int NT>
+static void launch_g2p_nt(const StepArgs &a, int n_wg, hipStream_t st)
 {
-    n_wg = (n_wg + 7) & ~7;
     const bool pen = a.contact != 0;
     if (a.B == 4) {
-        if (pen) k_g2p<4, true><<<n_wg, WG, 0, st>>>(a);
-        else k_g2p<4, false><<<n_wg, WG, 0, st>>>(a);
+        if (pen) k_g2p<4, true, NT><<<n_wg, NT, 0, st>>>(a);
+        else k_g2p<4, false, NT><<<n_wg, NT, 0, st>>>(a);
     } else {
-        if (pen) k_g2p<8, true><<<n_wg, WG, 0, st>>>(a);
-        else k_g2p<8, false><<<n_wg, WG, 0, st>>>(a);
+        if (pen) k_g2p<8, true, NT><<<n_wg, NT, 0, st>>>(a);
+        else k_g2p<8, false, NT><<<n_wg, NT, 0, st>>>(a);
     }
+}
+
+hipError_t launch_g2p(const StepArgs &a, int n_wg, hipStream_t st)
+{
+    if (a.nt == 512) n_wg /= 2;   // the same threads in workgroups of twice the size
+    n_wg = (n_wg + 7) & ~7;
+    if (a.nt == 512) launch_g2p_nt<512>(a, n_wg, st);
+    else launch_g2p_nt<WG>(a, n_wg, st);
     return hipGetLastError();
 }
 

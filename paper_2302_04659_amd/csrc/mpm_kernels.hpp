@@ -36,6 +36,7 @@ struct StepArgs {
     int contact;              // 0 grid-node projection, 1 particle penalty (in G2P), 2 both
     float *wrench;            // per collider (global index): [6] impulse and angular impulse about its centre
                               //   received from the material, summed over grid updates (or null)
+    int nt;                   // threads per workgroup of P2G and G2P: 256 or 512
 };
 
 

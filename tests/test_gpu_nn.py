@@ -6,8 +6,15 @@ Bars:
     BF16, FP64 accumulation): |gpu - ref| <= 1e-5 * sum |terms| per output
     element for FP32 outputs (the FP32-accumulation bound), one BF16 ulp
     for BF16 outputs; bit-exact for ReLU masking and exact resampling sums;
-  * whole network against the unquantised FP64 oracle: relative L2 error
-    <= 2e-2 for the forward output and <= 5e-2 for every parameter gradient.
+  * whole network: the forward output within relative L2 2e-2 of the
+    unquantised FP64 oracle; every parameter gradient (a) within half of the
+    BF16-storage oracle's own distance from the exact gradient, plus 2e-3,
+    of that BF16-storage oracle (the same rounding points as the kernels:
+    activations, stored gradients and weights rounded to BF16), and (b)
+    within 1.5 times that distance, plus 5e-3, of the exact FP64 gradient.
+    A fixed 5e-2 bar against the exact gradient cannot hold: BF16 storage
+    of the backward signal alone puts the deepest layers' exact-vs-BF16
+    distance near 1e-1 (printed per parameter by the test).
 Shapes are chosen so that voxel counts leave ragged waves and workgroups.
 """
 import numpy as np

@@ -92,19 +92,21 @@ def _c18_check(sim, orc, batch, states, what):
 
 
 @pytest.mark.parametrize("which", ["cfg2", "cfg3x16"])
-@pytest.mark.parametrize("block,chunk", [(4, 512), (4, 2048), (4, 8192), (8, 512), (8, 2048), (8, 8192)])
-def test_grid_momentum_every_launch_config(mpm, orc, which, block, chunk):
+@pytest.mark.parametrize("block,chunk,wg", [(4, 512, 256), (4, 2048, 256), (4, 8192, 256), (8, 512, 256),
+                                            (8, 2048, 256), (8, 8192, 256), (4, 2048, 512), (8, 8192, 512)])
+def test_grid_momentum_every_launch_config(mpm, orc, which, block, chunk, wg):
     """The per-substep grid-momentum bar at every block edge and chunk size
-    the autotuner can pick (the fixed-point scale of P2G depends on the
+    the autotuner can pick, with both workgroup sizes (the fixed-point scale of P2G depends on the
     work item's particle count): the first P2G after a re-sort, from a
     handed-in state (seeded C, F; scale bound from the sort), and the P2G of
     the next substep (scale bound from the G2P that wrote the state, which is
     read back for the oracle)."""
     batch = _c18_batch(which)
-    announce("grid momentum", which, "B", block, "chunk", chunk, "n", sum(sc.n for sc in batch))
+    announce("grid momentum", which, "B", block, "chunk", chunk, "wg", wg, "n", sum(sc.n for sc in batch))
     sim = mpm.Sim(batch)
     sim.set_option(mpm.OPT_BLOCK, block)
     sim.set_option(mpm.OPT_CHUNK, chunk)
+    sim.set_option(mpm.OPT_WG, wg)
     sim.set_option(mpm.OPT_CAPTURE_GRID, 1)
     states = []
     for s, sc in enumerate(batch):
@@ -335,7 +337,16 @@ def test_graph_replays_match_eager(mpm, orc):
     graph.close()
 
 
-def test_autotune_keeps_state(mpm):
+def test_autotune_keeps_state(mpm, tmp_path, monkeypatch):
+    """The autotuner's trials (block edge x chunk x sort cadence, then the
+    workgroup size) leave the particle state as it was; the tuning is cached
+    for the process and in a file, so that a second process on the same
+    kind of workload gets it without trials."""
+    import json
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("MPM_AUTOTUNE_CACHE", str(cache))
     batch = [scenes.small_scene(60 + s, n=3000, res=32, n_ctrl=2, dt=1e-4) for s in range(4)]
     announce("autotune", len(batch))
     sim = mpm.Sim(batch)
@@ -344,15 +355,46 @@ def test_autotune_keeps_state(mpm):
     before = sim.get_state(-1)
     rep = sim.autotune(5)
     print(rep)
-    import json
     r = json.loads(rep)
-    assert r["best"]["block"] in (4, 8) and r["best"]["chunk"] in (512, 2048, 8192)
+    assert not r["cached"]
+    assert {t["wg"] for t in r["trials"]} == {256, 512}
+    assert r["best"]["block"] in (4, 8) and r["best"]["chunk"] in (512, 2048, 8192) and r["best"]["wg"] in (256, 512)
     after = sim.get_state(-1)
     for a, b in zip(before, after):
         assert np.abs(a - b).max() <= 1e-6 * max(1.0, np.abs(a).max())
     assert sim.get_option(mpm.OPT_BLOCK) == r["best"]["block"]
+    assert sim.get_option(mpm.OPT_WG) == r["best"]["wg"]
     rep2 = json.loads(sim.autotune(5))
     assert rep2["cached"] and rep2["best"] == r["best"]
     sim.step(10)
     assert sim.sync() == mpm.OK
     sim.close()
+    assert cache.exists()
+    code = ("import json, sys; sys.path.insert(0, %r); from paper_2302_04659_amd import mpm, scenes; "
+            "b = [scenes.small_scene(60 + s, n=3000, res=32, n_ctrl=2, dt=1e-4) for s in range(4)]; "
+            "sim = mpm.Sim(b); print(sim.autotune(5)); sim.close()" % (str(__import__("pathlib").Path(__file__).parents[1]),))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    r3 = json.loads(out.stdout.strip().splitlines()[-1])
+    print(r3)
+    assert r3["cached"] and r3["source"] == "file" and r3["best"] == r["best"]
+
+
+def test_workgroup_sizes_match_oracle(mpm, orc):
+    """Both workgroup sizes of the particle kernels (256 and 512 threads) on
+    uneven items, against the oracle after two control steps."""
+    batch = [scenes.small_scene(80 + s, n=700 * (1 + s), res=32, model=s % 2, n_ctrl=2, dt=1e-4) for s in range(3)]
+    for nt in (256, 512):
+        announce("workgroup size", nt)
+        sim = mpm.Sim(batch)
+        sim.set_option(mpm.OPT_WG, nt)
+        sim.set_option(mpm.OPT_BLOCK, 8)
+        sim.set_option(mpm.OPT_CHUNK, 512)
+        sim.run_schedule(2)
+        assert sim.sync() == mpm.OK
+        for s, sc in enumerate(batch):
+            o = orc.Oracle(sc)
+            o.run_schedule(2)
+            x, *_ = sim.get_state(s)
+            assert np.abs(x - o.x).max() <= 1e-3 * sc.dx, (nt, s)
+        sim.close()
