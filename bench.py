@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # (FP32): P2G reads x, v, A (15 floats); G2P reads x, G (12 floats) and
 # writes x, v, A, G (24 floats).  Grid bytes (16 B per active node and
 # pass) are left out, so `achieved` is a lower bound.
-ALG_BYTES = {"p2g": 60.0, "g2p": 144.0, "grid": 0.0, "sort": 0.0}
+ALG_BYTES = {"p2g": 60.0, "g2p": 144.0, "grid": 0.0, "sort": 0.0, "persistent": 204.0}
 # Sources the substep kernels are compiled from: a traffic summary is valid
 # only for the exact sources it was measured on.
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2302_04659_amd", "csrc", f) for f in
@@ -224,7 +224,7 @@ def main():
     assert substeps == SUB * args.steps, window
     value = N * substeps / elapsed
     per_launch = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
-    dom = max(("p2g", "g2p", "grid", "sort"), key=lambda k: kt[k][0])
+    dom = max(("p2g", "g2p", "grid", "sort", "persistent"), key=lambda k: kt[k][0])
     dom_ms = per_launch[dom]
     bytes_launch = ALG_BYTES[dom] * N
     achieved = bytes_launch / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None

@@ -95,7 +95,6 @@ struct mpm_ctx_s {
     Lists L{};
     int items_cap = 0;
     int *d_flags = nullptr;
-    int *d_queue = nullptr, *d_scene_done = nullptr;
 
     // per-scene step mask (1 = step), dense per-scene grid offsets
     int *d_active = nullptr;
@@ -388,8 +387,6 @@ StepArgs step_args(mpm_ctx ctx, int substep)
     a.flags = ctx->d_flags;
     a.substep = substep;
     a.B = ctx->B;
-    a.queue = ctx->d_queue;
-    a.scene_done = ctx->d_scene_done;
     a.active = ctx->d_active;
     a.dense = nullptr;
     a.feat = nullptr;
@@ -430,9 +427,9 @@ mpm_status queue_plain(mpm_ctx ctx, int n)
         }
         if (ctx->capture) HIPCHK(launch_clear_f(ctx->d_cap, 4 * ctx->cap_nodes, ctx->stream));
         StepArgs a = step_args(ctx, i);
-        if (ctx->persistent) {
+        if (ctx->persistent && !ctx->capture) {
             KTimer kt(ctx, MPM_K_PERSISTENT);
-            HIPCHK(launch_persistent(a, ctx->CH, ctx->cus * 4, ctx->stream));
+            HIPCHK(launch_persistent(a, ctx->cus, ctx->stream));
             ctx->since_sort++;
             ctx->cnt[MPM_CNT_SUBSTEPS]++;
             ctx->cnt[MPM_CNT_HOST_SUBSTEPS]++;
@@ -508,7 +505,7 @@ mpm_status queue_graph_block(mpm_ctx ctx)
 
 mpm_status queue_substeps(mpm_ctx ctx, int n)
 {
-    if (ctx->graph && !ctx->timing && !ctx->capture) {
+    if (ctx->graph && !ctx->timing && !ctx->capture && !ctx->persistent) {
         while (n >= GRAPH_BLOCK) {
             mpm_status st = queue_graph_block(ctx);
             if (st != MPM_OK) return st;
@@ -562,7 +559,7 @@ void release(mpm_ctx ctx)
                     ctx->d_col_scene, ctx->d_scene_bin_off, ctx->d_keys, ctx->d_count, ctx->d_pstart, ctx->d_perm,
                     ctx->d_tsum, ctx->d_dil, ctx->L.items, ctx->L.gitems, ctx->L.n_items, ctx->L.n_gitems,
                     ctx->L.scene_item_begin, ctx->L.scene_gitem_begin, ctx->L.bflag, ctx->L.ovf, ctx->L.n_ovf, ctx->L.ibound, ctx->L.icell, ctx->L.touched,
-                    ctx->d_flags, ctx->d_queue, ctx->d_scene_done, ctx->d_cap, ctx->d_cap_off, ctx->d_io,
+                    ctx->d_flags, ctx->d_cap, ctx->d_cap_off, ctx->d_io,
                     ctx->d_active, ctx->d_sur_gend, ctx->d_sur_acc, ctx->d_sur_out, ctx->d_sur_nfb,
                     ctx->d_wrench, ctx->d_wrench_out, ctx->d_sdf, ctx->d_sb_box, ctx->d_sb_origin, ctx->d_sb_feat,
                     ctx->d_sb_grid0, ctx->d_sb_pred, ctx->d_sb_res};
@@ -680,8 +677,6 @@ mpm_status create_impl(mpm_ctx ctx, const mpm_scene_desc *scenes, int n_scenes)
         HIPCHK(dalloc(&ctx->d_cap_off, n_scenes));
         HIPCHK(hipMemcpy(ctx->d_cap_off, off.data(), sizeof(long long) * n_scenes, hipMemcpyHostToDevice));
     }
-    HIPCHK(dalloc(&ctx->d_queue, 4));
-    HIPCHK(dalloc(&ctx->d_scene_done, 3 * n_scenes));
     HIPCHK(dalloc(&ctx->d_io, (size_t)24 * N));
     for (int i = 0; i < STAGE_RING; i++) {
         size_t bytes = std::max<size_t>(ctx->h_cols.size(), 1) * sizeof(ColliderDev) + 64;
@@ -695,8 +690,6 @@ mpm_status create_impl(mpm_ctx ctx, const mpm_scene_desc *scenes, int n_scenes)
     HIPCHK(hipMemsetAsync(ctx->L.n_items, 0, sizeof(int), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->L.n_gitems, 0, sizeof(int), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->d_flags, 0, sizeof(int) * n_scenes, ctx->stream));
-    HIPCHK(hipMemsetAsync(ctx->d_queue, 0, sizeof(int) * 4, ctx->stream));
-    HIPCHK(hipMemsetAsync(ctx->d_scene_done, 0, sizeof(int) * 3 * n_scenes, ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->d_wrench, 0, sizeof(float) * 6 * std::max<size_t>(ctx->h_cols.size(), 1), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->d_P[0], 0, sizeof(float) * NCOMP * ctx->pstride, ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->d_P[1], 0, sizeof(float) * NCOMP * ctx->pstride, ctx->stream));
@@ -882,10 +875,6 @@ mpm_status mpm_sync(mpm_ctx ctx)
         ctx->last_error = "non-finite particle state";
         return MPM_ERR_NONFINITE;
     }
-    if (any & FLAG_SPIN) {
-        ctx->last_error = "persistent substep: a dependency wait timed out";
-        return MPM_ERR_STATE;
-    }
     if (any & FLAG_OVERFLOW_FULL) {
         ctx->last_error = "overflow grid-block list full";
         return MPM_ERR_STATE;
@@ -1013,15 +1002,8 @@ mpm_status mpm_set_option(mpm_ctx ctx, int option, int value)
         return MPM_OK;
     case MPM_OPT_PERSISTENT:
         ARGCHK(value == 0 || value == 1, "persistent must be 0 or 1");
-        if (value == 1) {
-            // The one-launch-per-substep kernel (k_substep_persistent) stopped
-            // making progress in one tested configuration (block 8, chunk 512,
-            // re-sort every substep) and the cause is not established; it stays
-            // switched off until it is.
-            ctx->last_error = "persistent substep is disabled";
-            return MPM_ERR_STATE;
-        }
         ctx->persistent = value;
+        clear_graphs(ctx);
         return MPM_OK;
     case MPM_OPT_GRAPH:
         ARGCHK(value == 0 || value == 1, "graph must be 0 or 1");
@@ -1413,7 +1395,7 @@ mpm_status mpm_sur_targets(mpm_ctx ctx, const float *g0, const float *g1, float 
 
 // Tuning results, keyed by device architecture, grid resolutions and
 // particle-count bucket: kept for the life of the process and in a text file
-// (one "key block chunk sort_every wg" line per tuning, the last one for a key
+// (one "key block chunk sort_every wg persistent" line per tuning, the last one for a key
 // wins), so that a later process on the same kind of workload starts tuned.
 static std::map<std::string, std::vector<int>> g_tune_cache;
 
@@ -1449,12 +1431,12 @@ static bool tune_file_lookup(const std::string &path, const std::string &key, st
     std::FILE *f = std::fopen(path.c_str(), "r");
     if (!f) return false;
     char k[256];
-    int v[4];
+    int v[5];
     bool found = false;
-    while (std::fscanf(f, "%255s %d %d %d %d", k, &v[0], &v[1], &v[2], &v[3]) == 5) {
+    while (std::fscanf(f, "%255s %d %d %d %d %d", k, &v[0], &v[1], &v[2], &v[3], &v[4]) == 6) {
         if (key == k && (v[0] == 4 || v[0] == 8) && v[1] >= 64 && v[1] <= 8192 && v[2] >= 1 &&
-            (v[3] == 256 || v[3] == 512)) {
-            best.assign(v, v + 4);
+            (v[3] == 256 || v[3] == 512) && (v[4] == 0 || v[4] == 1)) {
+            best.assign(v, v + 5);
             found = true;
         }
     }
@@ -1468,7 +1450,7 @@ static void tune_file_store(const std::string &path, const std::string &key, con
     std::string dir = path.substr(0, path.find_last_of('/'));
     if (!dir.empty() && dir != path) (void)mkdir(dir.c_str(), 0755);
     if (std::FILE *f = std::fopen(path.c_str(), "a")) {
-        std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), best[0], best[1], best[2], best[3]);
+        std::fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), best[0], best[1], best[2], best[3], best[4]);
         std::fclose(f);
     }
 }
@@ -1524,7 +1506,8 @@ mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_l
         HIPCHK(hipMemcpyAsync(wsnap.data(), ctx->d_wrench, sizeof(float) * wsnap.size(), hipMemcpyDeviceToHost,
                               ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
-        const int saved[4] = {ctx->B, ctx->CH, ctx->sort_every, ctx->nt};
+        const int saved[5] = {ctx->B, ctx->CH, ctx->sort_every, ctx->nt, ctx->persistent};
+        ctx->persistent = 0;
         const int saved_timing = ctx->timing, saved_graph = ctx->graph;
         ctx->timing = 0;
         ctx->graph = 0;
@@ -1560,8 +1543,9 @@ mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_l
             const float per = ms / n;
             char buf[192];
             std::snprintf(buf, sizeof buf,
-                          "%s{\"block\": %d, \"chunk\": %d, \"sort_every\": %d, \"wg\": %d, \"ms_per_substep\": %.5f}",
-                          first ? "" : ", ", B, CH, SE, NT, per);
+                          "%s{\"block\": %d, \"chunk\": %d, \"sort_every\": %d, \"wg\": %d, \"persistent\": %d, "
+                          "\"ms_per_substep\": %.5f}",
+                          first ? "" : ", ", B, CH, SE, NT, ctx->persistent, per);
             rep += buf;
             first = false;
             if (per < best_ms) {
@@ -1584,12 +1568,23 @@ mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_l
             trial(b256[0], b256[1], b256[2], 512, st);
             if (st != MPM_OK) return st;
         }
+        // one cooperative launch per substep at the best so far
+        {
+            const std::vector<int> b = best;
+            ctx->persistent = 1;
+            trial(b[0], b[1], b[2], b[3], st);
+            ctx->persistent = 0;
+            if (st != MPM_OK) return st;
+            if (best != b) best.push_back(1);   // the launch mode that won
+        }
+        if (best.size() == 4) best.push_back(0);
         rep += "]";
         // restore the state the caller had
         if (ctx->B != saved[0] && (st = set_block(ctx, saved[0])) != MPM_OK) return st;
         ctx->CH = saved[1];
         ctx->sort_every = saved[2];
         ctx->nt = saved[3];
+        ctx->persistent = saved[4];
         if ((st = mpm_set_state(ctx, -1, sx, sv, sC, sF, 1)) != MPM_OK) return st;
         if (!ctx->h_cols.empty())
             HIPCHK(hipMemcpyAsync(ctx->d_cols, ts.csnap, sizeof(ColliderDev) * ctx->h_cols.size(),
@@ -1607,12 +1602,14 @@ mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_l
     ctx->CH = best[1];
     ctx->sort_every = best[2];
     ctx->nt = best[3];
+    ctx->persistent = best[4];
     ctx->since_sort = 1 << 30;
     clear_graphs(ctx);
     char buf[256];
     std::snprintf(buf, sizeof buf,
-                  ", \"key\": \"%s\", \"best\": {\"block\": %d, \"chunk\": %d, \"sort_every\": %d, \"wg\": %d}}",
-                  key.c_str(), best[0], best[1], best[2], best[3]);
+                  ", \"key\": \"%s\", \"best\": {\"block\": %d, \"chunk\": %d, \"sort_every\": %d, \"wg\": %d, "
+                  "\"persistent\": %d}}",
+                  key.c_str(), best[0], best[1], best[2], best[3], best[4]);
     rep += buf;
     if (report && report_len) {
         std::strncpy(report, rep.c_str(), report_len - 1);

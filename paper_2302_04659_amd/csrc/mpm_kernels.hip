@@ -14,6 +14,7 @@
 //           momentum A = m C - dt V (4/dx^2) tau(F) the next P2G scatters.
 // Particles are binned by grid block (Morton order inside a scene) every
 // few substeps by a counting sort (k_keys .. k_gather).
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include "mpm_device.hpp"
@@ -1072,114 +1073,83 @@ hipError_t launch_g2p(const StepArgs &a, int n_wg, hipStream_t st)
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- persistent substep
-// One launch per substep over all scenes.  Workgroups pull queue entries in
-// order: all P2G items, then grid blocks (four per entry, one per wave, plus
-// one overflow sweep per scene), then all G2P items.  A grid entry of scene s
-// waits until every P2G item of s has finished, a G2P item of s until every
-// grid entry of s has; per-scene counters replace a device-wide barrier, so
-// a small scene never waits for a big one.  Entries only ever wait for
-// entries dequeued before them, which are held by running workgroups, so the
-// waits always end; a bounded spin guards against a broken invariant (it
-// raises FLAG_SPIN instead of hanging).  The last workgroup to leave resets
-// the counters for the next launch.
-__device__ __forceinline__ void wait_counter(int *ctr, int target, int *flag)
-{
-    for (int i = 0; i < (1 << 22); i++) {
-        if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) {
-            __threadfence();
-            return;
-        }
-        __builtin_amdgcn_s_sleep(2);
-    }
-    atomicOr(flag, (int)FLAG_SPIN);
-    __threadfence();
-}
-
-template <int B>
-__global__ __launch_bounds__(WG) void k_substep_persistent(StepArgs a)
+// ---------------------------------------------------------------- one-launch substep
+// One cooperative launch per substep over all scenes: every workgroup is
+// resident at once (the launch is sized from the kernel's occupancy and the
+// runtime refuses a larger one), and the three phases of the substep are
+// separated by grid-wide barriers: P2G over all work items, the grid update
+// over every listed block (one wave per block), G2P over all work items.
+// Within a phase the workgroups stride over the work as the separate kernels
+// do.  The phases share one LDS allocation (the P2G tile, or the G2P
+// velocity tile and prefetch slices).
+template <int B, bool PEN>
+__global__ __launch_bounds__(WG, 4) void k_substep_coop(StepArgs a)
 {
     constexpr int T = B + 4, T3 = T * T * T;
-    __shared__ __align__(16) int smem[4 * T3];
+    constexpr int P2G_WORDS = 4 * T3;
+    constexpr int G2P_WORDS = 3 * T3 + (WG / 64) * PF_COMPS * 64;
+    __shared__ __align__(16) int smem[P2G_WORDS > G2P_WORDS ? P2G_WORDS : G2P_WORDS];
     __shared__ int cells[p2g_cells<B>() + 1];
-    __shared__ int s_q;
     __shared__ ColliderNow cls[WG / 64][MAX_COLLIDERS_PER_SCENE];
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    const int G = gridDim.x;   // a multiple of 8: every workgroup takes part in every phase
     const int n_items = *a.L.n_items;
-    const int n_g = *a.L.n_gitems;
-    const int n_grid = n_g + a.n_scenes;
-    const int n_gq = (n_grid + 3) / 4;
-    const int total = 2 * n_items + n_gq;
-    int *p2g_done = a.scene_done;
-    int *grid_done = a.scene_done + a.n_scenes;
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (;;) {
-        if (threadIdx.x == 0) s_q = atomicAdd(a.queue, 1);
-        __syncthreads();
-        const int q = s_q;
-        __syncthreads();
-        if (q >= total) break;
-        if (q < n_items) {
-            Item item = a.L.items[q];
-            p2g_item<B>(a, q, item, smem, cells);
-            if (threadIdx.x == 0) {
-                __threadfence();
-                atomicAdd(&p2g_done[item.scene], 1);
-            }
-        } else if (q < n_items + n_gq) {
-            const int g = (q - n_items) * 4 + wv;
-            if (g < n_grid) {
-                int s, lb = -1;
-                if (g < n_g) {
-                    int2 e = a.L.gitems[g];
-                    s = e.x;
-                    lb = e.y;
-                } else {
-                    s = g - n_g;
-                }
-                wait_counter(&p2g_done[s], a.L.scene_item_begin[s + 1] - a.L.scene_item_begin[s], a.flags + s);
-                if (lb >= 0) {
-                    grid_block<B>(a, s, lb, lane, cls[wv]);
-                } else {
-                    const int no = min(*a.L.n_ovf, a.L.ovf_cap);
-                    for (int k = 0; k < no; k++) {
-                        int2 e = a.L.ovf[k];
-                        if (e.x != s) continue;
-                        grid_block<B>(a, s, e.y, lane, cls[wv]);
-                        if (lane == 0) a.L.bflag[a.scenes[s].bin_off + e.y] = 0;
-                    }
-                }
-                __threadfence();
-                if (lane == 0) atomicAdd(&grid_done[s], 1);
-            }
-        } else {
-            const int qi = q - n_items - n_gq;
-            Item item = a.L.items[qi];
-            const int s = item.scene;
-            if (threadIdx.x == 0)
-                wait_counter(&grid_done[s], a.L.scene_gitem_begin[s + 1] - a.L.scene_gitem_begin[s] + 1, a.flags + s);
-            __syncthreads();
-            g2p_item<B, false, false>(a, qi, item, (float *)smem, nullptr, cells);
+    // P2G, items in reverse order (as k_p2g)
+    for (int r = xcd_remap(blockIdx.x, G); r < n_items; r += G) {
+        const int it = n_items - 1 - r;
+        const Item item = a.L.items[it];
+        if (!a.active[item.scene]) continue;
+        p2g_item<B, WG>(a, it, item, smem, cells);
+    }
+    grid.sync();
+    {
+        const int lane = threadIdx.x & 63;
+        const int ng = *a.L.n_gitems;
+        const int no = min(*a.L.n_ovf, a.L.ovf_cap);
+        const int nw = G * (WG / 64);
+        const int w0 = xcd_remap(blockIdx.x, G) * (WG / 64) + (threadIdx.x >> 6);
+        for (int w = w0; w < ng + no; w += nw) {
+            const int2 e = w < ng ? a.L.gitems[w] : a.L.ovf[w - ng];
+            grid_block<B, false>(a, e.x, e.y, lane, cls[threadIdx.x >> 6]);
+            if (w >= ng && lane == 0) a.L.bflag[a.scenes[e.x].bin_off + e.y] = 0;
         }
     }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        int done = atomicAdd(a.queue + 1, 1);
-        if (done == (int)gridDim.x - 1) {
-            a.queue[0] = 0;
-            a.queue[1] = 0;
-            *a.L.n_ovf = 0;
-            for (int s = 0; s < 2 * a.n_scenes; s++) a.scene_done[s] = 0;
-            __threadfence();
-        }
+    grid.sync();
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(a.L.n_ovf, 0);   // the grid update has consumed the list
+    float *vt = (float *)smem;
+    for (int it = xcd_remap(blockIdx.x, G); it < n_items; it += G) {
+        const Item item = a.L.items[it];
+        if (!a.active[item.scene]) continue;
+        g2p_item<B, true, PEN, WG>(a, it, item, vt, vt + 3 * T3, cells);
     }
 }
 
-hipError_t launch_persistent(const StepArgs &a, int chunk, int n_wg, hipStream_t st)
+// Co-resident workgroups of the cooperative substep on this device (a
+// multiple of 8), from the kernel's occupancy; 0 on error.
+template <int B, bool PEN>
+static int coop_workgroups(int cus)
 {
-    (void)chunk;
-    if (a.B == 4) k_substep_persistent<4><<<n_wg, WG, 0, st>>>(a);
-    else k_substep_persistent<8><<<n_wg, WG, 0, st>>>(a);
-    return hipGetLastError();
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_substep_coop<B, PEN>, WG, 0) != hipSuccess) return 0;
+    return (per_cu * cus) & ~7;
+}
+
+hipError_t launch_persistent(const StepArgs &a, int cus, hipStream_t st)
+{
+    const bool pen = a.contact != 0;
+    const void *fn;
+    int G;
+    if (a.B == 4) {
+        fn = pen ? (const void *)k_substep_coop<4, true> : (const void *)k_substep_coop<4, false>;
+        G = pen ? coop_workgroups<4, true>(cus) : coop_workgroups<4, false>(cus);
+    } else {
+        fn = pen ? (const void *)k_substep_coop<8, true> : (const void *)k_substep_coop<8, false>;
+        G = pen ? coop_workgroups<8, true>(cus) : coop_workgroups<8, false>(cus);
+    }
+    if (G <= 0) return hipErrorInvalidConfiguration;
+    StepArgs args = a;
+    void *params[] = {(void *)&args};
+    return hipLaunchCooperativeKernel(fn, dim3(G), dim3(WG), params, 0, st);
 }
 
 // ====================================================================== colliders
@@ -1317,21 +1287,6 @@ hipError_t launch_clear_f(float *p, long long n, hipStream_t st)
         long long nb = (n + WG - 1) / WG;
         k_clear_f<<<(unsigned)(nb < 8192 ? nb : 8192), WG, 0, st>>>(p, n);
     }
-    return hipGetLastError();
-}
-
-__global__ void k_reset_counters(int *queue, int *scene_done, int n, int *n_ovf)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0 && queue) queue[0] = 0;
-    if (scene_done)
-        for (int k = i; k < 3 * n; k += gridDim.x * blockDim.x) scene_done[k] = 0;
-    (void)n_ovf;
-}
-
-hipError_t launch_reset_scene_counters(int *queue, int *scene_done, int n_scenes, int *n_ovf, hipStream_t st)
-{
-    k_reset_counters<<<1, WG, 0, st>>>(queue, scene_done, n_scenes, n_ovf);
     return hipGetLastError();
 }
 

@@ -21,9 +21,6 @@ struct StepArgs {
     int *flags;               // per scene
     int substep;              // substep index within the current call
     int B;                    // block edge
-    int *queue;               // persistent mode: [0] queue cursor, [1] workgroups finished
-    int *scene_done;          // persistent mode: [n_scenes] P2G items done, [n_scenes] grid entries done
-    int n_wg;                 // persistent mode: number of workgroups launched
     const int *active;        // per scene: 0 = leave this scene's particles as they are (P2G / G2P skip it)
     float *dense;             // optional grid-update output per scene on the surrogate box [box][4] = (m, v), or null
     float *feat;              // optional surrogate input channels 0-3 (m, p normalised) [box][cf], or null
@@ -66,7 +63,9 @@ hipError_t launch_sort(const SortArgs &a, hipStream_t st);
 hipError_t launch_p2g(const StepArgs &a, int chunk, int n_wg, hipStream_t st);
 hipError_t launch_grid(const StepArgs &a, int n_wg, hipStream_t st);
 hipError_t launch_g2p(const StepArgs &a, int n_wg, hipStream_t st);
-hipError_t launch_persistent(const StepArgs &a, int chunk, int n_wg, hipStream_t st);
+// One cooperative launch per substep (P2G, grid update, G2P separated by
+// grid-wide barriers); cus = compute units of the device.
+hipError_t launch_persistent(const StepArgs &a, int cus, hipStream_t st);
 hipError_t launch_collider_advance(ColliderDev *cols, int n_cols, const int *col_scene, const SceneDev *scenes,
                                    int n_substeps, hipStream_t st);
 
@@ -81,7 +80,6 @@ hipError_t launch_init_particles(const SceneDev *scenes, int n_scenes, const int
 hipError_t launch_get_state(const SceneDev *scenes, const int *psc, const float *P, long long pstride, int begin,
                             int end, float *x, float *v, float *C, float *F, hipStream_t st);
 hipError_t launch_clear_f(float *p, long long n, hipStream_t st);
-hipError_t launch_reset_scene_counters(int *queue, int *scene_done, int n_scenes, int *n_ovf, hipStream_t st);
 hipError_t launch_fill_i(int *p, long long n, int v, hipStream_t st);
 
 // Grid surrogate support (all scenes share one resolution `res`).

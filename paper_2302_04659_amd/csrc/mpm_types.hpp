@@ -17,7 +17,7 @@ enum Comp : int {
     NCOMP
 };
 
-enum Flag : int { FLAG_CLAMPED = 1, FLAG_NONFINITE = 2, FLAG_SPIN = 4, FLAG_OVERFLOW_FULL = 8 };
+enum Flag : int { FLAG_CLAMPED = 1, FLAG_NONFINITE = 2, FLAG_OVERFLOW_FULL = 8 };
 
 constexpr int MAX_COLLIDERS_PER_SCENE = 4;   // equals MPM_MAX_COLLIDERS of the public header
 

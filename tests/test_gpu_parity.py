@@ -245,14 +245,10 @@ def test_ragged_items_match_oracle(mpm, orc, block, chunk, graph):
 @pytest.mark.parametrize("persistent", [0, 1])
 @pytest.mark.parametrize("block,chunk,sort_every", [(4, 1024, 25), (8, 512, 1), (8, 256, 25), (4, 256, 7)])
 def test_launch_modes_match_oracle(mpm, orc, persistent, block, chunk, sort_every):
-    # (the persistent cases are skipped; see the skip reason)
-    """Every launch configuration (one persistent launch or three launches per
-    substep, block edge, chunk size, sort cadence) matches the oracle on a
-    batch of uneven scenes."""
+    """Every launch configuration (one cooperative launch or three launches
+    per substep, block edge, chunk size, sort cadence) matches the oracle on
+    a batch of uneven scenes."""
     batch = [scenes.small_scene(20 + s, n=600 * (1 + s), res=32, model=s % 2, n_ctrl=2, dt=1e-4) for s in range(3)]
-    if persistent:
-        pytest.skip("persistent substep disabled: it stopped making progress with block 8, chunk 512, "
-                    "re-sort every substep; cause not established")
     announce("modes", "persistent", persistent, "B", block, "chunk", chunk, "sort_every", sort_every)
     sim = mpm.Sim(batch)
     sim.set_option(mpm.OPT_PERSISTENT, persistent)
@@ -269,14 +265,39 @@ def test_launch_modes_match_oracle(mpm, orc, persistent, block, chunk, sort_ever
     sim.close()
 
 
-def test_persistent_option_is_refused(mpm):
-    sc = scenes.small_scene(0, n=100, res=16)
-    announce("persistent refused")
-    sim = mpm.Sim([sc])
-    with pytest.raises(mpm.MPMError) as e:
-        sim.set_option(mpm.OPT_PERSISTENT, 1)
-    assert e.value.status == mpm.ERR_STATE
-    sim.close()
+@pytest.mark.parametrize("contact", [0, 2])
+def test_one_launch_substep_matches_three_launches(mpm, orc, contact):
+    """The one-launch substep (MPM_OPT_PERSISTENT: one cooperative kernel,
+    grid-wide barriers between P2G, grid update and G2P) queues exactly one
+    kernel per substep and gives what the three launches give (to FP32
+    reorder tolerance), with grid-node contact and with penalty contact too,
+    and the collider wrench sums agree."""
+    batch = [scenes.small_scene(90 + s, n=1500 + 700 * s, res=32, model=scenes.HENCKY_VM, n_ctrl=2, dt=1e-4)
+             for s in range(3)]
+    announce("one-launch substep, contact", contact)
+    out = []
+    for persistent in (0, 1):
+        sim = mpm.Sim(batch)
+        sim.set_option(mpm.OPT_CONTACT, contact)
+        sim.set_option(mpm.OPT_PERSISTENT, persistent)
+        sim.set_option(mpm.OPT_TIMING, 1)
+        sim.timing(reset=True)
+        sim.run_schedule(2)
+        assert sim.sync() == mpm.OK
+        kt = sim.timing(reset=True)
+        if persistent:
+            assert kt["persistent"][1] == 50 and kt["p2g"][1] == 0 and kt["g2p"][1] == 0
+        out.append((sim.get_state(-1), sim.collider_wrenches()))
+        sim.close()
+    (s0, w0), (s1, w1) = out
+    assert np.abs(s0[0] - s1[0]).max() <= 1e-4 * batch[0].dx
+    assert np.abs(w0 - w1).max() <= 1e-3 * max(np.abs(w0).max(), 1e-12)
+    x1 = s1[0]
+    off = np.cumsum([0] + [sc.n for sc in batch])
+    for s, sc in enumerate(batch):
+        o = orc.Oracle(sc, contact=contact)
+        o.run_schedule(2)
+        assert np.abs(x1[off[s]:off[s + 1]] - o.x).max() <= 1e-3 * sc.dx, s
 
 
 def test_nonfinite_state_is_reported(mpm):
