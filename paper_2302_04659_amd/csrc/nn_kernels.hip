@@ -11,9 +11,10 @@
 //   wgrad    D[ci][co] += sum_voxel X[p(voxel, tap)][ci] dY[voxel][co]
 // with tap geometries: 3^3 zero-padded ("c3"), 3^3 over a nearest x2
 // upsampled input ("up"), 2^3 stride 2 ("down") and 1^3 ("c1").  The 3^3
-// kinds with a multiple of 32 input channels, and the 3^3 first layer over 8
-// channels, run on v_mfma_f32_16x16x32_bf16 (gfx950, twice the rate of the
-// 16x16x16 form); the rest on v_mfma_f32_16x16x16bf16_1k.
+// kinds with a multiple of 32 input channels, the 3^3 first layer over 8
+// channels and every weight gradient run on v_mfma_f32_16x16x32_bf16
+// (gfx950, twice the rate of the 16x16x16 form); the rest on
+// v_mfma_f32_16x16x16bf16_1k.
 // Operand lane layout (wave64, 16x16x16): A[i][k] sits in lane i + 16 (k/4),
 // element k % 4; B[k][j] in lane j + 16 (k/4), element k % 4; D[i][j] in lane
 // j + 16 (i/4), element i % 4.  16x16x32: A[i][k] in lane i + 16 (k/8),
@@ -26,6 +27,7 @@
 namespace nn {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f)
@@ -571,13 +573,13 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
     for (int m = 0; m < MF; m++)
 #pragma unroll
         for (int n = 0; n < NF; n++) acc[m][n] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-    const int kq = 4 * (lane >> 4);
-    for (long long v0 = vb; v0 < ve; v0 += 16) {
-        // K = 16 voxels; this lane supplies voxels v0 + kq .. + 3
-        long long src[4], dst[4];
-        bool ok[4];
+    const int kq = 8 * (lane >> 4);
+    for (long long v0 = vb; v0 < ve; v0 += 32) {
+        // K = 32 voxels (16x16x32 MFMA); this lane supplies voxels v0 + kq .. + 7
+        long long src[8], dst[8];
+        bool ok[8];
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
+        for (int r = 0; r < 8; r++) {
             long long v = v0 + kq + r;
             ok[r] = v < ve;
             if (!ok[r]) v = vb;
@@ -593,24 +595,26 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
             dst[r] = v * a.cg + a.g_off;
             if (!(v0 + kq + r < ve)) dst[r] = -1;
         }
-        s4 Bv[NF];
+        b8 Bv[NF];
 #pragma unroll
         for (int n = 0; n < NF; n++) {
             const int co = 16 * n + (lane & 15);
+            s8 b;
 #pragma unroll
-            for (int r = 0; r < 4; r++)
-                Bv[n][r] = (dst[r] >= 0 && co < a.cout) ? (short)a.g[dst[r] + co] : (short)0;
+            for (int r = 0; r < 8; r++) b[r] = (dst[r] >= 0 && co < a.cout) ? (short)a.g[dst[r] + co] : (short)0;
+            Bv[n] = __builtin_bit_cast(b8, b);
         }
 #pragma unroll
         for (int m = 0; m < MF; m++) {
             const int cf = wv + 4 * m;
             if (cf >= KC) continue;
             const int ci = 16 * cf + (lane & 15);
-            s4 Av;
+            s8 Av;
 #pragma unroll
-            for (int r = 0; r < 4; r++) Av[r] = ok[r] ? (short)a.x[src[r] + ci] : (short)0;
+            for (int r = 0; r < 8; r++) Av[r] = ok[r] ? (short)a.x[src[r] + ci] : (short)0;
+            const b8 Ab = __builtin_bit_cast(b8, Av);
 #pragma unroll
-            for (int n = 0; n < NF; n++) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Av, Bv[n], acc[m][n], 0, 0, 0);
+            for (int n = 0; n < NF; n++) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ab, Bv[n], acc[m][n], 0, 0, 0);
         }
     }
     float *P = a.partial + (((long long)chunk * ntap + t) * a.cin) * a.cout;
@@ -636,8 +640,8 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a)
 // [16 cf, 16 cf + 16) and taps [8 tg, 8 tg + 8).  Per tile it stages the
 // input halo channel-major (xh[ci][halo voxel]) and the output-gradient tile
 // voxel-packed (gt[co][4-voxel pack]); wave w owns taps 8 tg + w and
-// 8 tg + w + 4 and accumulates, over the tile's voxels (K = 16 voxels = one
-// x row per MFMA), D[ci][co] += sum_v X[v + tap][ci] dY[v][co].  The partial
+// 8 tg + w + 4 and accumulates, over the tile's voxels (K = 32 voxels = two
+// x rows per MFMA), D[ci][co] += sum_v X[v + tap][ci] dY[v][co].  The partial
 // of the group goes to P[group][tap][ci][co].
 template <int NF, int KIND>
 __global__ __launch_bounds__(256) void k_wgrad_lds(WgradArgs a, int tpg, int ntiles)
@@ -706,34 +710,42 @@ __global__ __launch_bounds__(256) void k_wgrad_lds(WgradArgs a, int tpg, int nti
             for (int k = 0; k < 4; k++) gts[(c0 + k) * TV + v] = w4[k];
         }
         __syncthreads();
-        for (int row = 0; row < TZ * TLY; row++) {
-            const int tz = row / TLY, ty = row % TLY;
-            s4 Bv[NF];
+        // two tile rows per 16x16x32 MFMA: K slot 4 h + r of lane group q is voxel
+        // (row + h, x = 4 q + r) for both operands (K is summed over, so any
+        // common order of the 32 voxels will do)
+        for (int row = 0; row < TZ * TLY; row += 2) {
+            b8 Bv[NF];
 #pragma unroll
             for (int n = 0; n < NF; n++) {
-                const uint2 raw = gt[(16 * n + i) * (TV / 4) + (row * TLX + 4 * q) / 4];
-                Bv[n] = s4{(short)(raw.x & 0xffff), (short)(raw.x >> 16), (short)(raw.y & 0xffff), (short)(raw.y >> 16)};
+                const uint2 r0 = gt[(16 * n + i) * (TV / 4) + (row * TLX + 4 * q) / 4];
+                const uint2 r1 = gt[(16 * n + i) * (TV / 4) + ((row + 1) * TLX + 4 * q) / 4];
+                Bv[n] = __builtin_bit_cast(b8, make_uint4(r0.x, r0.y, r1.x, r1.y));
             }
 #pragma unroll
             for (int u = 0; u < 2; u++) {
                 const int t = u ? t1 : t0;
                 if (t >= tmax) continue;
                 const int ta = t / 9, tb = (t / 3) % 3, tc = t % 3;
-                s4 Av;
+                s8 Av;
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const int tx = 4 * q + r;
-                    int lz, ly, lx;
-                    if (KIND == KIND_C3) { lz = tz + ta; ly = ty + tb; lx = tx + tc; }
-                    else {
-                        lz = ((z0 + tz + ta - 1) >> 1) - hz0;
-                        ly = ((y0 + ty + tb - 1) >> 1) - hy0;
-                        lx = ((x0 + tx + tc - 1) >> 1) - hx0;
+                for (int h = 0; h < 2; h++) {
+                    const int tz = (row + h) / TLY, ty = (row + h) % TLY;
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int tx = 4 * q + r;
+                        int lz, ly, lx;
+                        if (KIND == KIND_C3) { lz = tz + ta; ly = ty + tb; lx = tx + tc; }
+                        else {
+                            lz = ((z0 + tz + ta - 1) >> 1) - hz0;
+                            ly = ((y0 + ty + tb - 1) >> 1) - hy0;
+                            lx = ((x0 + tx + tc - 1) >> 1) - hx0;
+                        }
+                        Av[4 * h + r] = (short)xh[i * nh + (lz * hy + ly) * hx + lx];
                     }
-                    Av[r] = (short)xh[i * nh + (lz * hy + ly) * hx + lx];
                 }
+                const b8 Ab = __builtin_bit_cast(b8, Av);
 #pragma unroll
-                for (int n = 0; n < NF; n++) acc[u][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Av, Bv[n], acc[u][n], 0, 0, 0);
+                for (int n = 0; n < NF; n++) acc[u][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ab, Bv[n], acc[u][n], 0, 0, 0);
             }
         }
         __syncthreads();
