@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # (FP32): P2G reads x, v, A (15 floats); G2P reads x, G (12 floats) and
 # writes x, v, A, G (24 floats).  Grid bytes (16 B per active node and
 # pass) are left out, so `achieved` is a lower bound.
-ALG_BYTES = {"p2g": 60.0, "g2p": 144.0, "grid": 0.0, "sort": 0.0, "persistent": 204.0}
+ALG_BYTES = {"p2g": 60.0, "g2p": 144.0, "grid": 0.0, "sort": 0.0, "persistent": 204.0, "g2p2g": 96.0}
 # Sources the substep kernels are compiled from: a traffic summary is valid
 # only for the exact sources it was measured on.
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2302_04659_amd", "csrc", f) for f in
@@ -133,6 +133,8 @@ def main():
                     help="1: replay each 25-substep control step from a captured hipGraph (the default "
                          "production path), 0: launch every kernel from the host")
     ap.add_argument("--persistent", type=int, default=-1)
+    ap.add_argument("--fuse", type=int, default=-1, help="1: G2P and the next P2G in one launch (library default 0)")
+    ap.add_argument("--wg", type=int, default=0, help="threads per workgroup of the particle kernels (256, 512)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-scenes", type=int, default=64)
     ap.add_argument("--cpu-substeps", type=int, default=50)
@@ -177,6 +179,10 @@ def main():
         sim.set_option(mpm.OPT_GRAPH, args.graph)
     if args.persistent >= 0:
         sim.set_option(mpm.OPT_PERSISTENT, args.persistent)
+    if args.fuse >= 0:
+        sim.set_option(mpm.OPT_FUSE, args.fuse)
+    if args.wg:
+        sim.set_option(mpm.OPT_WG, args.wg)
     tune = None
     if args.autotune and not (args.block or args.chunk or args.sort_every):
         tune = sim.autotune(10)
@@ -224,7 +230,7 @@ def main():
     assert substeps == SUB * args.steps, window
     value = N * substeps / elapsed
     per_launch = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
-    dom = max(("p2g", "g2p", "grid", "sort", "persistent"), key=lambda k: kt[k][0])
+    dom = max(("p2g", "g2p", "grid", "sort", "persistent", "g2p2g"), key=lambda k: kt[k][0])
     dom_ms = per_launch[dom]
     bytes_launch = ALG_BYTES[dom] * N
     achieved = bytes_launch / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
@@ -246,6 +252,7 @@ def main():
         "config": {"workload": desc, "scenes": len(scene_list), "particles": N, "substeps_per_step": SUB,
                    "block": sim.get_option(mpm.OPT_BLOCK), "chunk": sim.get_option(mpm.OPT_CHUNK),
                    "sort_every": sim.get_option(mpm.OPT_SORT_EVERY),
+                   "wg": sim.get_option(mpm.OPT_WG), "fuse": sim.get_option(mpm.OPT_FUSE),
                    "graph": sim.get_option(mpm.OPT_GRAPH), "persistent": sim.get_option(mpm.OPT_PERSISTENT)},
         "window": window,
         "kernels_ms_per_launch": {k: round(v, 5) for k, v in per_launch.items()},

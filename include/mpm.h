@@ -219,13 +219,23 @@ typedef enum {
                                  * 1: particle penalty: a particle inside a collider after its
                                  *    position update gets -phi n / (4 dt) (stiffness m / (4 dt^2));
                                  * 2: both.  Either reaction goes into mpm_get_collider_wrenches. */
-    MPM_OPT_WG = 8              /* threads per workgroup of the particle kernels (P2G, G2P): 256
+    MPM_OPT_WG = 8,             /* threads per workgroup of the particle kernels (P2G, G2P): 256
                                  * (default) or 512 */
+    MPM_OPT_FUSE = 9            /* 1: between two re-sorts, the G2P of a substep and the P2G of
+                                 * the next run as one pass over the particles (each advanced
+                                 * particle is scattered from registers into the fixed-point LDS
+                                 * tile; only x and F are stored, and the last substep of the run,
+                                 * or of the call, stores v and C too); 0 (default): separate P2G
+                                 * and G2P launches.  Same results to FP32 reorder tolerance; the
+                                 * fused launch moves about half the bytes but is slower on MI355X
+                                 * (its LDS atomics and the G2P arithmetic do not overlap). */
 } mpm_option;
 
-/* Kernel classes reported by mpm_get_timing. */
+/* Kernel classes reported by mpm_get_timing (MPM_K_G2P2G: the fused G2P +
+ * next-substep P2G launch of MPM_OPT_FUSE). */
 typedef enum {
-    MPM_K_SORT = 0, MPM_K_P2G = 1, MPM_K_GRID = 2, MPM_K_G2P = 3, MPM_K_PERSISTENT = 4, MPM_KCLASSES = 5
+    MPM_K_SORT = 0, MPM_K_P2G = 1, MPM_K_GRID = 2, MPM_K_G2P = 3, MPM_K_PERSISTENT = 4, MPM_K_G2P2G = 5,
+    MPM_KCLASSES = 6
 } mpm_kernel_class;
 
 mpm_status mpm_set_option(mpm_ctx ctx, int option, int value);

@@ -119,6 +119,7 @@ struct mpm_ctx_s {
     long long cap_nodes = 0;
 
     int persistent = 0, graph = 0;
+    int fuse = 0;                    // MPM_OPT_FUSE: G2P and the next P2G in one launch
     int contact = 0;                 // MPM_OPT_CONTACT
     std::map<GraphKey, GraphEntry> graphs;
 
@@ -396,6 +397,7 @@ StepArgs step_args(mpm_ctx ctx, int substep)
     a.sdf = ctx->d_sdf;
     a.contact = ctx->contact;
     a.nt = ctx->nt;
+    a.chain = 0;
     return a;
 }
 
@@ -418,38 +420,55 @@ int substep_wgs(mpm_ctx ctx) { return ctx->cus * 32; }
 int grid_wgs(mpm_ctx ctx) { return ctx->cus * 16; }
 
 // Queue n substeps (sort when due, P2G, grid, G2P) and the collider advance.
+// With fusion on, a run of substeps with no re-sort inside is queued as
+// P2G, grid, (G2P2G, grid) x (run - 1), G2P: the G2P of one substep and the
+// P2G of the next share a pass over the particles, and the state at the end
+// of the run (and at a re-sort) is complete again.
 mpm_status queue_plain(mpm_ctx ctx, int n)
 {
-    for (int i = 0; i < n; i++) {
+    int i = 0;
+    while (i < n) {
         if (ctx->since_sort >= ctx->sort_every) {
             mpm_status st = do_sort(ctx);
             if (st != MPM_OK) return st;
         }
-        if (ctx->capture) HIPCHK(launch_clear_f(ctx->d_cap, 4 * ctx->cap_nodes, ctx->stream));
-        StepArgs a = step_args(ctx, i);
         if (ctx->persistent && !ctx->capture) {
+            StepArgs a = step_args(ctx, i);
             KTimer kt(ctx, MPM_K_PERSISTENT);
             HIPCHK(launch_persistent(a, ctx->cus, ctx->stream));
             ctx->since_sort++;
             ctx->cnt[MPM_CNT_SUBSTEPS]++;
             ctx->cnt[MPM_CNT_HOST_SUBSTEPS]++;
+            i++;
             continue;
         }
+        // substeps until the end of the call or the next re-sort
+        const int run = ctx->fuse ? std::min(n - i, ctx->sort_every - ctx->since_sort) : 1;
         {
             KTimer kt(ctx, MPM_K_P2G);
+            StepArgs a = step_args(ctx, i);
+            a.chain = run > 1;   // the fused G2P reads the scatter bound and cell count of this state
             HIPCHK(launch_p2g(a, ctx->CH, substep_wgs(ctx), ctx->stream));
         }
-        {
-            KTimer kt(ctx, MPM_K_GRID);
-            HIPCHK(launch_grid(a, grid_wgs(ctx), ctx->stream));
+        for (int k = i; k < i + run; k++) {
+            StepArgs a = step_args(ctx, k);
+            if (ctx->capture) HIPCHK(launch_clear_f(ctx->d_cap, 4 * ctx->cap_nodes, ctx->stream));
+            {
+                KTimer kt(ctx, MPM_K_GRID);
+                HIPCHK(launch_grid(a, grid_wgs(ctx), ctx->stream));
+            }
+            if (k + 1 < i + run) {
+                KTimer kt(ctx, MPM_K_G2P2G);
+                HIPCHK(launch_g2p2g(a, substep_wgs(ctx), ctx->stream));
+            } else {
+                KTimer kt(ctx, MPM_K_G2P);
+                HIPCHK(launch_g2p(a, substep_wgs(ctx), ctx->stream));
+            }
         }
-        {
-            KTimer kt(ctx, MPM_K_G2P);
-            HIPCHK(launch_g2p(a, substep_wgs(ctx), ctx->stream));
-        }
-        ctx->since_sort++;
-        ctx->cnt[MPM_CNT_SUBSTEPS]++;
-        ctx->cnt[MPM_CNT_HOST_SUBSTEPS]++;
+        ctx->since_sort += run;
+        ctx->cnt[MPM_CNT_SUBSTEPS] += run;
+        ctx->cnt[MPM_CNT_HOST_SUBSTEPS] += run;
+        i += run;
     }
     HIPCHK(launch_collider_advance(ctx->d_cols, (int)ctx->h_cols.size(), ctx->d_col_scene, ctx->d_scenes, n,
                                    ctx->stream));
@@ -660,7 +679,7 @@ mpm_status create_impl(mpm_ctx ctx, const mpm_scene_desc *scenes, int n_scenes)
     HIPCHK(dalloc(&ctx->L.bflag, T4));
     HIPCHK(dalloc(&ctx->L.touched, T4));
     HIPCHK(dalloc(&ctx->L.ovf, T4));
-    HIPCHK(dalloc(&ctx->L.n_ovf, 1));
+    HIPCHK(dalloc(&ctx->L.n_ovf, 2));
     ctx->L.ovf_cap = T4;
     HIPCHK(dalloc(&ctx->d_flags, n_scenes));
     HIPCHK(dalloc(&ctx->d_active, n_scenes));
@@ -686,7 +705,7 @@ mpm_status create_impl(mpm_ctx ctx, const mpm_scene_desc *scenes, int n_scenes)
     HIPCHK(hipMemsetAsync(ctx->d_count, 0, sizeof(int) * T4, ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->L.bflag, 0, sizeof(int) * T4, ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->L.touched, 0, T4, ctx->stream));
-    HIPCHK(hipMemsetAsync(ctx->L.n_ovf, 0, sizeof(int), ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->L.n_ovf, 0, 2 * sizeof(int), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->L.n_items, 0, sizeof(int), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->L.n_gitems, 0, sizeof(int), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->d_flags, 0, sizeof(int) * n_scenes, ctx->stream));
@@ -1009,6 +1028,11 @@ mpm_status mpm_set_option(mpm_ctx ctx, int option, int value)
         ARGCHK(value == 0 || value == 1, "graph must be 0 or 1");
         ctx->graph = value;
         return MPM_OK;
+    case MPM_OPT_FUSE:
+        ARGCHK(value == 0 || value == 1, "fuse must be 0 or 1");
+        ctx->fuse = value;
+        clear_graphs(ctx);   // the captured kernels depend on it
+        return MPM_OK;
     case MPM_OPT_WG:
         ARGCHK(value == 256 || value == 512, "workgroup size must be 256 or 512");
         ctx->nt = value;
@@ -1047,6 +1071,7 @@ mpm_status mpm_get_option(mpm_ctx ctx, int option, int *value)
     case MPM_OPT_GRAPH: *value = ctx->graph; return MPM_OK;
     case MPM_OPT_CONTACT: *value = ctx->contact; return MPM_OK;
     case MPM_OPT_WG: *value = ctx->nt; return MPM_OK;
+    case MPM_OPT_FUSE: *value = ctx->fuse; return MPM_OK;
     case MPM_OPT_CAPTURE_GRID: *value = ctx->capture; return MPM_OK;
     case MPM_OPT_TIMING: *value = ctx->timing; return MPM_OK;
     }
@@ -1161,7 +1186,7 @@ mpm_status mpm_sur_features(mpm_ctx ctx, float *feat, int cf, float *grid0, cons
     a.wrench = nullptr;   // not a substep: no impulse on the colliders
     HIPCHK(launch_p2g(a, ctx->CH, substep_wgs(ctx), ctx->stream));
     HIPCHK(launch_grid(a, grid_wgs(ctx), ctx->stream));
-    HIPCHK(launch_fill_i(ctx->L.n_ovf, 1, 0, ctx->stream));   // the overflow list has been consumed
+    HIPCHK(launch_fill_i(ctx->L.n_ovf, 2, 0, ctx->stream));   // the overflow list has been consumed
     return MPM_OK;
 }
 
@@ -1214,7 +1239,7 @@ mpm_status sur_block_impl(mpm_ctx ctx, const float *pred, int cp, const float *g
     r.wrench = nullptr;   // the re-splat is a check, not a substep
     HIPCHK(launch_p2g(r, ctx->CH, substep_wgs(ctx), ctx->stream));
     HIPCHK(launch_grid(r, grid_wgs(ctx), ctx->stream));
-    HIPCHK(launch_fill_i(ctx->L.n_ovf, 1, 0, ctx->stream));
+    HIPCHK(launch_fill_i(ctx->L.n_ovf, 2, 0, ctx->stream));
     HIPCHK(launch_clear_f(ctx->d_sur_acc, 4 * ctx->n_scenes, ctx->stream));
     HIPCHK(launch_sur_residual(a, R, grid0, pred, cp, ctx->d_sur_gend, ctx->d_sur_acc, ctx->stream));
     HIPCHK(launch_fill_i(ctx->d_sur_nfb, 1, 0, ctx->stream));

@@ -359,13 +359,20 @@ __device__ __forceinline__ void load_particle_xvA(const StepArgs &a, int jj, flo
     for (int e = 0; e < 9; e++) A[e] = pload(P, ps, A00 + e, jo);
 }
 
+// Length of the overflow list of substep k.  Two counters alternate by
+// substep parity: the G2P of substep k clears counter k & 1 (its grid update
+// has consumed the list) while a P2G fused into the same launch already
+// fills the list of substep k + 1; at the end of every substep both are zero.
+__device__ __forceinline__ int *ovf_count(const StepArgs &a, int k) { return a.L.n_ovf + (k & 1); }
+
 // Put a grid block that is not on the static update list on the overflow
-// list (once per substep).
-__device__ __forceinline__ void queue_block(const StepArgs &a, int s, const SceneDev &S, int lb)
+// list (once per substep); n_ovf: the list length of the substep that
+// scatters.
+__device__ __forceinline__ void queue_block(const StepArgs &a, int s, const SceneDev &S, int lb, int *n_ovf)
 {
     int *fl = a.L.bflag + S.bin_off + lb;
     if (*fl == 0 && atomicCAS(fl, 0, 1) == 0) {
-        int pos = atomicAdd(a.L.n_ovf, 1);
+        int pos = atomicAdd(n_ovf, 1);
         if (pos < a.L.ovf_cap) a.L.ovf[pos] = make_int2(s, lb);
         else atomicOr(a.flags + s, (int)FLAG_OVERFLOW_FULL);
     }
@@ -374,7 +381,7 @@ __device__ __forceinline__ void queue_block(const StepArgs &a, int s, const Scen
 // Slow path of P2G: scatter one particle straight into the global grid and
 // queue any block that is not already on the grid-update list.
 __device__ void p2g_global(const StepArgs &a, int s, const SceneDev &S, const float x[3], const float v[3],
-                           const float A[9], const int b[3], const float f[3])
+                           const float A[9], const int b[3], const float f[3], int *n_ovf)
 {
     int B = a.B;
     float w[3][3];
@@ -397,20 +404,10 @@ __device__ void p2g_global(const StepArgs &a, int s, const SceneDev &S, const fl
                 if ((cx && bx == b[0] / B) || (cy && by == b[1] / B) || (cz && bz == b[2] / B)) continue;
                 const int lb = (bx * S.nb + by) * S.nb + bz;
                 a.L.touched[S.bin_off + lb] = 1;
-                queue_block(a, s, S, lb);
+                queue_block(a, s, S, lb, n_ovf);
             }
 }
 
-// Collider poses of scene s at substep k, written once per substep.
-__device__ void write_colliders_now(const StepArgs &a, const SceneDev &S)
-{
-    int t = threadIdx.x;
-    if (t < S.n_col) {
-        ColliderNow cn;
-        collider_at(a.cols[S.col_off + t], (float)a.substep * S.dt, cn);
-        ((ColliderNow *)a.colnow)[S.col_off + t] = cn;
-    }
-}
 
 // Rounding by addition: RND = 1.5 * 2^23, whose float spacing is 1 for sums in [2^23, 2^24).
 constexpr float RND = 12582912.0f;
@@ -422,6 +419,116 @@ template <int B> constexpr int p2g_cells() { return (B + 2) * (B + 2) * (B + 2);
 // Items with more particles than this count their particles per base cell
 // before scattering (below it the per-term limit already sets the scale).
 constexpr int P2G_COUNT_MIN = 256;
+
+// Power-of-two fixed-point scales of the P2G tile, keeping every node sum
+// below 2^30: |contribution| <= w * bound with the weights of a node summing
+// to at most wsum; and every single term within 2^22 (w <= 0.421875; rounded
+// by the RND addition of scatter_packed).  A particle may be scattered into
+// the tile while its scatter bound b satisfies b * sp <= lim.
+struct TileScale {
+    float msc;   // Sm m: mass-scaled weights
+    float kk;    // Sp / (Sm m): momentum scale relative to the mass-scaled weight
+    float sp;    // Sp
+    float lim;
+    float im, ip;   // 1 / Sm, 1 / Sp
+};
+
+__device__ __forceinline__ TileScale tile_scale(const SceneK &K, float wsum, float bmax)
+{
+    TileScale ts;
+    ts.lim = fminf(1073741824.0f / wsum, 4194304.0f / 0.421875f);
+    int em = ilogbf(ts.lim / K.mass);
+    em = min(max(em, -120), 120);
+    int ep = bmax > 0.0f ? ilogbf(ts.lim / bmax) : 120;
+    ep = min(max(ep, -120), 120);
+    const float Sm = ldexpf(1.0f, em), Sp = ldexpf(1.0f, ep);
+    ts.kk = Sp / (Sm * K.mass);
+    ts.msc = Sm * K.mass;
+    ts.sp = Sp;
+    ts.im = 1.0f / Sm;
+    ts.ip = 1.0f / Sp;
+    return ts;
+}
+
+// One particle's 27 stencil terms into the tile t64 (per node two 64-bit sums,
+// (p_x, m) and (p_y, p_z) as (hi, lo), each the exact sum of 32-bit fixed-point
+// terms packed as hi * 2^32 + lo: an integer sum, so both halves are recovered
+// exactly while they fit in 32 bits); tb: the particle's base cell in tile
+// coordinates, f its offset from it in cells.
+template <int B>
+__device__ __forceinline__ void scatter_packed(long long *t64, const int tb[3], const float f[3], const TileScale &ts,
+                                               const SceneK &K, const float v[3], const float A[9])
+{
+    constexpr int T = B + 4, T3 = T * T * T;
+    float wx[3], wy[3], wz[3];
+    bspline_w(f[0], wx);
+    bspline_w(f[1], wy);
+    bspline_w(f[2], wz);
+#pragma unroll
+    for (int o = 0; o < 3; o++) wx[o] *= ts.msc;
+    // r(o) = kk * (m v + A (o - f) dx); increments along each axis
+    float Ad[3][3], r0[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+#pragma unroll
+        for (int e = 0; e < 3; e++) Ad[c][e] = ts.kk * A[3 * c + e] * K.dx;
+        r0[c] = ts.kk * K.mass * v[c] - (Ad[c][0] * f[0] + Ad[c][1] * f[1] + Ad[c][2] * f[2]);
+    }
+    long long *tb0 = t64 + (tb[0] * T + tb[1]) * T + tb[2];
+    // r at offset (ox, oy, oz): r0 + ox Ad_x + oy Ad_y + oz Ad_z, one add per axis step
+    // (offset 0 adds nothing, 1 adds Ad, 2 adds 2 Ad)
+    auto step = [](float r, float d, int o) { return o == 0 ? r : (o == 1 ? r + d : fmaf(2.0f, d, r)); };
+#pragma unroll
+    for (int ox = 0; ox < 3; ox++)
+#pragma unroll
+        for (int oy = 0; oy < 3; oy++) {
+            float wxy = wx[ox] * wy[oy];
+            float rxy[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) rxy[c] = step(step(r0[c], Ad[c][0], ox), Ad[c][1], oy);
+#pragma unroll
+            for (int oz = 0; oz < 3; oz++) {
+                float w = wxy * wz[oz];
+                int o = (ox * T + oy) * T + oz;
+                // x + RND (|x| <= 2^22) holds round(x) in its low mantissa bits: bits = RND_BITS + round(x).
+                // A pair of such bit patterns as hi * 2^32 + lo, minus RND_BITS * (2^32 + 1), is
+                // round(x_hi) * 2^32 + round(x_lo) exactly (one 64-bit subtraction per pair).
+                const unsigned b0 = __float_as_uint(fmaf(wxy, wz[oz], RND));   // mass term
+                const unsigned b1 = __float_as_uint(fmaf(w, step(rxy[0], Ad[0][2], oz), RND));
+                const unsigned b2 = __float_as_uint(fmaf(w, step(rxy[1], Ad[1][2], oz), RND));
+                const unsigned b3 = __float_as_uint(fmaf(w, step(rxy[2], Ad[2][2], oz), RND));
+                atomicAdd((unsigned long long *)(tb0 + o), ((unsigned long long)b1 << 32 | b0) - RND_PAIR);
+                atomicAdd((unsigned long long *)(tb0 + T3 + o), ((unsigned long long)b2 << 32 | b3) - RND_PAIR);
+            }
+        }
+}
+
+// The tile's node sums into the global grid: marks the grid blocks that
+// received mass, queues lower neighbour blocks off the update list.
+template <int B, int NT>
+__device__ void flush_packed(const StepArgs &a, int s, const SceneDev &S, const int org[3], const long long *t64,
+                             const TileScale &ts, int *n_ovf)
+{
+    constexpr int T = B + 4, T3 = T * T * T;
+    for (int n = threadIdx.x; n < T3; n += NT) {
+        int m0, p0, p1, p2;
+        unpack2(t64[n], p0, m0);
+        unpack2(t64[T3 + n], p1, p2);
+        if ((m0 | p0 | p1 | p2) == 0) continue;
+        int tx = n / (T * T), ty = (n / T) % T, tz = n % T;
+        int gi = org[0] + tx, gj = org[1] + ty, gk = org[2] + tz;
+        if (gi < 0 || gj < 0 || gk < 0 || gi >= S.res || gj >= S.res || gk >= S.res) continue;
+        const int lb = ((gi / B) * S.nb + (gj / B)) * S.nb + (gk / B);
+        a.L.touched[S.bin_off + lb] = 1;
+        if (tx == 0 || ty == 0 || tz == 0)   // node of a lower neighbour block: make sure it is updated
+            queue_block(a, s, S, lb, n_ovf);
+        long long idx = node_index(S, B, gi, gj, gk);
+        atomicAdd(a.gm + idx, (float)m0 * ts.im);
+        atomicAdd(a.gpx + idx, (float)p0 * ts.ip);
+        atomicAdd(a.gpy + idx, (float)p1 * ts.ip);
+        atomicAdd(a.gpz + idx, (float)p2 * ts.ip);
+    }
+}
 
 template <int B, int NT = WG>
 __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile, int *cells)
@@ -450,9 +557,8 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile,
     }
     // bound of this item's particles, left by the previous G2P (or the sort)
     const float bmax = a.L.ibound[it];
-    if (it == a.L.scene_item_begin[s]) write_colliders_now(a, S);
     __syncthreads();
-    if (t == 0 && !a.keep_bound) a.L.ibound[it] = 0.0f;   // this substep's G2P accumulates the next bound
+    if (t == 0 && !a.keep_bound && !a.chain) a.L.ibound[it] = 0.0f;   // this substep's G2P accumulates the next bound
 
     // Node sums of weights: a node receives w <= 0.5, 0.75, 0.5 per axis from
     // particles whose base cell is 0, 1, 2 cells below it, so the weights
@@ -484,23 +590,13 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile,
         mx = wave_max_i(mx);
         if ((t & 63) == 0) atomicMax(cells + NC, mx);
         __syncthreads();
+        if (a.chain && t == 0) a.L.icell[it] = cells[NC];   // the fused G2P's scale
         wsum = fminf(wsum, 5.359375f * (float)max(cells[NC], 1));
     } else if (known > 0) {
         wsum = fminf(wsum, 5.359375f * (float)known);
     }
 
-    // Power-of-two fixed-point scales keeping every node sum below 2^30:
-    // |contribution| <= w * bound with the weights of a node summing to at
-    // most wsum; and every single term within 2^22 (w <= 0.421875; rounded by
-    // the RND addition below).
-    const float lim = fminf(1073741824.0f / wsum, 4194304.0f / 0.421875f);
-    int em = ilogbf(lim / K.mass);
-    em = min(max(em, -120), 120);
-    int ep = bmax > 0.0f ? ilogbf(lim / bmax) : 120;
-    ep = min(max(ep, -120), 120);
-    const float Sm = ldexpf(1.0f, em), Sp = ldexpf(1.0f, ep);
-    const float kk = Sp / (Sm * K.mass);       // momentum scale relative to the mass-scaled weight
-    const float msc = Sm * K.mass;
+    const TileScale ts = tile_scale(K, wsum, bmax);
 
     for (int base = 0; base < item.count; base += NT) {
         const int li = base + t;
@@ -517,71 +613,14 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile,
         }
         if (cl) atomicOr(a.flags + s, (int)FLAG_CLAMPED);
         if (!in || cl) {
-            p2g_global(a, s, S, x, v, A, bp, f);
+            p2g_global(a, s, S, x, v, A, bp, f, ovf_count(a, a.substep));
             continue;
         }
-        float wx[3], wy[3], wz[3];
-        bspline_w(f[0], wx);
-        bspline_w(f[1], wy);
-        bspline_w(f[2], wz);
-#pragma unroll
-        for (int o = 0; o < 3; o++) wx[o] *= msc;
-        // r(o) = kk * (m v + A (o - f) dx); increments along each axis
-        float Ad[3][3], r0[3];
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-#pragma unroll
-            for (int e = 0; e < 3; e++) Ad[c][e] = kk * A[3 * c + e] * K.dx;
-            r0[c] = kk * K.mass * v[c] - (Ad[c][0] * f[0] + Ad[c][1] * f[1] + Ad[c][2] * f[2]);
-        }
-        long long *tb = t64 + ((bp[0] - org[0]) * T + (bp[1] - org[1])) * T + (bp[2] - org[2]);
-        // r at offset (ox, oy, oz): r0 + ox Ad_x + oy Ad_y + oz Ad_z, one add per axis step
-        // (offset 0 adds nothing, 1 adds Ad, 2 adds 2 Ad)
-        auto step = [](float r, float d, int o) { return o == 0 ? r : (o == 1 ? r + d : fmaf(2.0f, d, r)); };
-#pragma unroll
-        for (int ox = 0; ox < 3; ox++)
-#pragma unroll
-            for (int oy = 0; oy < 3; oy++) {
-                float wxy = wx[ox] * wy[oy];
-                float rxy[3];
-#pragma unroll
-                for (int c = 0; c < 3; c++) rxy[c] = step(step(r0[c], Ad[c][0], ox), Ad[c][1], oy);
-#pragma unroll
-                for (int oz = 0; oz < 3; oz++) {
-                    float w = wxy * wz[oz];
-                    int o = (ox * T + oy) * T + oz;
-                    // x + RND (|x| <= 2^22) holds round(x) in its low mantissa bits: bits = RND_BITS + round(x).
-                    // A pair of such bit patterns as hi * 2^32 + lo, minus RND_BITS * (2^32 + 1), is
-                    // round(x_hi) * 2^32 + round(x_lo) exactly (one 64-bit subtraction per pair).
-                    const unsigned b0 = __float_as_uint(fmaf(wxy, wz[oz], RND));   // mass term
-                    const unsigned b1 = __float_as_uint(fmaf(w, step(rxy[0], Ad[0][2], oz), RND));
-                    const unsigned b2 = __float_as_uint(fmaf(w, step(rxy[1], Ad[1][2], oz), RND));
-                    const unsigned b3 = __float_as_uint(fmaf(w, step(rxy[2], Ad[2][2], oz), RND));
-                    atomicAdd((unsigned long long *)(tb + o), ((unsigned long long)b1 << 32 | b0) - RND_PAIR);
-                    atomicAdd((unsigned long long *)(tb + T3 + o), ((unsigned long long)b2 << 32 | b3) - RND_PAIR);
-                }
-            }
+        const int tb[3] = {bp[0] - org[0], bp[1] - org[1], bp[2] - org[2]};
+        scatter_packed<B>(t64, tb, f, ts, K, v, A);
     }
     __syncthreads();
-    const float im = 1.0f / Sm, ip = 1.0f / Sp;
-    for (int n = t; n < T3; n += NT) {
-        int m0, p0, p1, p2;
-        unpack2(t64[n], p0, m0);
-        unpack2(t64[T3 + n], p1, p2);
-        if ((m0 | p0 | p1 | p2) == 0) continue;
-        int tx = n / (T * T), ty = (n / T) % T, tz = n % T;
-        int gi = org[0] + tx, gj = org[1] + ty, gk = org[2] + tz;
-        if (gi < 0 || gj < 0 || gk < 0 || gi >= S.res || gj >= S.res || gk >= S.res) continue;
-        const int lb = ((gi / B) * S.nb + (gj / B)) * S.nb + (gk / B);
-        a.L.touched[S.bin_off + lb] = 1;
-        if (tx == 0 || ty == 0 || tz == 0)   // node of a lower neighbour block: make sure it is updated
-            queue_block(a, s, S, lb);
-        long long idx = node_index(S, B, gi, gj, gk);
-        atomicAdd(a.gm + idx, (float)m0 * im);
-        atomicAdd(a.gpx + idx, (float)p0 * ip);
-        atomicAdd(a.gpy + idx, (float)p1 * ip);
-        atomicAdd(a.gpz + idx, (float)p2 * ip);
-    }
+    flush_packed<B, NT>(a, s, S, org, t64, ts, ovf_count(a, a.substep));
     __syncthreads();
 }
 
@@ -626,9 +665,12 @@ __device__ void grid_block(const StepArgs &a, int s, int lb, int lane, ColliderN
     const float gdt[3] = {K.dt * uniform_f(S.g[0]), K.dt * uniform_f(S.g[1]), K.dt * uniform_f(S.g[2])};
     const long long goff = S.grid_off;
     {
-        const float *src = (const float *)((const ColliderNow *)a.colnow + S.col_off);
-        float *dst = (float *)cl;
-        for (int q = lane; q < n_col * (int)(sizeof(ColliderNow) / 4); q += 64) dst[q] = src[q];
+        // this substep's collider poses, one lane per collider
+        if (lane < n_col) {
+            ColliderNow cn;
+            collider_at(a.cols[S.col_off + lane], (float)a.substep * K.dt, cn);
+            cl[lane] = cn;
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -709,19 +751,34 @@ __device__ void grid_block(const StepArgs &a, int s, int lb, int lane, ColliderN
     if (lane == 0) *tf = 0;
 }
 
+// The wave that takes the first static grid block of scene s also leaves the
+// scene's collider poses of this substep in a.colnow for the G2P (penalty
+// contact reads them there).
+__device__ __forceinline__ void publish_colliders(const StepArgs &a, int w, int s, int lane)
+{
+    if (w != a.L.scene_gitem_begin[s]) return;
+    const SceneDev &S = a.scenes[s];
+    if (lane < S.n_col) {
+        ColliderNow cn;
+        collider_at(a.cols[S.col_off + lane], (float)a.substep * S.dt, cn);
+        ((ColliderNow *)a.colnow)[S.col_off + lane] = cn;
+    }
+}
+
 template <int B, bool EXTRA>
 __global__ __launch_bounds__(WG, (B == 8 && !EXTRA) ? 7 : 1) void k_grid(StepArgs a)
 {
     const int lane = threadIdx.x & 63;
     __shared__ ColliderNow cls[WG / 64][MAX_COLLIDERS_PER_SCENE];
     const int ng = *a.L.n_gitems;
-    const int no = min(*a.L.n_ovf, a.L.ovf_cap);
+    const int no = min(*ovf_count(a, a.substep), a.L.ovf_cap);
     const int G = active_wgs((ng + no + WG / 64 - 1) / (WG / 64));
     if ((int)blockIdx.x >= G) return;
     const int nw = G * (WG / 64);
     const int w0 = xcd_remap(blockIdx.x, G) * (WG / 64) + (threadIdx.x >> 6);
     for (int w = w0; w < ng + no; w += nw) {
         int2 e = w < ng ? a.L.gitems[w] : a.L.ovf[w - ng];
+        if (w < ng) publish_colliders(a, w, e.x, lane);
         grid_block<B, EXTRA>(a, e.x, e.y, lane, cls[threadIdx.x >> 6]);
         if (w >= ng && lane == 0) a.L.bflag[a.scenes[e.x].bin_off + e.y] = 0;
     }
@@ -732,8 +789,21 @@ __global__ __launch_bounds__(WG, (B == 8 && !EXTRA) ? 7 : 1) void k_grid(StepArg
 // cells: LDS of p2g_cells<B>() + 1 ints; the item's particles are counted per
 // base cell of their new position (as the next P2G's tile sees them) and the
 // largest count is left in L.icell[it] for that P2G's fixed-point scale.
-template <int B, bool PF, bool PEN, int NT = WG>
-__device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt, float *pf, int *cells)
+// FUSE: the P2G of substep a.substep + 1 follows in the same pass: each
+// particle, once advanced, is scattered from registers into the fixed-point
+// LDS tile t64 (as p2g_item's), which is flushed to the grid at the end of the
+// item; only x and G are stored (v and A live on in the grid, and the G2P
+// that ends the run of fused substeps stores them).  The tile's scale has to
+// be fixed before any particle has moved, so it comes from the state this
+// G2P starts from: the largest particle count of a base cell (L.icell) and
+// the scatter bound (L.ibound, with 1/8 headroom).  Both stay bounds of the
+// scattered state because a particle goes into the tile only if it kept its
+// base cell (so no cell gains particles) and its bound stays within the
+// scale; any other particle is scattered straight into the grid.  The item's
+// L.ibound and L.icell are then replaced by those of the advanced state.
+template <int B, bool PF, bool PEN, int NT = WG, bool FUSE = false>
+__device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt, float *pf, int *cells,
+                         long long *t64 = nullptr)
 {
     constexpr int T = B + 4, T3 = T * T * T, NC = p2g_cells<B>();
     const int t = threadIdx.x;
@@ -749,6 +819,17 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
     // the compiler, which would reload them after each one)
     const Material mat = material_of(S);
     const SceneK K = scene_k(S);
+    TileScale ts{};
+    if (FUSE) {
+        const int known = item.count > P2G_COUNT_MIN ? a.L.icell[it] : 0;
+        float wsum = 0.421875f * (float)item.count;
+        if (known > 0) wsum = fminf(wsum, 5.359375f * (float)known);
+        // floor: 2^-20 of the momentum of a particle crossing a cell per substep (a state at rest
+        // has bound 0)
+        const float floor_b = 9.5367431640625e-7f * K.mass * K.dx / K.dt;
+        ts = tile_scale(K, wsum, fmaxf(1.125f * a.L.ibound[it], floor_b));
+        for (int n = t; n < 2 * T3; n += NT) t64[n] = 0;
+    }
     for (int n = t; n < NC + 1; n += NT) cells[n] = 0;
     if (PF) {
         const int res = uniform_i(S.res);
@@ -788,6 +869,7 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
         }
     }
     __syncthreads();
+    if (FUSE && t == 0) a.L.ibound[it] = 0.0f;   // read by every thread above; the advanced state's bound follows
     int bad_any = 0, cl_any = 0;
     float bnd = 0.0f;
     // penalty contact: this substep's collider poses of the scene (uniform), the per-lane sums of
@@ -890,17 +972,17 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
             for (int e = 0; e < 3; e++) C[3 * c + e] = Dd * fmaf(-vp[c], f[e], So[c][e]);
 #pragma unroll
         for (int d = 0; d < 3; d++) x[d] = fmaf(K.dt, vp[d], x[d]);
+        // base cell of the new position in this item's P2G tile
+        int bn[3], tbn[3], inn = 1, cln = 0;
+        float fn[3];
         {
-            // base cell of the new position in this item's P2G tile
-            int c = 0, inn = 1, cln = 0;
+            int c = 0;
 #pragma unroll
             for (int d = 0; d < 3; d++) {
-                int bn;
-                float fn;
-                particle_base(K, x[d], bn, fn, cln);
-                const int tb = bn - org[d];
-                inn &= (tb >= 0) & (tb <= B + 1);
-                c = c * (B + 2) + tb;
+                particle_base(K, x[d], bn[d], fn[d], cln);
+                tbn[d] = bn[d] - org[d];
+                inn &= (tbn[d] >= 0) & (tbn[d] <= B + 1);
+                c = c * (B + 2) + tbn[d];
             }
             if (inn && !cln) atomicAdd(cells + c, 1);
         }
@@ -962,19 +1044,24 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
 #pragma unroll
         for (int d = 0; d < 3; d++) {
             pstore(a.P, ps, X0 + d, jo, x[d]);
-            pstore(a.P, ps, V0 + d, jo, vp[d]);
+            if (!FUSE) pstore(a.P, ps, V0 + d, jo, vp[d]);
         }
         float An[9];
 #pragma unroll
         for (int e = 0; e < 9; e++) {
             An[e] = fmaf(K.mass, C[e], -K.kstress * tau[e]);
-            pstore(a.P, ps, A00 + e, jo, An[e]);
+            if (!FUSE) pstore(a.P, ps, A00 + e, jo, An[e]);
             pstore(a.P, ps, G00 + e, jo, Gn[e]);
         }
-        // a non-finite v or A (the next P2G would scatter it as garbage fixed-point terms)
+        // a non-finite v or A (the next P2G would scatter it as garbage)
         const float sb = scatter_bound(K.mass, K.dx, vp, An);
         bad_any |= !(sb <= 3.0e38f);
         bnd = fmaxf(bnd, sb);
+        if (FUSE) {
+            const bool kept = bn[0] == b[0] && bn[1] == b[1] && bn[2] == b[2];
+            if (inn && !cln && kept && sb * ts.sp <= ts.lim) scatter_packed<B>(t64, tbn, fn, ts, K, vp, An);
+            else p2g_global(a, s, S, x, vp, An, bn, fn, ovf_count(a, a.substep + 1));
+        }
     }
     bnd = wave_max(bnd);
     if ((t & 63) == 0 && bnd > 0.0f) atomicMax((int *)(a.L.ibound + it), __float_as_int(bnd));
@@ -996,6 +1083,7 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
     if (bad_any) atomicOr(a.flags + s, (int)FLAG_NONFINITE);
     if (cl_any) atomicOr(a.flags + s, (int)FLAG_CLAMPED);
     __syncthreads();
+    if (FUSE) flush_packed<B, NT>(a, s, S, org, t64, ts, ovf_count(a, a.substep + 1));
     int mx = 0;
     for (int n = t; n < NC; n += NT) mx = max(mx, cells[n]);
     mx = wave_max_i(mx);
@@ -1011,7 +1099,7 @@ __global__ __launch_bounds__(NT, 4) void k_g2p(StepArgs a)
     __shared__ float vt[3 * T3];
     __shared__ float pf[(NT / 64) * PF_COMPS * 64];
     __shared__ int cells[p2g_cells<B>() + 1];
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(a.L.n_ovf, 0);   // grid update has consumed the list
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(ovf_count(a, a.substep), 0);   // consumed by the grid update
     const int n_items = *a.L.n_items;
     const int G = active_wgs(n_items);
     if ((int)blockIdx.x >= G) return;
@@ -1020,6 +1108,51 @@ __global__ __launch_bounds__(NT, 4) void k_g2p(StepArgs a)
         if (!a.active[item.scene]) continue;
         g2p_item<B, true, PEN, NT>(a, it, item, vt, pf, cells);
     }
+}
+
+// G2P of substep a.substep fused with the P2G of substep a.substep + 1 (one
+// pass over the particles; the grid update sits between two such launches).
+// LDS: the velocity tile, the x / G prefetch, the fixed-point tile and the
+// base-cell counts (77 KB at block edge 8 with 512 threads: two workgroups per CU).
+template <int B, bool PEN, int NT>
+__global__ __launch_bounds__(NT, 4) void k_g2p2g(StepArgs a)
+{
+    constexpr int T = B + 4, T3 = T * T * T;
+    __shared__ float vt[3 * T3];
+    __shared__ float pf[(NT / 64) * PF_COMPS * 64];
+    __shared__ __align__(16) long long t64[2 * T3];
+    __shared__ int cells[p2g_cells<B>() + 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(ovf_count(a, a.substep), 0);   // consumed by the grid update
+    const int n_items = *a.L.n_items;
+    const int G = active_wgs(n_items);
+    if ((int)blockIdx.x >= G) return;
+    for (int it = xcd_remap(blockIdx.x, G); it < n_items; it += G) {
+        Item item = a.L.items[it];
+        if (!a.active[item.scene]) continue;
+        g2p_item<B, true, PEN, NT, true>(a, it, item, vt, pf, cells, t64);
+    }
+}
+
+template <int NT>
+static void launch_g2p2g_nt(const StepArgs &a, int n_wg, hipStream_t st)
+{
+    const bool pen = a.contact != 0;
+    if (a.B == 4) {
+        if (pen) k_g2p2g<4, true, NT><<<n_wg, NT, 0, st>>>(a);
+        else k_g2p2g<4, false, NT><<<n_wg, NT, 0, st>>>(a);
+    } else {
+        if (pen) k_g2p2g<8, true, NT><<<n_wg, NT, 0, st>>>(a);
+        else k_g2p2g<8, false, NT><<<n_wg, NT, 0, st>>>(a);
+    }
+}
+
+hipError_t launch_g2p2g(const StepArgs &a, int n_wg, hipStream_t st)
+{
+    if (a.nt == 512) n_wg /= 2;
+    n_wg = (n_wg + 7) & ~7;
+    if (a.nt == 512) launch_g2p2g_nt<512>(a, n_wg, st);
+    else launch_g2p2g_nt<WG>(a, n_wg, st);
+    return hipGetLastError();
 }
 
 hipError_t launch_p2g(const StepArgs &a, int chunk, int n_wg, hipStream_t st)
@@ -1105,17 +1238,18 @@ __global__ __launch_bounds__(WG, 4) void k_substep_coop(StepArgs a)
     {
         const int lane = threadIdx.x & 63;
         const int ng = *a.L.n_gitems;
-        const int no = min(*a.L.n_ovf, a.L.ovf_cap);
+        const int no = min(*ovf_count(a, a.substep), a.L.ovf_cap);
         const int nw = G * (WG / 64);
         const int w0 = xcd_remap(blockIdx.x, G) * (WG / 64) + (threadIdx.x >> 6);
         for (int w = w0; w < ng + no; w += nw) {
             const int2 e = w < ng ? a.L.gitems[w] : a.L.ovf[w - ng];
+            if (w < ng) publish_colliders(a, w, e.x, lane);
             grid_block<B, false>(a, e.x, e.y, lane, cls[threadIdx.x >> 6]);
             if (w >= ng && lane == 0) a.L.bflag[a.scenes[e.x].bin_off + e.y] = 0;
         }
     }
     grid.sync();
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(a.L.n_ovf, 0);   // the grid update has consumed the list
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(ovf_count(a, a.substep), 0);   // consumed by the grid update
     float *vt = (float *)smem;
     for (int it = xcd_remap(blockIdx.x, G); it < n_items; it += G) {
         const Item item = a.L.items[it];

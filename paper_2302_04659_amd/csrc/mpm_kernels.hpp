@@ -16,7 +16,7 @@ struct StepArgs {
     float *cap;               // optional capture of (m, p) per scene, dense [res^3] x 4, or null
     const long long *cap_off; // per scene offset into cap (in nodes)
     const ColliderDev *cols;
-    void *colnow;             // per collider: pose at the current substep (ColliderNow)
+    void *colnow;             // per collider: pose at the current substep (ColliderNow), left by the grid update
     Lists L;
     int *flags;               // per scene
     int substep;              // substep index within the current call
@@ -34,6 +34,8 @@ struct StepArgs {
     float *wrench;            // per collider (global index): [6] impulse and angular impulse about its centre
                               //   received from the material, summed over grid updates (or null)
     int nt;                   // threads per workgroup of P2G and G2P: 256 or 512
+    int chain;                // 1: a P2G that starts a run of fused substeps (keeps the scatter bounds, stores
+                              //   the per-cell count it takes for the fused G2P's scale)
 };
 
 
@@ -63,6 +65,8 @@ hipError_t launch_sort(const SortArgs &a, hipStream_t st);
 hipError_t launch_p2g(const StepArgs &a, int chunk, int n_wg, hipStream_t st);
 hipError_t launch_grid(const StepArgs &a, int n_wg, hipStream_t st);
 hipError_t launch_g2p(const StepArgs &a, int n_wg, hipStream_t st);
+// G2P of substep a.substep and P2G of substep a.substep + 1 in one launch.
+hipError_t launch_g2p2g(const StepArgs &a, int n_wg, hipStream_t st);
 // One cooperative launch per substep (P2G, grid update, G2P separated by
 // grid-wide barriers); cus = compute units of the device.
 hipError_t launch_persistent(const StepArgs &a, int cus, hipStream_t st);

@@ -72,7 +72,7 @@ struct Lists {
     int *scene_gitem_begin;   // [n_scenes + 1]
     int *bflag;               // per block (all scenes, linear order): 2 static grid block, 1 overflow, 0 none
     int2 *ovf;                // overflow grid blocks (scene, linear block)
-    int *n_ovf;               // [1]
+    int *n_ovf;               // [2] overflow list length, by substep parity
     int ovf_cap;
     float *ibound;            // per item: max over its particles of m|v_c| + 1.5 dx sum_e |A_ce| (P2G scale)
     int *icell;               // per item: most particles sharing a base cell (P2G scale), 0 = not known

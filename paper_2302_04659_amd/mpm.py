@@ -21,9 +21,10 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "mpm.h")
 
 OK, WARN_CLAMPED, WARN_FALLBACK = 0, 1, 2
 ERR_ARG, ERR_HIP, ERR_OOM, ERR_NONFINITE, ERR_STATE = -1, -2, -3, -4, -5
-OPT_SORT_EVERY, OPT_BLOCK, OPT_CHUNK, OPT_PERSISTENT, OPT_GRAPH, OPT_CAPTURE_GRID, OPT_TIMING, OPT_CONTACT, OPT_WG = range(9)
-K_SORT, K_P2G, K_GRID, K_G2P, K_PERSISTENT = range(5)
-KERNEL_CLASSES = ("sort", "p2g", "grid", "g2p", "persistent")
+OPT_SORT_EVERY, OPT_BLOCK, OPT_CHUNK, OPT_PERSISTENT, OPT_GRAPH, OPT_CAPTURE_GRID, OPT_TIMING, OPT_CONTACT, OPT_WG, \
+    OPT_FUSE = range(10)
+K_SORT, K_P2G, K_GRID, K_G2P, K_PERSISTENT, K_G2P2G = range(6)
+KERNEL_CLASSES = ("sort", "p2g", "grid", "g2p", "persistent", "g2p2g")
 MAX_COLLIDERS = 4
 
 
