@@ -265,11 +265,11 @@ MPM_HD void tau_from_M(const float *G, const float *M, float tau[9])
         }
 }
 
-// Hencky elasticity with an optional von Mises return map.  Gt is the trial
-// displacement gradient; Gout receives the projected one (may alias Gt only
-// through a copy made by the caller), tau the Kirchhoff stress of Gout.
+// Hencky elasticity with an optional von Mises return map through the
+// eigen-decomposition of F^T F (any state).  Gt is the trial displacement
+// gradient; Gout receives the projected one, tau the Kirchhoff stress of Gout.
 // Returns 1 if the particle yielded.
-MPM_HD int hencky_update(const float *Gt, const Material &mat, float *Gout, float tau[9], int &bad)
+MPM_HD int hencky_eigen(const float *Gt, const Material &mat, float *Gout, float tau[9], int &bad)
 {
     const float SMIN = 1e-6f;
     Sym3 s;   // C - I = G + G^T + G^T G
@@ -343,6 +343,137 @@ MPM_HD int hencky_update(const float *Gt, const Material &mat, float *Gout, floa
                            V[3 * i + 2] * dk[2] * V[3 * j + 2];
     tau_from_M(Gt, M, tau);
     return yielded;
+}
+
+// Symmetric 3x3 matrices as (00, 11, 22, 01, 02, 12).  The product of two
+// that commute (functions of one symmetric matrix) is symmetric: its six
+// entries.
+MPM_HD void sym_mul(const float a[6], const float b[6], float c[6])
+{
+    c[0] = fmaf(a[0], b[0], fmaf(a[3], b[3], a[4] * b[4]));
+    c[1] = fmaf(a[3], b[3], fmaf(a[1], b[1], a[5] * b[5]));
+    c[2] = fmaf(a[4], b[4], fmaf(a[5], b[5], a[2] * b[2]));
+    c[3] = fmaf(a[0], b[3], fmaf(a[3], b[1], a[4] * b[5]));
+    c[4] = fmaf(a[0], b[4], fmaf(a[3], b[5], a[4] * b[2]));
+    c[5] = fmaf(a[3], b[4], fmaf(a[1], b[5], a[5] * b[2]));
+}
+
+#ifndef MPM_HENCKY_SERIES
+#define MPM_HENCKY_SERIES 1
+#endif
+
+// Hencky stress of a state that stays elastic, without an eigen-decomposition.
+// With b = F F^T and the spatial log strain e = ln(b) / 2, the Kirchhoff
+// stress is tau = 2 mu e + lambda tr(e) I (the eigen path's U diag(d) U^T).
+// ln b = 2 atanh(Z) with Z = (b - I)(b + I)^-1 (functions of b, so they
+// commute), hence e = Z + Z^3/3 + Z^5/5 + Z^7/7 + Z^9/9 + ...; while
+// |b - I|_F <= 0.35 the eigenvalues of Z stay within 0.35 / 1.65 and the first
+// term left out is below 4e-9.  The deviatoric norm of e is that of the
+// principal log strains, so the yield test is the eigen path's.
+// hencky_series_strain: e (symmetric, as sym_mul's six entries) and 1 when
+// the series applies (det F > 1/2, |b - I|_F <= 0.35, no yield), else 0.
+MPM_HD int hencky_series_strain(const float *G, const Material &mat, float e[6])
+{
+    // b - I = G + G^T + G G^T
+    float s[6];
+    s[0] = 2.0f * G[0] + (G[0] * G[0] + G[1] * G[1] + G[2] * G[2]);
+    s[1] = 2.0f * G[4] + (G[3] * G[3] + G[4] * G[4] + G[5] * G[5]);
+    s[2] = 2.0f * G[8] + (G[6] * G[6] + G[7] * G[7] + G[8] * G[8]);
+    s[3] = G[1] + G[3] + (G[0] * G[3] + G[1] * G[4] + G[2] * G[5]);
+    s[4] = G[2] + G[6] + (G[0] * G[6] + G[1] * G[7] + G[2] * G[8]);
+    s[5] = G[5] + G[7] + (G[3] * G[6] + G[4] * G[7] + G[5] * G[8]);
+    const float nb2 = s[0] * s[0] + s[1] * s[1] + s[2] * s[2] + 2.0f * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]);
+    // (b + I)^-1 = (2 I + s)^-1 by its adjugate
+    const float a = 2.0f + s[0], d = 2.0f + s[1], f = 2.0f + s[2];
+    float inv[6];
+    inv[0] = d * f - s[5] * s[5];
+    inv[1] = a * f - s[4] * s[4];
+    inv[2] = a * d - s[3] * s[3];
+    inv[3] = s[4] * s[5] - s[3] * f;
+    inv[4] = s[3] * s[5] - s[4] * d;
+    inv[5] = s[3] * s[4] - a * s[5];
+    const float idet = frcp(a * inv[0] + s[3] * inv[3] + s[4] * inv[4]);
+#pragma unroll
+    for (int k = 0; k < 6; k++) inv[k] *= idet;
+    float z[6], z2[6], p[6], q[6];
+    sym_mul(s, inv, z);
+    sym_mul(z, z, z2);
+    // p = I + z2/3 + z2^2/5 + z2^3/7 + z2^4/9 (Horner in z2)
+#pragma unroll
+    for (int k = 0; k < 6; k++) p[k] = z2[k] * (1.0f / 9.0f) + (k < 3 ? 1.0f / 7.0f : 0.0f);
+    sym_mul(z2, p, q);
+#pragma unroll
+    for (int k = 0; k < 6; k++) p[k] = q[k] + (k < 3 ? 1.0f / 5.0f : 0.0f);
+    sym_mul(z2, p, q);
+#pragma unroll
+    for (int k = 0; k < 6; k++) p[k] = q[k] + (k < 3 ? 1.0f / 3.0f : 0.0f);
+    sym_mul(z2, p, q);
+#pragma unroll
+    for (int k = 0; k < 6; k++) p[k] = q[k] + (k < 3 ? 1.0f : 0.0f);
+    sym_mul(z, p, e);
+    const float mean = (e[0] + e[1] + e[2]) * (1.0f / 3.0f);
+    const float d0 = e[0] - mean, d1 = e[1] - mean, d2 = e[2] - mean;
+    const float nd2 = d0 * d0 + d1 * d1 + d2 * d2 + 2.0f * (e[3] * e[3] + e[4] * e[4] + e[5] * e[5]);
+    return nb2 <= 0.1225f && det_minus_one(G) > -0.5f && !(mat.plastic && nd2 > mat.yield_eps * mat.yield_eps);
+}
+
+// tau = 2 mu e + lambda tr(e) I.
+MPM_HD void hencky_tau_of_strain(const float e[6], const Material &mat, float tau[9])
+{
+    const float tm = 2.0f * mat.mu, tl = mat.la * (e[0] + e[1] + e[2]);
+    tau[0] = fmaf(tm, e[0], tl);
+    tau[4] = fmaf(tm, e[1], tl);
+    tau[8] = fmaf(tm, e[2], tl);
+    tau[1] = tau[3] = tm * e[3];
+    tau[2] = tau[6] = tm * e[4];
+    tau[5] = tau[7] = tm * e[5];
+}
+
+// The series path of one state (host tests): 1 and tau if it applies.
+MPM_HD int hencky_elastic_series(const float *G, const Material &mat, float *Gout, float tau[9])
+{
+    float e[6];
+    if (!hencky_series_strain(G, mat, e)) return 0;
+    hencky_tau_of_strain(e, mat, tau);
+#pragma unroll
+    for (int i = 0; i < 9; i++) Gout[i] = G[i];
+    return 1;
+}
+
+// Hencky elasticity with an optional von Mises return map.  Gt is the trial
+// displacement gradient; Gout receives the projected one (may alias Gt only
+// through a copy made by the caller), tau the Kirchhoff stress of Gout.
+// Returns 1 if the particle yielded.  States near the identity that stay
+// elastic take the series above, on the GPU when every lane of the wave
+// qualifies (one path per wave); the rest the eigen-decomposition of F^T F.
+MPM_HD int hencky_update(const float *Gt, const Material &mat, float *Gout, float tau[9], int &bad)
+{
+#if MPM_HENCKY_SERIES
+    float e[6];
+    int ok = hencky_series_strain(Gt, mat, e);
+#if defined(__HIP_DEVICE_COMPILE__)
+    ok = __ballot(ok) == __ballot(1);
+#endif
+    // both paths fill the same locals, written out once (stores of the two
+    // branches merged into one would keep the arrays out of registers)
+    float tv[9], gv[9];
+    int yielded = 0;
+    if (ok) {
+        hencky_tau_of_strain(e, mat, tv);
+#pragma unroll
+        for (int i = 0; i < 9; i++) gv[i] = Gt[i];
+    } else {
+        yielded = hencky_eigen(Gt, mat, gv, tv, bad);
+    }
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+        tau[i] = tv[i];
+        Gout[i] = gv[i];
+    }
+    return yielded;
+#else
+    return hencky_eigen(Gt, mat, Gout, tau, bad);
+#endif
 }
 
 // Weakly compressible fluid: Tait pressure p(J) = (K / 7) (J^-7 - 1) with the

@@ -2,6 +2,10 @@
 against the FP64 oracle on random deformation gradients: Hencky stress,
 von Mises return map, neo-Hookean stress and the fluid update.
 
+Hencky states near the identity that stay elastic take a series for the
+spatial log strain (no eigen-decomposition); the rest the eigen path.  Both
+are held to the oracle, and to each other where both apply.
+
 Bars (relative Frobenius error against the oracle; FP32 arithmetic):
   * stresses: 2e-5; the fluid's stress follows J - 1, which an FP32
     determinant of unit-size entries carries with an absolute error of a few
@@ -33,6 +37,7 @@ def hostmath():
     L = ct.CDLL(LIB)
     vp = ct.c_void_p
     L.host_material.argtypes = [vp, ct.c_int, ct.c_int, ct.c_int, ct.c_float, ct.c_float, ct.c_float, vp, vp, vp]
+    L.host_hencky_paths.argtypes = [vp, ct.c_int, ct.c_int, ct.c_float, ct.c_float, ct.c_float, vp, vp, vp]
     return L
 
 
@@ -61,10 +66,15 @@ def _rot(rng):
                      [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
 
 
-def _random_F(rng, n, strain):
+def _random_F(rng, n, strain, rotate=True):
+    """Stretches exp(+-strain) along random axes, then a random rotation
+    (rotate = False: a pure stretch, F = Q diag Q^T, whose small strains FP32
+    carries at full relative precision, as the state F - I of a particle
+    that does not rotate)."""
     F = np.empty((n, 3, 3))
     for p in range(n):
-        F[p] = _rot(rng) @ np.diag(np.exp(rng.uniform(-strain, strain, 3))) @ _rot(rng)
+        Q = _rot(rng)
+        F[p] = (_rot(rng) if rotate else Q.T) @ np.diag(np.exp(rng.uniform(-strain, strain, 3))) @ Q
     return F.astype(np.float32)
 
 
@@ -82,10 +92,13 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-@pytest.mark.parametrize("strain", [0.1, 0.3])
-def test_hencky_stress(hostmath, orc, strain):
+@pytest.mark.parametrize("strain,rotate", [(0.003, False), (0.03, False), (0.1, True), (0.3, True)])
+def test_hencky_stress(hostmath, orc, strain, rotate):
+    """Small strains as pure stretches: with a rotation, F's FP32 entries of
+    size 1 carry the strain only to a few ulp of 1, a relative error of
+    ~1e-4 at strain 3e-3 for any FP32 method."""
     rng = np.random.default_rng(7)
-    F = _random_F(rng, 400, strain)
+    F = _random_F(rng, 400, strain, rotate)
     elastic = _Mat(1, sy=0.0)            # no yield: the stress of F itself
     Fo, tau, bad = _host(hostmath, F, 1, 0, elastic)
     assert not bad.any()
@@ -145,3 +158,34 @@ def test_fluid_update(hostmath, orc):
         wt = max(wt, float(np.linalg.norm(tau[p] - ref) / (2e-5 * np.linalg.norm(ref) + floor)))
     print("fluid: worst F", wf, "worst tau error / bar", wt)
     assert wf <= 2e-6 and wt <= 1.0
+
+
+def test_hencky_series_and_eigen_paths(hostmath, orc):
+    """States spread over the series' range and past it (principal log
+    strains up to 0.2): the series takes exactly the states with
+    |F F^T - I|_F <= 0.35 and det F > 1/2 that do not yield, and there its
+    stress matches both the eigen path and the oracle; with plasticity it
+    declines every state the oracle's return map projects."""
+    rng = np.random.default_rng(23)
+    F = _random_F(rng, 600, 0.2)
+    n = len(F)
+    for plastic, mat in ((0, _Mat(1, sy=0.0)), (1, _Mat(1, sy=300.0))):
+        ts = np.zeros_like(F)
+        te = np.zeros_like(F)
+        applied = np.zeros(n, np.int32)
+        hostmath.host_hencky_paths(F.ctypes.data, n, plastic, mat.mu, mat.la,
+                                   mat.yield_eps if plastic else np.inf, ts.ctypes.data, te.ctypes.data,
+                                   applied.ctypes.data)
+        F64 = F.astype(np.float64)
+        b = np.einsum("nij,nkj->nik", F64, F64) - np.eye(3)
+        near = (np.linalg.norm(b.reshape(n, 9), axis=1) <= 0.35 - 1e-4) & (np.linalg.det(F64) > 0.5)
+        far = np.linalg.norm(b.reshape(n, 9), axis=1) > 0.35 + 1e-4
+        yielded = np.array([orc.return_map(mat, F64[p])[1] for p in range(n)]) if plastic else np.zeros(n, bool)
+        assert not applied[far].any()
+        assert applied[near & ~yielded].all()
+        assert not applied[yielded].any()
+        ws = max(_rel(ts[p], orc.stress(mat, F64[p])) for p in np.flatnonzero(applied))
+        we = max(_rel(ts[p], te[p]) for p in np.flatnonzero(applied))
+        print("plastic", plastic, "series took", int(applied.sum()), "of", n, "worst vs oracle", ws, "vs eigen", we)
+        assert (0.2 * n if not plastic else 30) <= applied.sum() <= 0.9 * n
+        assert ws <= 2e-5 and we <= 2e-5
