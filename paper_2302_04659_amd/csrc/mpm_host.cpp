@@ -435,7 +435,9 @@ mpm_status queue_plain(mpm_ctx ctx, int n)
         if (ctx->persistent && !ctx->capture) {
             StepArgs a = step_args(ctx, i);
             KTimer kt(ctx, MPM_K_PERSISTENT);
-            HIPCHK(launch_persistent(a, ctx->cus, ctx->stream));
+            // about one work item per workgroup: the grid-wide barriers cost per workgroup
+            const long long per_cu = ((long long)ctx->N + (long long)ctx->CH * ctx->cus - 1) / ((long long)ctx->CH * ctx->cus);
+            HIPCHK(launch_persistent(a, ctx->cus, (int)std::min<long long>(per_cu, 64), ctx->stream));
             ctx->since_sort++;
             ctx->cnt[MPM_CNT_SUBSTEPS]++;
             ctx->cnt[MPM_CNT_HOST_SUBSTEPS]++;

