@@ -598,12 +598,20 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile,
 
     const TileScale ts = tile_scale(K, wsum, bmax);
 
-    for (int base = 0; base < item.count; base += NT) {
-        const int li = base + t;
-        if (li >= item.count) break;
+    // the next particle's state is loaded while the current one scatters
+    float xn[3], vn[3], An[9];
+    if (t < item.count) load_particle_xvA(a, item.start + t, xn, vn, An);
+    for (int li = t; li < item.count; li += NT) {
         float x[3], v[3], A[9], f[3];
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            x[d] = xn[d];
+            v[d] = vn[d];
+        }
+#pragma unroll
+        for (int e = 0; e < 9; e++) A[e] = An[e];
+        if (li + NT < item.count) load_particle_xvA(a, item.start + li + NT, xn, vn, An);
         int bp[3];
-        load_particle_xvA(a, item.start + li, x, v, A);
         int cl = 0, in = 1;
 #pragma unroll
         for (int d = 0; d < 3; d++) {
@@ -625,7 +633,7 @@ __device__ void p2g_item(const StepArgs &a, int it, const Item &item, int *tile,
 }
 
 template <int B, int NT>
-__global__ __launch_bounds__(NT) void k_p2g(StepArgs a)
+__global__ __launch_bounds__(NT, 5) void k_p2g(StepArgs a)
 {
     constexpr int T = B + 4, T3 = T * T * T;
     __shared__ __align__(16) int tile[4 * T3];
