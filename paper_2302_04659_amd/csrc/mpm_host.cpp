@@ -301,23 +301,31 @@ hipEvent_t take_event(mpm_ctx ctx)
     return e;
 }
 
-// Brackets one kernel launch with events when timing is on.
+// Times one launch when timing is on: a single substep kernel (P2G, grid,
+// G2P, G2P2G) through events the runtime records at the kernel's own start
+// and end; the sort (several kernels) and the cooperative substep through
+// events recorded on the stream around them.
 struct KTimer {
     mpm_ctx ctx;
     int cls;
+    bool own;
     hipEvent_t a = nullptr, b = nullptr;
-    KTimer(mpm_ctx c, int k) : ctx(c), cls(k)
+    KTimer(mpm_ctx c, int k) : ctx(c), cls(k), own(k == MPM_K_SORT || k == MPM_K_PERSISTENT)
     {
         if (ctx->timing) {
             a = take_event(ctx);
             b = take_event(ctx);
-            if (a) (void)hipEventRecord(a, ctx->stream);
+            if (a && b) {
+                if (own) (void)hipEventRecord(a, ctx->stream);
+                else time_next_launch(a, b);
+            }
         }
     }
     ~KTimer()
     {
         if (ctx->timing && a && b) {
-            (void)hipEventRecord(b, ctx->stream);
+            if (own) (void)hipEventRecord(b, ctx->stream);
+            else time_next_launch(nullptr, nullptr);   // the launch took them (or failed before)
             ctx->ev_pending.push_back({cls, {a, b}});
         }
     }

@@ -18,8 +18,30 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include "mpm_device.hpp"
+#include <hip/hip_ext.h>
 
 namespace mpm {
+
+// Timing of the substep kernels: events handed in by time_next_launch are
+// recorded by the runtime at the start and the end of the next substep
+// kernel launched on this thread (hipExtLaunchKernelGGL), so they time the
+// kernel itself rather than the queue around it.
+static thread_local hipEvent_t t_ev[2] = {nullptr, nullptr};
+
+void time_next_launch(hipEvent_t start, hipEvent_t stop)
+{
+    t_ev[0] = start;
+    t_ev[1] = stop;
+}
+
+template <typename... KArgs, typename... Args>
+static void launch_timed(void (*kernel)(KArgs...), int n_wg, int nt, hipStream_t st, Args... args)
+{
+    hipEvent_t a = t_ev[0], b = t_ev[1];
+    t_ev[0] = t_ev[1] = nullptr;
+    if (a && b) hipExtLaunchKernelGGL(kernel, dim3(n_wg), dim3(nt), 0, st, a, b, 0, args...);
+    else kernel<<<n_wg, nt, 0, st>>>(args...);
+}
 
 // ====================================================================== sort
 // Runs of equal keys in consecutive lanes (the particles are nearly sorted
@@ -1146,11 +1168,11 @@ static void launch_g2p2g_nt(const StepArgs &a, int n_wg, hipStream_t st)
 {
     const bool pen = a.contact != 0;
     if (a.B == 4) {
-        if (pen) k_g2p2g<4, true, NT><<<n_wg, NT, 0, st>>>(a);
-        else k_g2p2g<4, false, NT><<<n_wg, NT, 0, st>>>(a);
+        if (pen) launch_timed(k_g2p2g<4, true, NT>, n_wg, NT, st, a);
+        else launch_timed(k_g2p2g<4, false, NT>, n_wg, NT, st, a);
     } else {
-        if (pen) k_g2p2g<8, true, NT><<<n_wg, NT, 0, st>>>(a);
-        else k_g2p2g<8, false, NT><<<n_wg, NT, 0, st>>>(a);
+        if (pen) launch_timed(k_g2p2g<8, true, NT>, n_wg, NT, st, a);
+        else launch_timed(k_g2p2g<8, false, NT>, n_wg, NT, st, a);
     }
 }
 
@@ -1169,11 +1191,11 @@ hipError_t launch_p2g(const StepArgs &a, int chunk, int n_wg, hipStream_t st)
     if (a.nt == 512) n_wg /= 2;   // the same threads in workgroups of twice the size
     n_wg = (n_wg + 7) & ~7;
     if (a.nt == 512) {
-        if (a.B == 4) k_p2g<4, 512><<<n_wg, 512, 0, st>>>(a);
-        else k_p2g<8, 512><<<n_wg, 512, 0, st>>>(a);
+        if (a.B == 4) launch_timed(k_p2g<4, 512>, n_wg, 512, st, a);
+        else launch_timed(k_p2g<8, 512>, n_wg, 512, st, a);
     } else {
-        if (a.B == 4) k_p2g<4, WG><<<n_wg, WG, 0, st>>>(a);
-        else k_p2g<8, WG><<<n_wg, WG, 0, st>>>(a);
+        if (a.B == 4) launch_timed(k_p2g<4, WG>, n_wg, WG, st, a);
+        else launch_timed(k_p2g<8, WG>, n_wg, WG, st, a);
     }
     return hipGetLastError();
 }
@@ -1183,11 +1205,11 @@ hipError_t launch_grid(const StepArgs &a, int n_wg, hipStream_t st)
     n_wg = (n_wg + 7) & ~7;
     const bool extra = a.cap || a.dense;
     if (a.B == 4) {
-        if (extra) k_grid<4, true><<<n_wg, WG, 0, st>>>(a);
-        else k_grid<4, false><<<n_wg, WG, 0, st>>>(a);
+        if (extra) launch_timed(k_grid<4, true>, n_wg, WG, st, a);
+        else launch_timed(k_grid<4, false>, n_wg, WG, st, a);
     } else {
-        if (extra) k_grid<8, true><<<n_wg, WG, 0, st>>>(a);
-        else k_grid<8, false><<<n_wg, WG, 0, st>>>(a);
+        if (extra) launch_timed(k_grid<8, true>, n_wg, WG, st, a);
+        else launch_timed(k_grid<8, false>, n_wg, WG, st, a);
     }
     return hipGetLastError();
 }
@@ -1197,11 +1219,11 @@ static void launch_g2p_nt(const StepArgs &a, int n_wg, hipStream_t st)
 {
     const bool pen = a.contact != 0;
     if (a.B == 4) {
-        if (pen) k_g2p<4, true, NT><<<n_wg, NT, 0, st>>>(a);
-        else k_g2p<4, false, NT><<<n_wg, NT, 0, st>>>(a);
+        if (pen) launch_timed(k_g2p<4, true, NT>, n_wg, NT, st, a);
+        else launch_timed(k_g2p<4, false, NT>, n_wg, NT, st, a);
     } else {
-        if (pen) k_g2p<8, true, NT><<<n_wg, NT, 0, st>>>(a);
-        else k_g2p<8, false, NT><<<n_wg, NT, 0, st>>>(a);
+        if (pen) launch_timed(k_g2p<8, true, NT>, n_wg, NT, st, a);
+        else launch_timed(k_g2p<8, false, NT>, n_wg, NT, st, a);
     }
 }
 

@@ -62,6 +62,9 @@ struct SortArgs {
 };
 
 hipError_t launch_sort(const SortArgs &a, hipStream_t st);
+// The next P2G / grid / G2P / G2P2G launch on this thread records start and
+// stop into these events at the kernel's own start and end.
+void time_next_launch(hipEvent_t start, hipEvent_t stop);
 hipError_t launch_p2g(const StepArgs &a, int chunk, int n_wg, hipStream_t st);
 hipError_t launch_grid(const StepArgs &a, int n_wg, hipStream_t st);
 hipError_t launch_g2p(const StepArgs &a, int n_wg, hipStream_t st);
