@@ -141,7 +141,7 @@ def main():
     ap.add_argument("--cpu-scenes-1t", type=int, default=8)
     ap.add_argument("--cpu-substeps-1t", type=int, default=25)
     ap.add_argument("--train-steps", type=int, default=12000, help="surrogate: training steps")
-    ap.add_argument("--train-seeds", type=int, default=128, help="surrogate: cfg2 rollouts generated for training")
+    ap.add_argument("--train-seeds", type=int, default=2000, help="surrogate: cfg2 rollouts generated for training")
     ap.add_argument("--train-blocks", type=int, default=20, help="surrogate: control steps per training rollout")
     ap.add_argument("--eval-scenes", type=int, default=256, help="surrogate: held-out scenes timed")
     ap.add_argument("--error-scenes", type=int, default=16, help="surrogate: held-out scenes judged by the oracle")

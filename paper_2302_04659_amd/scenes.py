@@ -7,7 +7,7 @@ oracle read the same float32 arrays produced here, and each computes the
 method on its own.
 
 The scenes stand in for the paper's soft-body tasks (Pinch, Write, Fill and
-the rest, Sec. 2.1 and App. C.4), whose assets are not available.  They use the
+the rest, Sec. 2.1 and App. C.5), whose assets are not available.  They use the
 paper's parameter ranges (App. D.3, Table "tab:mpm_param": about 8 particles
 per cell, Poisson ratio 0.3) and primitive box / capsule colliders (Sec. 3,
 "Rigid-soft Coupling").  Collider poses and velocities are handed over once
