@@ -329,16 +329,22 @@ __device__ __forceinline__ void conv_store(const ConvArgs &a, f4 (&acc)[4][NF], 
 }
 
 // The same tiling on v_mfma_f32_16x16x32_bf16 for a multiple of 32 input
-// channels.  K slot 4 h + r of lane group g (= lane / 16) carries channel
-// 16 h + 4 g + r of the 32-channel chunk, for A (halo) and B (packed weights)
-// alike.  The halo holds, per voxel, four 16-byte pairs (channels 4 g .. 4 g + 3
-// and 16 + 4 g .. 16 + 4 g + 3), pair g stored at slot g ^ ((v >> 2) & 3) so
-// that the 16-byte reads of 8 neighbouring x voxels hit distinct banks.  For
-// each (z tap, x tap) a wave reads the six halo rows its four output rows see
-// through the three y taps once.  Staging reads 16 bytes (8 channels) per
-// load; a BF16 output slice goes out through LDS as 16-byte rows (needs the
-// channel stride and offset of x and y to be multiples of 8).
+// channels.  K slot e of lane group g (= lane / 16) carries channel 8 g + e of
+// the 32-channel chunk, for A (halo) and B (packed weights) alike.  The halo
+// holds, per voxel, the chunk's four 16-byte pieces (channels 8 p .. 8 p + 7),
+// piece p stored at slot p ^ ((v >> 2) & 3) so that the 16-byte reads of 8
+// neighbouring x voxels hit distinct banks.  For each (z tap, x tap) a wave
+// reads the six halo rows its four output rows see through the three y taps
+// once.  With 16-byte aligned channel slices (x16) the halo is staged by
+// 16-byte global-to-LDS copies (global_load_lds_dwordx4): each wave
+// instruction fills 64 consecutive slots, lane L slot 64 j + L, so every load
+// of a chunk is in flight at once and no register holds the data; voxels in
+// the padding copy from a zero block.  A BF16 output slice goes out through
+// LDS as 16-byte rows (needs the channel stride and offset of x and y to be
+// multiples of 8).
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+
+__device__ __align__(16) uint16_t g_zero_piece[8];   // 16 zero bytes: the source of padding voxels
 
 template <int NF, int KIND, bool X16>
 __global__ __launch_bounds__(256, 2) void k_conv_lds32(ConvArgs a)
@@ -373,27 +379,35 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds32(ConvArgs a)
     const int kc = a.cin / 32;
     const int g = lane >> 4, i = lane & 15;
     uint2 *h2 = (uint2 *)halo;
-    // staging (X16): thread t loads channels 8 (t & 3) .. + 7 of voxels (t >> 2) + 64 k;
-    // otherwise 4 channels per load, thread t: group t & 7 of voxels (t >> 3) + 32 k
-    const int q = X16 ? (threadIdx.x & 3) : (threadIdx.x & 7);
-    const int gs = X16 ? 2 * (q & 1) : (q & 3), hs = X16 ? (q >> 1) : (q >> 2);
-    const uint16_t *xb = a.x + (long long)bn * a.id * a.ih * a.iw * a.cx + a.x_off + (X16 ? 8 * q : 16 * hs + 4 * gs);
+    const uint16_t *xb = a.x + (long long)bn * a.id * a.ih * a.iw * a.cx + a.x_off;
     for (int c = 0; c < kc; c++) {
-        for (int v = threadIdx.x >> (X16 ? 2 : 3); v < NH; v += (X16 ? 64 : 32)) {
-            const int lx = v % HX, ly = (v / HX) % HY, lz = v / (HX * HY);
-            const int gz = hz0 + lz, gy = hy0 + ly, gx = hx0 + lx;
-            const bool in = gz >= 0 && gy >= 0 && gx >= 0 && gz < a.id && gy < a.ih && gx < a.iw;
-            const long long off = (((long long)gz * a.ih + gy) * a.iw + gx) * a.cx + 32 * c;
-            const int sw = (v >> 2) & 3;
-            if (X16) {
-                uint4 val = make_uint4(0u, 0u, 0u, 0u);
-                if (in) val = *(const uint4 *)(xb + off);
-                h2[v * 8 + 2 * (gs ^ sw) + hs] = make_uint2(val.x, val.y);
-                h2[v * 8 + 2 * ((gs + 1) ^ sw) + hs] = make_uint2(val.z, val.w);
-            } else {
+        if (X16) {
+            typedef __attribute__((address_space(3))) void lds_void;
+            typedef const __attribute__((address_space(1))) void glob_void;
+            for (int j = wv; j * 64 < 4 * NH; j += 4) {
+                const int slot = 64 * j + lane;
+                if (slot < 4 * NH) {
+                    const int v = slot >> 2, p = (slot & 3) ^ ((v >> 2) & 3);
+                    const int lx = v % HX, ly = (v / HX) % HY, lz = v / (HX * HY);
+                    const int gz = hz0 + lz, gy = hy0 + ly, gx = hx0 + lx;
+                    const bool in = gz >= 0 && gy >= 0 && gx >= 0 && gz < a.id && gy < a.ih && gx < a.iw;
+                    const uint16_t *src =
+                        in ? xb + (((long long)gz * a.ih + gy) * a.iw + gx) * a.cx + 32 * c + 8 * p : g_zero_piece;
+                    __builtin_amdgcn_global_load_lds((glob_void *)src, (lds_void *)(halo + 64 * j), 16, 0, 0);
+                }
+            }
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the copies are not tracked by the compiler
+        } else {
+            // 4 channels per load, thread t: channels 4 (t & 7) .. + 3 of voxels (t >> 3) + 32 k
+            const int q = threadIdx.x & 7;
+            for (int v = threadIdx.x >> 3; v < NH; v += 32) {
+                const int lx = v % HX, ly = (v / HX) % HY, lz = v / (HX * HY);
+                const int gz = hz0 + lz, gy = hy0 + ly, gx = hx0 + lx;
+                const bool in = gz >= 0 && gy >= 0 && gx >= 0 && gz < a.id && gy < a.ih && gx < a.iw;
+                const long long off = (((long long)gz * a.ih + gy) * a.iw + gx) * a.cx + 32 * c + 4 * q;
                 uint2 val = make_uint2(0u, 0u);
                 if (in) val = *(const uint2 *)(xb + off);
-                h2[v * 8 + 2 * (gs ^ sw) + hs] = val;
+                h2[v * 8 + 2 * ((q >> 1) ^ ((v >> 2) & 3)) + (q & 1)] = val;
             }
         }
         __syncthreads();
@@ -498,8 +512,8 @@ __global__ __launch_bounds__(256, 2) void k_conv_first(ConvArgs a)
 // weights of the adjoint (dgrad) convolution: taps mirrored, ci <-> co.
 //   k32 = 0: element (((t * KC + c) * NF + n) * 64 + lane) * 4 + r holds
 //            B[k][j], k = 16 c + 4 (lane / 16) + r (16x16x16 fragments);
-//   k32 = 1: element (((t * KC2 + c) * NF + n) * 64 + lane) * 8 + 4 h + r holds
-//            k = 32 c + 16 h + 4 (lane / 16) + r (16x16x32 fragments).
+//   k32 = 1: element (((t * KC2 + c) * NF + n) * 64 + lane) * 8 + e holds
+//            k = 32 c + 8 (lane / 16) + e (16x16x32 fragments).
 //   k32 = 2: the first-layer order (8 input channels, taps folded into K):
 //            element ((c * NF + n) * 64 + lane) * 8 + j holds tap 4 c + lane / 16
 //            (zero for tap 27), channel j.
@@ -530,14 +544,14 @@ __global__ void k_pack(const float *w, int ntap, int cin, int cout, int cin_p, i
             t = (int)(q / KC);
             k = 16 * c + 4 * (lane >> 4) + r;             // input channel of this conv
         } else {
-            const int r = (int)(e & 3), h = (int)((e >> 2) & 1);
+            const int el = (int)(e & 7);
             lane = (int)((e >> 3) & 63);
             long long q = e >> 9;
             n = (int)(q % NF);
             q /= NF;
             const int c = (int)(q % (KC / 2));
             t = (int)(q / (KC / 2));
-            k = 32 * c + 16 * h + 4 * (lane >> 4) + r;
+            k = 32 * c + 8 * (lane >> 4) + el;
         }
         const int j = 16 * n + (lane & 15);              // output channel of this conv
         float v = 0.0f;
