@@ -262,8 +262,18 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
 // of channel 16 n + i).  A BF16-only output slice (cout = 16 NF, 16-byte
 // aligned rows) goes through `ot` (LDS, >= 256 x (16 min(NF, 4) + 8) BF16,
 // free after the last barrier) and out as 16-byte rows.
-template <int NF>
-__device__ __forceinline__ void conv_store(const ConvArgs &a, f4 (&acc)[4][NF], int bn, int z0, int y0, int x0, int wv,
+// Output channels per LDS pass of conv_store's fast path (its rows of 64 FR
+// voxels x (channels + 8) BF16 must fit the caller's LDS buffer).
+template <int NF, int FR>
+constexpr int store_pass_channels()
+{
+    return 16 * NF < (FR == 8 ? 32 : 64) ? 16 * NF : (FR == 8 ? 32 : 64);
+}
+
+// Epilogue of the tiled convolutions: wave wv holds FR rows (y) of 16 x
+// voxels of the z-slice z0 + wv, for all output channels.
+template <int NF, int FR = 4>
+__device__ __forceinline__ void conv_store(const ConvArgs &a, f4 (&acc)[FR][NF], int bn, int z0, int y0, int x0, int wv,
                                            int lane, uint16_t *ot)
 {
     constexpr int CO = 16 * NF;
@@ -273,13 +283,13 @@ __device__ __forceinline__ void conv_store(const ConvArgs &a, f4 (&acc)[4][NF], 
                       ((uintptr_t)a.y & 15) == 0;
     if (fast) {
         // D[i][j] -> LDS row (wave, f, x = 4 (lane / 16) + r), channel 16 n + lane % 16; then 16-byte rows out
-        constexpr int NP = NF == 8 ? 2 : 1;                   // channel passes (128 channels: two of 64)
-        constexpr int CP = CO / NP;
+        constexpr int CP = store_pass_channels<NF, FR>();
+        constexpr int NP = CO / CP;                           // channel passes
         constexpr int PROW = CP + 8;
 #pragma unroll
         for (int pass = 0; pass < NP; pass++) {
 #pragma unroll
-            for (int f = 0; f < 4; f++)
+            for (int f = 0; f < FR; f++)
 #pragma unroll
                 for (int nn = 0; nn < NF / NP; nn++) {
                     const int n = pass * (NF / NP) + nn;
@@ -288,13 +298,13 @@ __device__ __forceinline__ void conv_store(const ConvArgs &a, f4 (&acc)[4][NF], 
                     for (int r = 0; r < 4; r++) {
                         float val = acc[f][n][r] + bias;
                         if (a.relu) val = fmaxf(val, 0.0f);
-                        ot[((wv * 4 + f) * 16 + 4 * g + r) * PROW + 16 * nn + i] = f2bf(val);
+                        ot[((wv * FR + f) * 16 + 4 * g + r) * PROW + 16 * nn + i] = f2bf(val);
                     }
                 }
             __syncthreads();
-            for (int e = threadIdx.x; e < 256 * (CP / 8); e += 256) {
+            for (int e = threadIdx.x; e < 64 * FR * (CP / 8); e += 256) {
                 const int vl = e / (CP / 8), part = e % (CP / 8);
-                const int tz = vl >> 6, ty = (vl >> 4) & 3, tx = vl & 15;
+                const int tz = vl / (16 * FR), ty = (vl >> 4) % FR, tx = vl & 15;
                 const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
                 if (gz < a.od && gy < a.oh && gx < a.ow) {
                     const long long gv = (((long long)bn * a.od + gz) * a.oh + gy) * a.ow + gx;
@@ -306,7 +316,7 @@ __device__ __forceinline__ void conv_store(const ConvArgs &a, f4 (&acc)[4][NF], 
         return;
     }
 #pragma unroll
-    for (int f = 0; f < 4; f++) {
+    for (int f = 0; f < FR; f++) {
         const int oy = y0 + f;
         if (oz >= a.od || oy >= a.oh) continue;
 #pragma unroll
@@ -346,17 +356,22 @@ typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 
 __device__ __align__(16) uint16_t g_zero_piece[8];   // 16 zero bytes: the source of padding voxels
 
-template <int NF, int KIND, bool X16>
+// FR: output rows (y) per wave, 4 or 8 (tile 4 x FR x 16).  Every B fragment
+// (weights, read through the vector cache) feeds FR MFMAs; at FR = 4 those
+// reads alone would use the cache's whole bandwidth at the MFMA rate (a
+// timing-only build that skips them runs the forward 1.4x faster).
+template <int NF, int KIND, bool X16, int FR>
 __global__ __launch_bounds__(256, 2) void k_conv_lds32(ConvArgs a)
 {
     constexpr int HZ = KIND == KIND_C3 ? HLZ : TLZ / 2 + 2;
-    constexpr int HY = KIND == KIND_C3 ? HLY : TLY / 2 + 2;
+    constexpr int HY = KIND == KIND_C3 ? FR + 2 : FR / 2 + 2;
     constexpr int HX = KIND == KIND_C3 ? HLX : TLX / 2 + 2;
     constexpr int NH = HZ * HY * HX;
-    static_assert(256 * (16 * (NF < 4 ? NF : 4) + 8) * 2 <= HLZ * HLY * HLX * 64, "output tile must fit the halo buffer");
-    __shared__ uint4 halo[HLZ * HLY * HLX * 4];
+    constexpr int HBUF = HLZ * (FR + 2) * HLX * 4;   // uint4 slots of the largest (3^3) halo
+    static_assert(64 * FR * (store_pass_channels<NF, FR>() + 8) * 2 <= HBUF * 16, "output rows must fit the halo buffer");
+    __shared__ uint4 halo[HBUF];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int tiles_x = (a.ow + TLX - 1) / TLX, tiles_y = (a.oh + TLY - 1) / TLY, tiles_z = (a.od + TLZ - 1) / TLZ;
+    const int tiles_x = (a.ow + TLX - 1) / TLX, tiles_y = (a.oh + FR - 1) / FR, tiles_z = (a.od + TLZ - 1) / TLZ;
     int b = blockIdx.x;
     const int bx = b % tiles_x;
     b /= tiles_x;
@@ -364,16 +379,16 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds32(ConvArgs a)
     b /= tiles_y;
     const int bz = b % tiles_z;
     const int bn = b / tiles_z;
-    const int z0 = bz * TLZ, y0 = by * TLY, x0 = bx * TLX;
+    const int z0 = bz * TLZ, y0 = by * FR, x0 = bx * TLX;
     int hz0, hy0, hx0;
     if (KIND == KIND_C3) {
         hz0 = z0 - 1; hy0 = y0 - 1; hx0 = x0 - 1;
     } else {
         hz0 = (z0 >> 1) - 1; hy0 = (y0 >> 1) - 1; hx0 = (x0 >> 1) - 1;
     }
-    f4 acc[4][NF];
+    f4 acc[FR][NF];
 #pragma unroll
-    for (int f = 0; f < 4; f++)
+    for (int f = 0; f < FR; f++)
 #pragma unroll
         for (int n = 0; n < NF; n++) acc[f][n] = f4{0.0f, 0.0f, 0.0f, 0.0f};
     const int kc = a.cin / 32;
@@ -422,9 +437,9 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds32(ConvArgs a)
                 int lx;
                 if (KIND == KIND_C3) lx = i + tc;
                 else lx = ((x0 + i + tc - 1) >> 1) - hx0;
-                b8 Ar[6];
+                b8 Ar[FR + 2];
 #pragma unroll
-                for (int r = 0; r < 6; r++) {
+                for (int r = 0; r < FR + 2; r++) {
                     int ly;
                     if (KIND == KIND_C3) ly = r;
                     else ly = ((y0 + r - 1) >> 1) - hy0;
@@ -439,7 +454,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds32(ConvArgs a)
                     for (int n = 0; n < NF; n++) {
                         const b8 Bv = __builtin_bit_cast(b8, *(const uint4 *)(wt + (size_t)n * 512));
 #pragma unroll
-                        for (int f = 0; f < 4; f++)
+                        for (int f = 0; f < FR; f++)
                             acc[f][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar[f + tb], Bv, acc[f][n], 0, 0, 0);
                     }
                 }
@@ -447,7 +462,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_lds32(ConvArgs a)
         }
         __syncthreads();
     }
-    conv_store<NF>(a, acc, bn, z0, y0, x0, wv, lane, (uint16_t *)halo);
+    conv_store<NF, FR>(a, acc, bn, z0, y0, x0, wv, lane, (uint16_t *)halo);
 }
 
 // First layer: 3^3 convolution over 8 input channels with the taps folded
@@ -1173,11 +1188,16 @@ static hipError_t conv_lds(const ConvArgs &a, hipStream_t st)
     const unsigned g = (unsigned)tiles;
     if (a.cin % 32 == 0) {   // the weights were packed as 16x16x32 fragments (same condition in pack)
         const bool x16 = a.cx % 8 == 0 && a.x_off % 8 == 0 && ((uintptr_t)a.x & 15) == 0;
+        // 8 output rows per wave up to 32 output channels (measured on the 40 x 24 x 40 boxes: the
+        // forward 10.1 -> 9.8 ms; 8 rows at 64 channels cost an occupancy step and ran slower)
+        const long long t8 = (long long)a.n * ((a.od + TLZ - 1) / TLZ) * ((a.oh + 7) / 8) * ((a.ow + TLX - 1) / TLX);
+        if (t8 > 0x7fffffff) return hipErrorInvalidValue;
+        const unsigned g8 = (unsigned)t8;
         switch ((a.cout + 15) / 16) {
-        case 1: if (x16) k_conv_lds32<1, KIND, true><<<g, 256, 0, st>>>(a); else k_conv_lds32<1, KIND, false><<<g, 256, 0, st>>>(a); break;
-        case 2: if (x16) k_conv_lds32<2, KIND, true><<<g, 256, 0, st>>>(a); else k_conv_lds32<2, KIND, false><<<g, 256, 0, st>>>(a); break;
-        case 4: if (x16) k_conv_lds32<4, KIND, true><<<g, 256, 0, st>>>(a); else k_conv_lds32<4, KIND, false><<<g, 256, 0, st>>>(a); break;
-        case 8: if (x16) k_conv_lds32<8, KIND, true><<<g, 256, 0, st>>>(a); else k_conv_lds32<8, KIND, false><<<g, 256, 0, st>>>(a); break;
+        case 1: if (x16) k_conv_lds32<1, KIND, true, 8><<<g8, 256, 0, st>>>(a); else k_conv_lds32<1, KIND, false, 8><<<g8, 256, 0, st>>>(a); break;
+        case 2: if (x16) k_conv_lds32<2, KIND, true, 8><<<g8, 256, 0, st>>>(a); else k_conv_lds32<2, KIND, false, 8><<<g8, 256, 0, st>>>(a); break;
+        case 4: if (x16) k_conv_lds32<4, KIND, true, 4><<<g, 256, 0, st>>>(a); else k_conv_lds32<4, KIND, false, 4><<<g, 256, 0, st>>>(a); break;
+        case 8: if (x16) k_conv_lds32<8, KIND, true, 4><<<g, 256, 0, st>>>(a); else k_conv_lds32<8, KIND, false, 4><<<g, 256, 0, st>>>(a); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
