@@ -227,8 +227,8 @@ typedef enum {
                                  * tile; only x and F are stored, and the last substep of the run,
                                  * or of the call, stores v and C too); 0 (default): separate P2G
                                  * and G2P launches.  Same results to FP32 reorder tolerance; the
-                                 * fused launch moves about half the bytes but is slower on MI355X
-                                 * (its LDS atomics and the G2P arithmetic do not overlap). */
+                                 * fused launch does not read the particles a second time
+                                 * (mpm_autotune tries both). */
 } mpm_option;
 
 /* Kernel classes reported by mpm_get_timing (MPM_K_G2P2G: the fused G2P +
@@ -242,9 +242,11 @@ mpm_status mpm_set_option(mpm_ctx ctx, int option, int value);
 mpm_status mpm_get_option(mpm_ctx ctx, int option, int *value);
 
 /* Time the candidate tunings on the live scenes for `substeps` substeps each
- * (at least one re-sort period): every block edge (4, 8) x chunk size (512,
- * 2048, 8192) x sort cadence (10, 25, 50) with 256-thread workgroups, then
- * 512-thread workgroups at the fastest of those; keep the fastest, and
+ * (at least one re-sort period, after one untimed period): every block edge (4, 8) x chunk size (512,
+ * 2048, 8192) x sort cadence (10, 25, 50) x separate or fused launches
+ * (MPM_OPT_FUSE) with 256-thread workgroups, then 512-thread workgroups and
+ * the one-launch substep (MPM_OPT_PERSISTENT) at the fastest of those; keep
+ * the fastest, and
  * restore the particle state, the collider table and the collider wrench
  * sums afterwards.  The result is cached per (GPU architecture, grid
  * resolutions, particle-count bucket, one or many scenes), for the process
@@ -252,7 +254,8 @@ mpm_status mpm_get_option(mpm_ctx ctx, int option, int *value);
  * $XDG_CACHE_HOME/mpm_mi355x_autotune.txt, else
  * $HOME/.cache/mpm_mi355x_autotune.txt; unreadable or unwritable files are
  * ignored): a cached tuning is applied without trials.  Writes a one-line
- * JSON report to report[0 .. report_len) when report is non-NULL. */
+ * JSON report to report[0 .. report_len) when report is non-NULL (cut at
+ * report_len - 1 bytes; every trial is listed, 8 KB hold them all). */
 mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_len);
 
 /* Accumulated GPU time (ms, from HIP events recorded on the context stream

@@ -227,6 +227,12 @@ __device__ __forceinline__ int wave_max_i(int v)
     return v;
 }
 
+__device__ __forceinline__ unsigned wave_or(unsigned v)
+{
+    for (int o = 32; o > 0; o >>= 1) v |= (unsigned)__shfl_xor((int)v, o, 64);
+    return v;
+}
+
 // Sum over the 64 lanes, returned on every lane (all lanes must be active).
 // An inclusive scan with DPP moves (VALU, no LDS round trip): shifts by 1, 2, 4
 // and 8 inside each row of 16 lanes (lanes shifted in from outside the row read

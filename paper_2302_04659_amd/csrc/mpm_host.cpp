@@ -1430,8 +1430,8 @@ mpm_status mpm_sur_targets(mpm_ctx ctx, const float *g0, const float *g1, float 
 
 // Tuning results, keyed by device architecture, grid resolutions and
 // particle-count bucket: kept for the life of the process and in a text file
-// (one "key block chunk sort_every wg persistent" line per tuning, the last one for a key
-// wins), so that a later process on the same kind of workload starts tuned.
+// (one "key block chunk sort_every wg persistent fuse" line per tuning, the last one
+// for a key wins), so that a later process on the same kind of workload starts tuned.
 static std::map<std::string, std::vector<int>> g_tune_cache;
 
 static std::string tune_key(mpm_ctx ctx)
@@ -1446,7 +1446,7 @@ static std::string tune_key(mpm_ctx ctx)
     int bucket = 0;
     while ((1LL << bucket) < (long long)ctx->N) bucket++;
     char buf[128];
-    std::snprintf(buf, sizeof buf, "|res%d|n2^%d|s%d", resmask, bucket, ctx->n_scenes > 1 ? 1 : 0);
+    std::snprintf(buf, sizeof buf, "|res%d|n2^%d|s%d|t2", resmask, bucket, ctx->n_scenes > 1 ? 1 : 0);
     return k + buf;
 }
 
@@ -1465,13 +1465,14 @@ static bool tune_file_lookup(const std::string &path, const std::string &key, st
     if (path.empty()) return false;
     std::FILE *f = std::fopen(path.c_str(), "r");
     if (!f) return false;
-    char k[256];
-    int v[5];
+    char line[512], k[256];
+    int v[6];
     bool found = false;
-    while (std::fscanf(f, "%255s %d %d %d %d %d", k, &v[0], &v[1], &v[2], &v[3], &v[4]) == 6) {
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::sscanf(line, "%255s %d %d %d %d %d %d", k, &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) != 7) continue;
         if (key == k && (v[0] == 4 || v[0] == 8) && v[1] >= 64 && v[1] <= 8192 && v[2] >= 1 &&
-            (v[3] == 256 || v[3] == 512) && (v[4] == 0 || v[4] == 1)) {
-            best.assign(v, v + 5);
+            (v[3] == 256 || v[3] == 512) && (v[4] == 0 || v[4] == 1) && (v[5] == 0 || v[5] == 1)) {
+            best.assign(v, v + 6);
             found = true;
         }
     }
@@ -1485,7 +1486,7 @@ static void tune_file_store(const std::string &path, const std::string &key, con
     std::string dir = path.substr(0, path.find_last_of('/'));
     if (!dir.empty() && dir != path) (void)mkdir(dir.c_str(), 0755);
     if (std::FILE *f = std::fopen(path.c_str(), "a")) {
-        std::fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), best[0], best[1], best[2], best[3], best[4]);
+        std::fprintf(f, "%s %d %d %d %d %d %d\n", key.c_str(), best[0], best[1], best[2], best[3], best[4], best[5]);
         std::fclose(f);
     }
 }
@@ -1541,7 +1542,7 @@ mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_l
         HIPCHK(hipMemcpyAsync(wsnap.data(), ctx->d_wrench, sizeof(float) * wsnap.size(), hipMemcpyDeviceToHost,
                               ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
-        const int saved[5] = {ctx->B, ctx->CH, ctx->sort_every, ctx->nt, ctx->persistent};
+        const int saved[6] = {ctx->B, ctx->CH, ctx->sort_every, ctx->nt, ctx->persistent, ctx->fuse};
         ctx->persistent = 0;
         const int saved_timing = ctx->timing, saved_graph = ctx->graph;
         ctx->timing = 0;
@@ -1551,12 +1552,13 @@ mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_l
         float best_ms = 1e30f;
         rep = "{\"cached\": false, \"trials\": [";
         bool first = true;
-        // one trial: ms per substep of (B, CH, SE, WG) on the snapshot, the sort included
-        auto trial = [&](int B, int CH, int SE, int NT, mpm_status &st2) -> float {
+        // one trial: ms per substep of (B, CH, SE, WG, fused launches) on the snapshot, the sort included
+        auto trial = [&](int B, int CH, int SE, int NT, int FU, mpm_status &st2) -> float {
             if (B != ctx->B && (st2 = set_block(ctx, B)) != MPM_OK) return -1.0f;
             ctx->CH = CH;
             ctx->sort_every = SE;
             ctx->nt = NT;
+            ctx->fuse = FU;
             if ((st2 = mpm_set_state(ctx, -1, sx, sv, sC, sF, 1)) != MPM_OK) return -1.0f;
             if (!ctx->h_cols.empty() &&
                 hipMemcpyAsync(ctx->d_cols, ts.csnap, sizeof(ColliderDev) * ctx->h_cols.size(),
@@ -1564,8 +1566,11 @@ mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_l
                 st2 = MPM_ERR_HIP;
                 return -1.0f;
             }
-            // the sort right after set_state is part of every trial; time enough substeps
-            // that later re-sorts are amortised as in use
+            // one re-sort period untimed first (a state at rest speeds up over its first
+            // substeps, which the fused launches' tile scale, taken from the previous
+            // substep's bound, lags behind), then enough substeps that re-sorts are
+            // amortised as in use, a re-sort included
+            if ((st2 = queue_plain(ctx, SE)) != MPM_OK) return -1.0f;
             const int n = std::max(substeps, SE);
             float ms = 0.0f;
             if (hipEventRecord(ts.e0, ctx->stream) != hipSuccess) { st2 = MPM_ERR_HIP; return -1.0f; }
@@ -1579,13 +1584,13 @@ mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_l
             char buf[192];
             std::snprintf(buf, sizeof buf,
                           "%s{\"block\": %d, \"chunk\": %d, \"sort_every\": %d, \"wg\": %d, \"persistent\": %d, "
-                          "\"ms_per_substep\": %.5f}",
-                          first ? "" : ", ", B, CH, SE, NT, ctx->persistent, per);
+                          "\"fuse\": %d, \"ms_per_substep\": %.5f}",
+                          first ? "" : ", ", B, CH, SE, NT, ctx->persistent, FU, per);
             rep += buf;
             first = false;
             if (per < best_ms) {
                 best_ms = per;
-                best = {B, CH, SE, NT};
+                best = {B, CH, SE, NT, ctx->persistent, FU};
             }
             st2 = MPM_OK;
             return per;
@@ -1593,26 +1598,25 @@ mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_l
         const int Bs[2] = {4, 8}, CHs[3] = {512, 2048, 8192}, SEs[3] = {10, 25, 50};
         for (int B : Bs)
             for (int CH : CHs)
-                for (int SE : SEs) {
-                    trial(B, CH, SE, 256, st);
-                    if (st != MPM_OK) return st;
-                }
-        // the workgroup size at the best (block, chunk, cadence)
+                for (int SE : SEs)
+                    for (int FU = 0; FU < 2; FU++) {
+                        trial(B, CH, SE, 256, FU, st);
+                        if (st != MPM_OK) return st;
+                    }
+        // the workgroup size at the best (block, chunk, cadence, launches)
         {
             const std::vector<int> b256 = best;
-            trial(b256[0], b256[1], b256[2], 512, st);
+            trial(b256[0], b256[1], b256[2], 512, b256[5], st);
             if (st != MPM_OK) return st;
         }
         // one cooperative launch per substep at the best so far
         {
             const std::vector<int> b = best;
             ctx->persistent = 1;
-            trial(b[0], b[1], b[2], b[3], st);
+            trial(b[0], b[1], b[2], b[3], 0, st);
             ctx->persistent = 0;
             if (st != MPM_OK) return st;
-            if (best != b) best.push_back(1);   // the launch mode that won
         }
-        if (best.size() == 4) best.push_back(0);
         rep += "]";
         // restore the state the caller had
         if (ctx->B != saved[0] && (st = set_block(ctx, saved[0])) != MPM_OK) return st;
@@ -1620,6 +1624,7 @@ mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_l
         ctx->sort_every = saved[2];
         ctx->nt = saved[3];
         ctx->persistent = saved[4];
+        ctx->fuse = saved[5];
         if ((st = mpm_set_state(ctx, -1, sx, sv, sC, sF, 1)) != MPM_OK) return st;
         if (!ctx->h_cols.empty())
             HIPCHK(hipMemcpyAsync(ctx->d_cols, ts.csnap, sizeof(ColliderDev) * ctx->h_cols.size(),
@@ -1638,13 +1643,14 @@ mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_l
     ctx->sort_every = best[2];
     ctx->nt = best[3];
     ctx->persistent = best[4];
+    ctx->fuse = best[5];
     ctx->since_sort = 1 << 30;
     clear_graphs(ctx);
     char buf[256];
     std::snprintf(buf, sizeof buf,
                   ", \"key\": \"%s\", \"best\": {\"block\": %d, \"chunk\": %d, \"sort_every\": %d, \"wg\": %d, "
-                  "\"persistent\": %d}}",
-                  key.c_str(), best[0], best[1], best[2], best[3], best[4]);
+                  "\"persistent\": %d, \"fuse\": %d}}",
+                  key.c_str(), best[0], best[1], best[2], best[3], best[4], best[5]);
     rep += buf;
     if (report && report_len) {
         std::strncpy(report, rep.c_str(), report_len - 1);

@@ -371,6 +371,7 @@ class Sim:
         return {"substeps": int(c[0]), "graph_launches": int(c[1]), "host_substeps": int(c[2]), "sorts": int(c[3])}
 
     def autotune(self, substeps: int = 10) -> str:
-        buf = ct.create_string_buffer(4096)
-        self._check(self.L.mpm_autotune(self.h, int(substeps), buf, 4096), "autotune")
+        n = 1 << 15                # the report lists every trial (about 120 bytes each)
+        buf = ct.create_string_buffer(n)
+        self._check(self.L.mpm_autotune(self.h, int(substeps), buf, n), "autotune")
         return buf.value.decode()

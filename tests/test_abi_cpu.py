@@ -110,7 +110,7 @@ def test_traffic_summaries_match_current_kernel_sources():
     spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
     bench = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(bench)
-    for kernel, wl in [(k, w) for w in ("cfg3", "cfg4") for k in ("g2p", "p2g", "grid")]:
+    for kernel, wl in [(k, w) for w in ("cfg3", "cfg4") for k in ("g2p2g", "g2p", "p2g", "grid")]:
         total = bench.kernel_traffic(kernel, wl)
         assert total is not None, f"{kernel} {wl}: summary missing or taken on other kernel sources"
         vals = {}

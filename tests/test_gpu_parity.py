@@ -359,8 +359,8 @@ def test_graph_replays_match_eager(mpm, orc):
 
 
 def test_autotune_keeps_state(mpm, tmp_path, monkeypatch):
-    """The autotuner's trials (block edge x chunk x sort cadence, then the
-    workgroup size) leave the particle state as it was; the tuning is cached
+    """The autotuner's trials (block edge x chunk x sort cadence x separate or
+    fused launches, then the workgroup size) leave the particle state as it was; the tuning is cached
     for the process and in a file, so that a second process on the same
     kind of workload gets it without trials."""
     import json
@@ -379,12 +379,14 @@ def test_autotune_keeps_state(mpm, tmp_path, monkeypatch):
     r = json.loads(rep)
     assert not r["cached"]
     assert {t["wg"] for t in r["trials"]} == {256, 512}
+    assert {t["fuse"] for t in r["trials"]} == {0, 1} and r["best"]["fuse"] in (0, 1)
     assert r["best"]["block"] in (4, 8) and r["best"]["chunk"] in (512, 2048, 8192) and r["best"]["wg"] in (256, 512)
     after = sim.get_state(-1)
     for a, b in zip(before, after):
         assert np.abs(a - b).max() <= 1e-6 * max(1.0, np.abs(a).max())
     assert sim.get_option(mpm.OPT_BLOCK) == r["best"]["block"]
     assert sim.get_option(mpm.OPT_WG) == r["best"]["wg"]
+    assert sim.get_option(mpm.OPT_FUSE) == r["best"]["fuse"]
     rep2 = json.loads(sim.autotune(5))
     assert rep2["cached"] and rep2["best"] == r["best"]
     sim.step(10)
