@@ -243,7 +243,7 @@ mpm_status mpm_get_option(mpm_ctx ctx, int option, int *value);
 
 /* Time the candidate tunings on the live scenes for `substeps` substeps each
  * (at least one re-sort period, after one untimed period): every block edge (4, 8) x chunk size (512,
- * 2048, 8192) x sort cadence (10, 25, 50) x separate or fused launches
+ * 2048, 8192) x sort cadence (10, 25, 50, 100) x separate or fused launches
  * (MPM_OPT_FUSE) with 256-thread workgroups, then 512-thread workgroups and
  * the one-launch substep (MPM_OPT_PERSISTENT) at the fastest of those; keep
  * the fastest, and

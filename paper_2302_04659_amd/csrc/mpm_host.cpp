@@ -1595,7 +1595,7 @@ mpm_status mpm_autotune(mpm_ctx ctx, int substeps, char *report, size_t report_l
             st2 = MPM_OK;
             return per;
         };
-        const int Bs[2] = {4, 8}, CHs[3] = {512, 2048, 8192}, SEs[3] = {10, 25, 50};
+        const int Bs[2] = {4, 8}, CHs[3] = {512, 2048, 8192}, SEs[4] = {10, 25, 50, 100};
         for (int B : Bs)
             for (int CH : CHs)
                 for (int SE : SEs)

@@ -283,10 +283,14 @@ class RolloutData:
 
 
 def train(net: UNet, data: RolloutData, steps: int, batch: int = 8, lr: float = 3e-4, seed: int = 0,
-          log_every: int = 50, holdout: Optional[RolloutData] = None, lr_final: Optional[float] = None) -> List[Dict]:
+          log_every: int = 50, holdout: Optional[RolloutData] = None, lr_final: Optional[float] = None,
+          tail: float = 0.0) -> List[Dict]:
     """Adam on the masked MSE of the targets; returns a loss log.  With
     lr_final the step size falls from lr to lr_final on a cosine over the
-    run."""
+    run; with tail > 0 it stays at lr and then falls linearly to lr / 20 over
+    the last `tail` fraction of the steps (the weights at a constant step
+    size keep wandering around the minimum; the last step decides which of
+    them the network keeps)."""
     torch = _torch()
     sh = tuple(data.shape)
     rng = np.random.default_rng(seed)
@@ -301,6 +305,10 @@ def train(net: UNet, data: RolloutData, steps: int, batch: int = 8, lr: float = 
         lr_t = lr
         if lr_final is not None:
             lr_t = lr_final + 0.5 * (lr - lr_final) * (1.0 + np.cos(np.pi * (it - 1) / max(steps - 1, 1)))
+        elif tail > 0.0:
+            t0_tail = steps * (1.0 - tail)
+            if it > t0_tail:
+                lr_t = lr * (1.0 - 0.95 * (it - t0_tail) / max(steps - t0_tail, 1.0))
         loss = net.train_step(xb, tb.view(-1, COUT), mb.view(-1), lr=lr_t)
         if it % log_every == 0 or it == steps:
             rec = {"step": it, "loss": loss.value(), "s": time.perf_counter() - t0}
