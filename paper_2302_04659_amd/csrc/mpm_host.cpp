@@ -588,7 +588,7 @@ void release(mpm_ctx ctx)
                     ctx->d_col_scene, ctx->d_scene_bin_off, ctx->d_keys, ctx->d_count, ctx->d_pstart, ctx->d_perm,
                     ctx->d_tsum, ctx->d_dil, ctx->L.items, ctx->L.gitems, ctx->L.n_items, ctx->L.n_gitems,
                     ctx->L.scene_item_begin, ctx->L.scene_gitem_begin, ctx->L.bflag, ctx->L.ovf, ctx->L.n_ovf, ctx->L.ibound, ctx->L.icell, ctx->L.touched,
-                    ctx->d_flags, ctx->d_cap, ctx->d_cap_off, ctx->d_io,
+                    ctx->L.order, ctx->d_flags, ctx->d_cap, ctx->d_cap_off, ctx->d_io,
                     ctx->d_active, ctx->d_sur_gend, ctx->d_sur_acc, ctx->d_sur_out, ctx->d_sur_nfb,
                     ctx->d_wrench, ctx->d_wrench_out, ctx->d_sdf, ctx->d_sb_box, ctx->d_sb_origin, ctx->d_sb_feat,
                     ctx->d_sb_grid0, ctx->d_sb_pred, ctx->d_sb_res};
@@ -681,6 +681,7 @@ mpm_status create_impl(mpm_ctx ctx, const mpm_scene_desc *scenes, int n_scenes)
     HIPCHK(dalloc(&ctx->L.items, ctx->items_cap));
     HIPCHK(dalloc(&ctx->L.ibound, ctx->items_cap));
     HIPCHK(dalloc(&ctx->L.icell, ctx->items_cap));
+    HIPCHK(dalloc(&ctx->L.order, ctx->items_cap));
     HIPCHK(dalloc(&ctx->L.gitems, T4));
     HIPCHK(dalloc(&ctx->L.n_items, 1));
     HIPCHK(dalloc(&ctx->L.n_gitems, 1));

@@ -331,6 +331,41 @@ __global__ __launch_bounds__(WG) void k_gather(SortArgs a)
     for (int c = 0; c < NCOMP; c++) dst[(long long)c * a.pstride + p] = v[c];
 }
 
+// Dispatch order of the work items for P2G and G2P: most particles first.
+// Those kernels take one item per workgroup in workgroup order (the
+// dispatcher deals workgroups to the XCDs in turn, so each XCD gets every
+// eighth item of the order), and items range from a few dozen particles to
+// a full chunk: in block order the largest ones could start last and hold
+// the end of the launch.  A counting sort by particle count in 64 classes
+// (order inside a class: arbitrary).
+constexpr int ORDER_CLASSES = 64;
+
+__device__ __forceinline__ int order_class(int count, int CH)
+{
+    return min(ORDER_CLASSES - 1, (int)((long long)count * ORDER_CLASSES / (CH + 1)));
+}
+
+__global__ __launch_bounds__(1024) void k_item_order(SortArgs a)
+{
+    __shared__ int cnt[ORDER_CLASSES];
+    const int n = *a.L.n_items;
+    if (threadIdx.x < ORDER_CLASSES) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (int it = threadIdx.x; it < n; it += blockDim.x) atomicAdd(&cnt[order_class(a.L.items[it].count, a.CH)], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;   // classes from the largest down: cnt[c] becomes the first slot of class c
+        for (int c = ORDER_CLASSES - 1; c >= 0; c--) {
+            const int k = cnt[c];
+            cnt[c] = s;
+            s += k;
+        }
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < n; it += blockDim.x)
+        a.L.order[atomicAdd(&cnt[order_class(a.L.items[it].count, a.CH)], 1)] = it;
+}
+
 // Scale bound of every new work item (the P2G fixed-point scale), from the
 // freshly gathered particles.
 __global__ __launch_bounds__(WG) void k_item_bounds(SortArgs a)
@@ -368,6 +403,7 @@ hipError_t launch_sort(const SortArgs &a, hipStream_t st)
     k_scan_tiles<<<ntiles, WG, 0, st>>>(a);
     k_scan_top<<<1, WG, 0, st>>>(a, ntiles);
     k_scan_emit<<<ntiles, WG, 0, st>>>(a);
+    k_item_order<<<1, 1024, 0, st>>>(a);
     if (a.N > 0) {
         const int gN8 = (gN + 7) & ~7;    // xcd_remap (gather) needs a multiple of 8 workgroups
         k_scatter<<<gN, WG, 0, st>>>(a);
@@ -710,10 +746,9 @@ __global__ __launch_bounds__(NT, 5) void k_p2g(StepArgs a)
     const int n_items = *a.L.n_items;
     const int G = active_wgs(n_items);
     if ((int)blockIdx.x >= G) return;
-    // items in reverse order: G2P walks them forward, so the particles it wrote last
-    // are still in the memory-side cache when P2G starts on them
-    for (int r = xcd_remap(blockIdx.x, G); r < n_items; r += G) {
-        const int it = n_items - 1 - r;
+    // items in dispatch order, most particles first (L.order)
+    for (int r = blockIdx.x; r < n_items; r += G) {
+        const int it = a.L.order[r];
         Item item = a.L.items[it];
         if (!a.active[item.scene]) continue;
         p2g_item<B, NT>(a, it, item, tile, cells);
@@ -1194,7 +1229,8 @@ __global__ __launch_bounds__(NT, 4) void k_g2p(StepArgs a)
     const int n_items = *a.L.n_items;
     const int G = active_wgs(n_items);
     if ((int)blockIdx.x >= G) return;
-    for (int it = xcd_remap(blockIdx.x, G); it < n_items; it += G) {
+    for (int r = blockIdx.x; r < n_items; r += G) {   // most particles first (L.order)
+        const int it = a.L.order[r];
         Item item = a.L.items[it];
         if (!a.active[item.scene]) continue;
         g2p_item<B, true, PEN, NT>(a, it, item, vt, pf, cells);
@@ -1203,24 +1239,29 @@ __global__ __launch_bounds__(NT, 4) void k_g2p(StepArgs a)
 
 // G2P of substep a.substep fused with the P2G of substep a.substep + 1 (one
 // pass over the particles; the grid update sits between two such launches).
-// LDS: the velocity tile, the x / G prefetch, the fixed-point tile and the
-// base-cell counts (77 KB at block edge 8 with 512 threads: two workgroups per CU).
+// LDS: the velocity tile, the fixed-point tile and the base-cell counts (40 KB
+// at block edge 8: four workgroups of 256 threads per CU).  x and G go straight
+// into registers: the LDS prefetch slices of k_g2p would cost a workgroup per
+// CU (measured 2.5 % slower on the 256-scene workload, 1.6 % on the heap).
+// With penalty contact the kernel needs more registers than four workgroups
+// leave, and keeps the prefetch.
 template <int B, bool PEN, int NT>
 __global__ __launch_bounds__(NT, 4) void k_g2p2g(StepArgs a)
 {
     constexpr int T = tile_edge<B>(), T3 = T * T * T;
     __shared__ float vt[3 * T3];
-    __shared__ float pf[(NT / 64) * PF_COMPS * 64];
+    __shared__ float pf[PEN ? (NT / 64) * PF_COMPS * 64 : 1];
     __shared__ __align__(16) long long t64[2 * T3];
     __shared__ int cells[p2g_cells<B>() + 1];
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(ovf_count(a, a.substep), 0);   // consumed by the grid update
     const int n_items = *a.L.n_items;
     const int G = active_wgs(n_items);
     if ((int)blockIdx.x >= G) return;
-    for (int it = xcd_remap(blockIdx.x, G); it < n_items; it += G) {
+    for (int r = blockIdx.x; r < n_items; r += G) {   // most particles first (L.order)
+        const int it = a.L.order[r];
         Item item = a.L.items[it];
         if (!a.active[item.scene]) continue;
-        g2p_item<B, true, PEN, NT, true>(a, it, item, vt, pf, cells, t64);
+        g2p_item<B, PEN, PEN, NT, true>(a, it, item, vt, pf, cells, t64);
     }
 }
 

@@ -77,6 +77,7 @@ struct Lists {
     float *ibound;            // per item: max over its particles of m|v_c| + 1.5 dx sum_e |A_ce| (P2G scale)
     int *icell;               // per item: most particles sharing a base cell (P2G scale), 0 = not known
     unsigned char *touched;   // per block (all scenes, linear order): 1 = received mass in this substep's P2G
+    int *order;               // [n_items] item indices, most particles first: the dispatch order of P2G / G2P
 };
 
 }  // namespace mpm
