@@ -945,10 +945,10 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
         for (int n = t; n < 2 * T3; n += NT) t64[n] = 0;
     }
     for (int n = t; n < NC + 1; n += NT) cells[n] = 0;
-    if (PF) {
+    {
         const int res = Sn.res;
         // the wave's first 64 particles: x and G copied into LDS while the tile is staged
-        pf_issue(a.P, ps, item.start + (t - lane), item.count - (t - lane), lane, pw);
+        if (PF) pf_issue(a.P, ps, item.start + (t - lane), item.count - (t - lane), lane, pw);
         // tile nodes copied straight into LDS, all in flight at once; nodes outside the grid are zeroed
         for (int n0 = t - lane; n0 < T3; n0 += NT) {
             const int n = n0 + lane;
@@ -966,20 +966,6 @@ __device__ void g2p_item(const StepArgs &a, int it, const Item &item, float *vt,
             }
         }
         wait_vmem();
-    } else {
-        for (int n = t; n < T3; n += NT) {
-            int gi = org[0] + n / (T * T), gj = org[1] + (n / T) % T, gk = org[2] + n % T;
-            float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
-            if (gi >= 0 && gj >= 0 && gk >= 0 && gi < S.res && gj < S.res && gk < S.res) {
-                long long idx = node_index(S, B, gi, gj, gk);
-                v0 = a.gvx[idx];
-                v1 = a.gvy[idx];
-                v2 = a.gvz[idx];
-            }
-            vt[n] = v0;
-            vt[T3 + n] = v1;
-            vt[2 * T3 + n] = v2;
-        }
     }
     __syncthreads();
     if (FUSE && t == 0) a.L.ibound[it] = 0.0f;   // read by every thread above; the advanced state's bound follows
