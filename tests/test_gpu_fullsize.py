@@ -3,19 +3,22 @@ benchmark times (block, chunk and re-sort cadence the autotuner picks on
 the MI355X), against the FP64 oracle on what the oracle can afford:
 
   * cfg3, all 256 scenes (7.7 M particles) stepped together with block 8,
-    chunk 8192, re-sort every 50 substeps:
+    chunk 8192, re-sort every 100 substeps, G2P fused with the next P2G:
       - positions after 100 substeps (four 25-substep control steps, each
         replayed from a captured hipGraph as the benchmark runs them) of
         sampled scenes (the first, the last, the largest, the smallest)
         against the oracle run on each alone (the scenes are independent),
         1e-3 dx; every scene's state stays finite and inside its grid;
       - the per-substep grid-momentum bar (1e-5) on 16 sampled scenes at
-        substep 1 (a handed-in state with seeded C, F) and at substep 25
-        (the state the GPU reached, read back for the oracle);
+        substep 1 (a handed-in state with seeded C, F), at substep 25
+        (the state the GPU reached, read back for the oracle), and for the
+        P2G inside the fused launch (substep 2 of a two-substep call,
+        against the oracle's P2G of the state separate launches reach after
+        one substep from the same start);
   * cfg4, the 1,048,576-particle heap on a 128^3 grid with 3 colliders,
-    block 4, chunk 8192, re-sort every 10: every particle after 100
-    substeps (graph replay, ten sorts in the run) against the oracle,
-    1e-3 dx; grid momentum at substeps 1 and 25.
+    block 4, chunk 8192, re-sort every 10, fused launches: every particle
+    after 100 substeps (graph replay, ten sorts in the run) against the
+    oracle, 1e-3 dx; grid momentum at substeps 1, 2 (fused) and 25.
 """
 import numpy as np
 import pytest
@@ -25,8 +28,8 @@ from paper_2302_04659_amd import scenes
 
 pytestmark = pytest.mark.gpu
 
-CFG3_LAUNCH = dict(block=8, chunk=8192, sort_every=50)
-CFG4_LAUNCH = dict(block=4, chunk=8192, sort_every=10)
+CFG3_LAUNCH = dict(block=8, chunk=8192, sort_every=100, fuse=1)
+CFG4_LAUNCH = dict(block=4, chunk=8192, sort_every=10, fuse=1)
 
 
 @pytest.fixture(scope="module")
@@ -38,11 +41,12 @@ def mpm():
     return m
 
 
-def _sim(mpm, batch, launch, graph=1, capture=0):
+def _sim(mpm, batch, launch, graph=1, capture=0, fuse=None):
     sim = mpm.Sim(batch)
     sim.set_option(mpm.OPT_BLOCK, launch["block"])
     sim.set_option(mpm.OPT_CHUNK, launch["chunk"])
     sim.set_option(mpm.OPT_SORT_EVERY, launch["sort_every"])
+    sim.set_option(mpm.OPT_FUSE, launch["fuse"] if fuse is None else fuse)
     sim.set_option(mpm.OPT_GRAPH, graph)
     sim.set_option(mpm.OPT_CAPTURE_GRID, capture)
     return sim
@@ -62,7 +66,6 @@ def _grid_momentum(sim, orc, batch, sample, states, what):
 
 
 def _c18_at_1_and_25(mpm, orc, batch, sample, launch):
-    sim = _sim(mpm, batch, launch, graph=0, capture=1)
     states = {}
     xs, vs, Cs, Fs = [], [], [], []
     for s, sc in enumerate(batch):
@@ -70,7 +73,29 @@ def _c18_at_1_and_25(mpm, orc, batch, sample, launch):
         xs.append(sc.x), vs.append(sc.v), Cs.append(C), Fs.append(F)
         if s in sample:
             states[s] = (sc.x, sc.v, C, F)
-    sim.set_state(np.concatenate(xs), np.concatenate(vs), np.concatenate(Cs), np.concatenate(Fs))
+    start = [np.concatenate(a) for a in (xs, vs, Cs, Fs)]
+    # the P2G inside the fused launch: substep 2 of a two-substep call, against the oracle's P2G
+    # of the state separate launches reach after one substep
+    ref = _sim(mpm, batch, launch, graph=0, fuse=0)
+    ref.set_state(*start)
+    ref.set_colliders_ctrl(0)
+    ref.step(1)
+    assert ref.sync() == mpm.OK
+    after_one = {s: ref.get_state(s) for s in sample}
+    ref.close()
+    fused = _sim(mpm, batch, launch, graph=0, capture=1, fuse=1)
+    fused.set_option(mpm.OPT_TIMING, 1)
+    fused.set_state(*start)
+    fused.set_colliders_ctrl(0)
+    fused.timing(reset=True)
+    fused.step(2)
+    assert fused.sync() == mpm.OK
+    assert fused.timing(reset=True)["g2p2g"][1] == 1
+    _grid_momentum(fused, orc, batch, sample, after_one, "substep 2 (fused P2G)")
+    fused.close()
+
+    sim = _sim(mpm, batch, launch, graph=0, capture=1)
+    sim.set_state(*start)
     sim.set_colliders_ctrl(0)
     sim.step(1)
     assert sim.sync() == mpm.OK
