@@ -148,7 +148,7 @@ def main():
                     help="1: replay each 25-substep control step from a captured hipGraph (the default "
                          "production path), 0: launch every kernel from the host")
     ap.add_argument("--persistent", type=int, default=-1)
-    ap.add_argument("--fuse", type=int, default=-1, help="1: G2P and the next P2G in one launch (library default 0)")
+    ap.add_argument("--fuse", type=int, default=-1, help="1: G2P and the next P2G in one launch (library default 1)")
     ap.add_argument("--wg", type=int, default=0, help="threads per workgroup of the particle kernels (256, 512)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-scenes", type=int, default=64)

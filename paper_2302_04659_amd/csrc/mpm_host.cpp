@@ -119,7 +119,7 @@ struct mpm_ctx_s {
     long long cap_nodes = 0;
 
     int persistent = 0, graph = 0;
-    int fuse = 0;                    // MPM_OPT_FUSE: G2P and the next P2G in one launch
+    int fuse = 1;                    // MPM_OPT_FUSE: G2P and the next P2G in one launch
     int contact = 0;                 // MPM_OPT_CONTACT
     std::map<GraphKey, GraphEntry> graphs;
 

@@ -279,6 +279,7 @@ def test_one_launch_substep_matches_three_launches(mpm, orc, contact):
     for persistent in (0, 1):
         sim = mpm.Sim(batch)
         sim.set_option(mpm.OPT_CONTACT, contact)
+        sim.set_option(mpm.OPT_FUSE, 0)   # the three launches of a substep on the other side
         sim.set_option(mpm.OPT_PERSISTENT, persistent)
         sim.set_option(mpm.OPT_TIMING, 1)
         sim.timing(reset=True)
