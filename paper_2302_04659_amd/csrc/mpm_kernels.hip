@@ -1345,7 +1345,8 @@ __global__ __launch_bounds__(WG, 4) void k_substep_coop(StepArgs a)
     cooperative_groups::grid_group grid = cooperative_groups::this_grid();
     const int G = gridDim.x;   // a multiple of 8: every workgroup takes part in every phase
     const int n_items = *a.L.n_items;
-    // P2G, items in reverse order (as k_p2g)
+    // P2G, items in reverse order: the G2P of the previous substep walked them forward, so the
+    // particles it wrote last are still in the memory-side cache
     for (int r = xcd_remap(blockIdx.x, G); r < n_items; r += G) {
         const int it = n_items - 1 - r;
         const Item item = a.L.items[it];
